@@ -1,0 +1,198 @@
+"""Benchmark of the P-GVIMP hot path on one MI355X.
+
+Workload (default): 32 seeded point-robot plans, N = 750 support states
+each, 500 x 500 FP32 SDF maps of 40 discs/boxes, Gauss-Hermite p = 5 on
+(x, y), 20 proximal iterations.  One step = one full solve of the batch:
+prior build, initial marginals and 20 iterations (expectations, step-size
+selection, update, marginals) for all 32 plans, captured in one HIP graph.
+The primary mode is mixed precision (FP32 quadrature, FP64 elsewhere); the
+plain FP64 path is timed beside it.
+
+Prints ONE JSON line.  `value` = factor expectations per second over the
+whole path (32 x 750 factors x 20 iterations per step / step time).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "factor-expectations/s + plans/s with p50/p99 latency, mixed vs plain FP64 GPU"
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--plans", type=int, default=32)
+    ap.add_argument("--N", type=int, default=750)
+    ap.add_argument("--iters", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
+    ap.add_argument("--segments", type=int, default=0)
+    ap.add_argument("--lanes", type=int, default=0)
+    return ap.parse_args()
+
+
+def make_batch(n_plans, N, iters):
+    import workloads
+    probs = []
+    for k in range(n_plans):
+        p = workloads.config1_problem(seed=k, N=N)
+        p["n_iters"] = iters
+        probs.append(p)
+    return probs
+
+
+def timed_solve(pg, probs, precision, steps, warmup, iters, segments=0, lanes=0, profile=True):
+    """Create one context for the batch, warm up, then time `steps` solves,
+    each one HIP graph replay.  With profile, the same number of solves is
+    then run with HIP events around every kernel on the context's stream
+    (launched directly, since events inside a graph cannot be timed) to get
+    each kernel's mean duration."""
+    import torch
+    ctx = pg.pgvimp_create(probs, precision=precision, use_graph=True, segments=segments, lanes=lanes)
+    for _ in range(warmup):
+        pg.pgvimp_solve(ctx, iters)
+    torch.cuda.synchronize()
+    step_ms, trials = [], 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s0 = time.perf_counter()
+        st = pg.pgvimp_solve(ctx, iters)
+        step_ms.append(1e3 * (time.perf_counter() - s0))
+        trials += sum(v["trials_total"] for v in st.values())
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kt = None
+    if profile:
+        pg.pgvimp_profile(ctx, True)
+        pg.pgvimp_kernel_times(ctx, reset=True)
+        t1 = time.perf_counter()
+        for _ in range(steps):
+            pg.pgvimp_solve(ctx, iters)
+        kt = pg.pgvimp_kernel_times(ctx, reset=True)
+        kt["eager_ms_per_step"] = 1e3 * (time.perf_counter() - t1) / steps
+        pg.pgvimp_profile(ctx, False)
+    status = [v["status"] for v in st.values()]
+    seg, lanes_used = pg.pgvimp_launch_shape(ctx, probs[0]["N"])
+    pg.pgvimp_destroy(ctx)
+    return {"wall_s": wall, "step_ms": step_ms, "trials": trials, "kt": kt, "status": status,
+            "segments": seg, "lanes": lanes_used}
+
+
+def pct(xs, q):
+    xs = sorted(xs)
+    k = min(len(xs) - 1, max(0, int(math.ceil(q / 100.0 * len(xs))) - 1))
+    return xs[k]
+
+
+_CPU_SAMPLE = """
+import sys, time
+sys.path.insert(0, {root!r})
+import workloads
+from oracle import prior, prox
+p = workloads.config1_problem(seed=0, N={N})
+t0 = time.perf_counter()
+pri = prior.build_prior(p)
+st = prox.init_state(p, pri)
+for _ in range({iters}):
+    st, _, _ = prox.prox_iteration(p, pri, st)
+print(time.perf_counter() - t0)
+"""
+
+
+def cpu_baseline(N, iters_sample=20):
+    """The oracle as it stands, on one plan of the same workload, timed on
+    the host in a child process pinned to one BLAS/OpenMP thread (it never
+    touches the GPU): factor expectations per second of the whole solve."""
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    code = _CPU_SAMPLE.format(root=ROOT, N=N, iters=iters_sample)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=600)
+    if r.returncode != 0:
+        return {"value": None, "error": r.stderr[-500:]}
+    dt = float(r.stdout.strip().splitlines()[-1])
+    return {"value": N * iters_sample / dt, "unit": "factor-expectations/s", "cores": 1, "kind": "oracle",
+            "sample": f"1 of the {N}-state plans: prior build + {iters_sample} iterations in {dt:.1f} s "
+                      f"(numpy/scipy FP64, 1 thread)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
+              "(plans are independent and would shard by request, see the design notes)", file=sys.stderr)
+        sys.exit(2)
+    import paper_2411_03416_amd as pg
+
+    probs = make_batch(args.plans, args.N, args.iters)
+    B, N, K = args.plans, args.N, args.iters
+    n = probs[0]["n"]
+    mixed = timed_solve(pg, probs, pg.MIXED, args.steps, args.warmup, K, args.segments, args.lanes)
+    ms = 1e3 * mixed["wall_s"] / args.steps
+    factors_per_step = B * N * K
+    value = factors_per_step / (ms / 1e3)
+    out = {
+        "metric": METRIC, "value": value, "unit": "factor-expectations/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "fp32 quadrature + fp64", "data": "synthetic",
+        "config": {"workload": f"point robot, {B} seeded maps 500x500 (40 discs/boxes), N={N}, GH p=5, "
+                               f"{K} prox iterations per solve, one HIP graph per solve",
+                   "plans": B, "N": N, "iters": K, "n": n, "segments": mixed["segments"],
+                   "lanes_per_factor": mixed["lanes"]},
+        "plans_per_s": B / (ms / 1e3),
+        "latency_ms": {"p50": pct(mixed["step_ms"], 50), "p99": pct(mixed["step_ms"], 99)},
+        "status_ok": all(s == 0 for s in mixed["status"]),
+    }
+    kt = mixed["kt"]
+    if kt and kt["expect_launches"] and kt["chain_launches"]:
+        # expectation kernel: 88 B per factor of HBM traffic that the method
+        # must move (marginal mean 2 + covariance 3 doubles in; E, g (2),
+        # H (3) doubles out)
+        exp_bytes = 88.0 * B * N
+        exp_gbs = exp_bytes / (kt["expect_ms"] * 1e-3) / 1e9
+        # chain kernel: FP64 flops of the plain block-tridiagonal algorithm per
+        # state and step-size trial (~10 n^3 for the marginals, ~5 n^3 for the
+        # mean solve) over the trials of the timed steps
+        chain_flops = 15.0 * n ** 3 * N * (mixed["trials"] / args.steps) / K
+        chain_tf = chain_flops / (kt["chain_ms"] * 1e-3) / 1e12
+        t_exp = kt["expect_ms"] * kt["expect_launches"]
+        t_chain = kt["chain_ms"] * kt["chain_launches"]
+        rexp = {"kernel": "expect_kernel<float,2,5,32,point2d>", "bound": "hbm", "achieved": exp_gbs,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": exp_gbs / HBM_PEAK_GBS, "traffic": None,
+                "avg_ms": kt["expect_ms"], "bytes_per_launch": exp_bytes}
+        rchain = {"kernel": "chain_kernel<4>", "bound": "alu", "achieved": chain_tf, "peak": FP64_PEAK_TFLOPS,
+                  "unit": "TFLOP/s", "frac": chain_tf / FP64_PEAK_TFLOPS, "traffic": None,
+                  "avg_ms": kt["chain_ms"], "flops_per_launch": chain_flops}
+        dominant_is_chain = t_chain >= t_exp
+        out["roofline"] = rchain if dominant_is_chain else rexp
+        out["roofline_other"] = rexp if dominant_is_chain else rchain
+        out["kernel_share"] = {"expect": t_exp / (t_exp + t_chain), "chain": t_chain / (t_exp + t_chain)}
+    if not args.no_fp64:
+        f64 = timed_solve(pg, probs, pg.FP64, max(2, args.steps // 2), 1, K, args.segments, args.lanes,
+                          profile=False)
+        ms64 = 1e3 * f64["wall_s"] / max(2, args.steps // 2)
+        out["fp64"] = {"value": factors_per_step / (ms64 / 1e3), "ms_per_step": ms64,
+                       "plans_per_s": B / (ms64 / 1e3),
+                       "latency_ms": {"p50": pct(f64["step_ms"], 50), "p99": pct(f64["step_ms"], 99)}}
+        # serial FP64: the same plans solved one at a time
+        ser = timed_solve(pg, probs[:1], pg.FP64, 3, 1, K, args.segments, args.lanes, profile=False)
+        ser_ms = 1e3 * ser["wall_s"] / 3
+        out["serial_fp64"] = {"plans_per_s": 1.0 / (ser_ms / 1e3), "ms_per_plan": ser_ms}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(N)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

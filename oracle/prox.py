@@ -14,7 +14,9 @@ touches its own state's diagonal block).
 
 Step size (Alg. 1, App. C): start at beta_max and halve until Lambda' is
 positive definite and KL(q' || q_k) <= kl_bound, at most max_bisect trials;
-if no trial passes the state is left unchanged.
+if no trial passes the state is left unchanged.  The paper prints neither
+the bound nor the bisection constants; halving from beta_max is the reading
+used.  The KL is evaluated in the rearranged form of kl_step.
 
 Initial state (not stated in the paper): mu_0 = mu_bar, Lambda_0 = K^-1.
 """
@@ -57,6 +59,27 @@ def kl_banded(mu1, Sig1, Soff1, logdet1, mu0, D0, U0, logdet0):
     d = mu1 - mu0
     quad = np.sum(d * prior_mod.block_matvec(D0, U0, d))
     return 0.5 * (tr + quad - N * n + logdet1 - logdet0)
+
+
+def kl_step(prob, pri, st, H, beta, mu1, Sig1, Soff1, logdet1):
+    """KL(q_{k+1} || q_k) for the step of size beta, evaluated stably.
+
+    Same quantity as kl_banded.  Because Lambda_k = (beta T + 1) Lambda' -
+    beta (K^-1 + H) exactly and tr(Lambda' Sigma') = dim, the trace term is
+    tr(Lambda_k Sigma') - dim = beta (T dim - tr((K^-1 + H) Sigma')); this
+    avoids subtracting dim from a sum of terms many orders of magnitude
+    larger (the precision of a long, loosely pinned trajectory has a
+    condition number near 1e10, which leaves the textbook form with an
+    absolute error of several nats).
+    """
+    N, n = mu1.shape
+    T = prob["temperature"]
+    trKH = np.einsum("iab,iba->", pri["D"] + H, Sig1)
+    if N > 1:
+        trKH += 2.0 * np.einsum("iab,iab->", pri["U"], Soff1)
+    d = mu1 - st["mu"]
+    quad = np.sum(d * prior_mod.block_matvec(st["D"], st["U"], d))
+    return 0.5 * (beta * (T * N * n - trKH) + quad + logdet1 - st["logdet"])
 
 
 def kl_dense(mu1, S1, mu0, S0):
@@ -108,7 +131,7 @@ def prox_iteration(prob, pri, st):
             beta *= 0.5
             continue
         mu = prior_mod.banded_solve(MD, MU, rhs)
-        kl = kl_banded(mu, Sig, Soff, logdet, st["mu"], st["D"], st["U"], st["logdet"])
+        kl = kl_step(prob, pri, st, H, beta, mu, Sig, Soff, logdet)
         if not (kl <= bound):
             beta *= 0.5
             continue

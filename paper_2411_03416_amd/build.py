@@ -1,0 +1,85 @@
+"""Build the in-tree HIP library libpgvimp.so for gfx950.
+
+Each .hip translation unit under csrc/ is compiled with hipcc for gfx950
+and linked into paper_2411_03416_amd/libpgvimp.so.  Packed FP32 vector
+instructions are disabled for all device code.
+"""
+from __future__ import annotations
+
+import concurrent.futures
+import os
+import shutil
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+BUILD = os.path.join(ROOT, "_build")
+LIB = os.path.join(PKG, "libpgvimp.so")
+ARCH = os.environ.get("PGVIMP_ARCH", "gfx950")
+
+SOURCES = ["chain_n14.hip", "chain_n8.hip", "chain_n6.hip", "expect.hip", "chain_n4.hip", "chain_n2.hip",
+           "chain.hip", "api.hip", "prior.hip"]
+FLAGS = [
+    f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-I", INCLUDE, "-I", CSRC,
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-ffp-contract=fast", "-Wno-unused-result", "-Wno-cuda-compat", "-Wno-zero-length-array",
+]
+# extra flags for a resource report (set PGVIMP_RESOURCE_REPORT=1)
+if os.environ.get("PGVIMP_RESOURCE_REPORT"):
+    FLAGS += ["-Rpass-analysis=kernel-resource-usage"]
+
+
+def hipcc() -> str:
+    cand = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(cand):
+        raise RuntimeError("hipcc not found")
+    return cand
+
+
+def _stale(src: str, obj: str) -> bool:
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    deps = [os.path.join(CSRC, src)] + [os.path.join(CSRC, h) for h in os.listdir(CSRC) if h.endswith(".h")]
+    deps.append(os.path.join(INCLUDE, "pgvimp.h"))
+    return any(os.path.getmtime(d) > t for d in deps)
+
+
+def _compile(src: str, incremental: bool = False) -> str:
+    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+    if incremental and not _stale(src, obj):
+        return obj
+    cmd = [hipcc(), *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"compile of {src} failed:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    if os.environ.get("PGVIMP_RESOURCE_REPORT"):
+        with open(obj + ".resources.txt", "w") as f:
+            f.write(r.stderr)
+    return obj
+
+
+def build(verbose: bool = True, incremental: bool = False) -> str:
+    """Compile every translation unit (only changed ones if incremental) and
+    link the shared library."""
+    os.makedirs(BUILD, exist_ok=True)
+    jobs = min(len(SOURCES), max(1, int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
+    with concurrent.futures.ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(lambda s: _compile(s, incremental), SOURCES))
+    tmp = LIB + ".tmp"
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, LIB)
+    if verbose:
+        print(f"built {LIB}")
+    return LIB
+
+
+if __name__ == "__main__":
+    build(incremental="--incremental" in sys.argv)
+    sys.exit(0)

@@ -1,0 +1,168 @@
+// Device-resident plan table and the context that owns it.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "pgvimp.h"
+
+namespace pg {
+
+constexpr int kMaxSeg = 64;      // chain segments per plan (upper bound)
+constexpr int kChainThreads = 64; // one wavefront per plan in the chain kernel
+constexpr int kMaxGH = 10;        // Gauss-Hermite points per dimension
+// n x n temporaries a chain-kernel thread may hold at once.  Deepest call
+// paths: kernel loop body 1 + prior cost 8 = 9; segment elimination 7 +
+// Cholesky inverse 2 = 9; segment backward sweep 3 + 6 = 9.
+constexpr int kTwsBlocks = 12;
+constexpr int kTwsVecs = 16;  // n-vector temporaries (deepest path: 8)
+
+// Per-plan parameters and statistics, read by every kernel.  One entry per
+// plan slot; an empty slot has active = 0.
+struct PlanDev {
+    int32_t active, N, off, nseg;
+    int32_t iters_left, iters_done, max_bisect, coll_kind;
+    int32_t d, gh_points, gx, gy;
+    int32_t gz, n_spheres, coll_states, status;
+    int32_t trials, m, n_iters, trials_total;
+    int32_t coll_index[PGVIMP_MAX_COLL_DIM];
+    double temperature, beta_max, kl_bound, cell, dt;
+    double inv_cell, hinge_eps, obs_weight, logdet;
+    double origin[3];
+    double beta, kl, E_coll, E_prior, entropy;
+    const float* sdf;
+    // model block (FP64) laid out by the host, see Layout in api.cpp
+    double* Wstart;  // Sig_start^-1 [n*n]   (written by the prior kernel)
+    double* Wgoal;   // Sig_goal^-1 [n*n]
+    const double* mu_start;
+    const double* mu_goal;
+    const double* Sig_start;
+    const double* Sig_goal;
+    const double* Qc;    // [m*m]
+    double* A;     // [N-1][n*n]  (rewritten by statistical linearisation)
+    double* a;     // [N-1][n]
+    const double* B;     // [N-1][n*m]
+    const double* radius;  // [n_spheres]
+    const double* fk;      // base[3], len[7], frac[S], axes[7], link[S] (as doubles)
+};
+
+// Device arrays shared by the kernels.  Per-state arrays are SoA:
+// X[e * S + s] for entry e of state s, S = capacity in states.
+struct DevState {
+    int64_t S;       // state capacity
+    int32_t n, P;    // state dim, plan capacity
+    PlanDev* plans;  // [P]
+    int32_t* state_plan;  // [S] plan of each state or -1
+    // prior
+    double *KD, *KU, *eta;      // K^-1 blocks and K^-1 mu_bar
+    double *Phi, *Qinv, *abar;  // per interval (index = state of its start)
+    // current iterate
+    double *LD, *LU, *mu;  // precision blocks and mean
+    double *SD, *SU;       // marginal covariances
+    // trial iterate
+    double *TD, *TU, *Tmu, *TSD, *TSU;
+    // collision expectations (d-dim, not embedded): E [S], g [d][S], H [d*d][S]
+    double *Ecol, *gcol, *Hcol;
+    // mean-solve right-hand side parts: rb = eta - g, Lmu = Lambda_k mu_k
+    double *rb, *Lmu;
+    // prior factor costs [S] (transition starting at state s) and end costs
+    double* Epri;
+    // chain workspace: per state AoS (stride ws_stride), per segment AoS
+    double* ws;
+    double* seg;
+    int32_t ws_stride, seg_stride;
+    // per-thread block temporaries of the chain kernels: [P][kChainThreads]
+    // slices of tws_stride doubles (kTwsBlocks n x n blocks and kTwsVecs
+    // n-vectors each)
+    double* tws;
+    int64_t tws_stride;
+    // Gauss-Hermite 1-D tables [kMaxGH+1][kMaxGH] (row p), FP64 and FP32
+    const double* gh_x64;
+    const double* gh_w64;
+    const float* gh_x32;
+    const float* gh_w32;
+};
+
+// First-fit allocator over [0, capacity) with coalescing free list.
+class RangeAlloc {
+  public:
+    explicit RangeAlloc(int64_t cap = 0) { reset(cap); }
+    void reset(int64_t cap) {
+        free_.clear();
+        if (cap > 0) free_[0] = cap;
+        cap_ = cap;
+    }
+    int64_t alloc(int64_t len, int64_t align = 1) {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            int64_t start = (it->first + align - 1) / align * align;
+            int64_t end = it->first + it->second;
+            if (start + len <= end) {
+                int64_t b = it->first;
+                free_.erase(it);
+                if (start > b) free_[b] = start - b;
+                if (start + len < end) free_[start + len] = end - (start + len);
+                used_[start] = len;
+                return start;
+            }
+        }
+        return -1;
+    }
+    void release(int64_t start) {
+        auto u = used_.find(start);
+        if (u == used_.end()) return;
+        int64_t len = u->second;
+        used_.erase(u);
+        auto it = free_.emplace(start, len).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    int64_t high_water() const {
+        int64_t hw = 0;
+        for (auto& u : used_) hw = std::max(hw, u.first + u.second);
+        return hw;
+    }
+
+  private:
+    std::map<int64_t, int64_t> free_, used_;
+    int64_t cap_ = 0;
+};
+
+}  // namespace pg
+
+// Kernel launchers (defined in the .hip translation units).
+namespace pg {
+// prior build for plans [plan_lo, plan_hi) of up to maxN states each
+hipError_t launch_prior_build(const DevState& st, int plan_lo, int plan_hi, int maxN, hipStream_t s);
+hipError_t launch_prior_assemble(const DevState& st, int plan_lo, int plan_hi, int maxN, hipStream_t s);
+hipError_t launch_chain(const DevState& st, int mode, int plan_lo, int plan_hi, hipStream_t s);
+hipError_t launch_expect(const DevState& st, int coll_kind, int d, int p, int precision, int lanes,
+                         int64_t s_lo, int64_t s_hi, int respect_budget, hipStream_t s);
+hipError_t launch_prior_costs(const DevState& st, int plan, int N, hipStream_t s);
+hipError_t launch_gather(const DevState& st, int what, int plan, int N, double* out, hipStream_t s);
+hipError_t launch_scatter(const DevState& st, int what, int plan, int N, const double* in, hipStream_t s);
+hipError_t launch_slr_model(const DevState& st, int plan, int N, double gravity, int p, double* A_out,
+                            double* a_out, int write_model, hipStream_t s);
+bool chain_supported(int n);
+bool expect_supported(int coll_kind, int d, int p, int lanes);
+int default_lanes(int coll_kind, int d, int p);
+
+// modes of the chain kernel
+enum ChainMode { CHAIN_INIT = 0, CHAIN_MARGINALS = 1, CHAIN_PROX = 2, CHAIN_REINIT = 3 };
+// what to gather/scatter between SoA device arrays and [N][..] host layouts
+enum GatherWhat {
+    G_SD = 0, G_SU = 1, G_MU = 2, G_LD = 3, G_LU = 4, G_ECOL = 5, G_GEMB = 6, G_HEMB = 7, G_EPRI = 8
+};
+}  // namespace pg

@@ -304,6 +304,27 @@ def test_kl_banded_matches_dense_and_is_zero_on_self():
     assert abs(prox.kl_banded(mu0, S0, So0, ld0, mu0, D0, U0, ld0)) < 1e-10
 
 
+def test_kl_step_equals_textbook_kl():
+    p = workloads.config0_problem(3)
+    p["N"] = 12
+    pri = prior.build_prior(p)
+    st = prox.init_state(p, pri)
+    rng = np.random.default_rng(1)
+    H = np.zeros((12, 4, 4))
+    for i in range(12):
+        Hi = _rand_spd(rng, 2, 50.0)
+        H[i, :2, :2] = Hi
+    g = rng.normal(size=(12, 4)) * 10
+    for beta in (1.0, 0.25, 1e-3):
+        Dn, Un, MD, MU, rhs = prox.trial(p, pri, st, g, H, beta)
+        Sig, Soff, ld = gbp.gbp_marginals(Dn, Un)
+        mu = prior.banded_solve(MD, MU, rhs)
+        k1 = prox.kl_step(p, pri, st, H, beta, mu, Sig, Soff, ld)
+        ref = prox.kl_dense(mu.reshape(-1), np.linalg.inv(prior.dense_from_blocks(Dn, Un)),
+                            st["mu"].reshape(-1), np.linalg.inv(prior.dense_from_blocks(st["D"], st["U"])))
+        assert abs(k1 - ref) < 1e-7 * max(1.0, abs(ref)), (beta, k1, ref)
+
+
 def test_prior_costs_match_quadrature_over_pairwise_marginals():
     p = workloads.config0_problem(1)
     p["N"] = 6

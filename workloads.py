@@ -302,9 +302,11 @@ def config2_problem(seed=0):
 def quadrotor_problem(seed, N=None, gh_points=3, slr_points=3, n_rounds=10,
                       n_iters=15, qc=0.8, hinge_eps=0.5, sigma_obs=0.01):
     """Nonlinear planar quadrotor (x, z, phi, vx, vz, phidot) over a 10x10 m
-    map of 6 seeded discs.  N ~ U{100..300} unless given.  The LTV fields
-    (A, a) are placeholders until the first statistical linearisation; the
-    nominal trajectory is the straight line with covariance 1e-2 I."""
+    map of 6 seeded discs.  N ~ U{100..300} unless given.  The LTI fields
+    (A, a) hold the model's hover linearisation (phi = 0, zero velocity:
+    xdot = vx, zdot = vz, vxdot = -g phi, vzdot = -g) until the first
+    statistical linearisation replaces them; the nominal trajectory is the
+    straight line with covariance 1e-2 I."""
     rng = _rng(seed)
     if N is None:
         N = int(rng.integers(100, 301))
@@ -324,7 +326,11 @@ def quadrotor_problem(seed, N=None, gh_points=3, slr_points=3, n_rounds=10,
     B = quadrotor_B(params)
     mu_s = np.array([s[0], s[1], 0.0, 0.0, 0.0, 0.0])
     mu_g = np.array([g[0], g[1], 0.0, 0.0, 0.0, 0.0])
-    p = _base(6, 2, N, 0.1, np.zeros((6, 6)), np.zeros(6), B, qc * np.eye(2), mu_s, mu_g)
+    A_hover = np.zeros((6, 6))
+    A_hover[0, 3] = A_hover[1, 4] = A_hover[2, 5] = 1.0
+    A_hover[3, 2] = -params["gravity"]
+    a_hover = np.array([0.0, 0.0, 0.0, 0.0, -params["gravity"], 0.0])
+    p = _base(6, 2, N, 0.1, A_hover, a_hover, B, qc * np.eye(2), mu_s, mu_g)
     ts = np.linspace(0.0, 1.0, N)[:, None]
     nominal = (1.0 - ts) * mu_s[None, :] + ts * mu_g[None, :]
     p.update({
