@@ -140,6 +140,9 @@ typedef struct pgvimp_problem {
  * the context); otherwise it allocates its own.  segments and
  * lanes_per_factor override the tuned launch shapes (0 = tuned default);
  * use_graph = 1 captures pgvimp_prox_step's iterations in a HIP graph.
+ * trial_width (0 = 16, at most 64) is the number of step sizes of the
+ * halving sequence evaluated concurrently per plan and iteration; it changes
+ * speed and memory (the trial scratch scales with it), never results.
  */
 typedef struct pgvimp_engine_cfg {
     int32_t device, n, precision, max_plans;
@@ -148,6 +151,7 @@ typedef struct pgvimp_engine_cfg {
     void *dev_arena;
     uint64_t arena_bytes;
     int32_t io_on_device, segments, lanes_per_factor, use_graph;
+    int32_t trial_width, reserved;
 } pgvimp_engine_cfg;
 
 /* Per-plan statistics of the last iteration run by pgvimp_prox_step. */

@@ -129,9 +129,10 @@ class Context:
             pass
 
 
-def pgvimp_arena_bytes(n, max_plans, max_states, heap_bytes):
+def pgvimp_arena_bytes(n, max_plans, max_states, heap_bytes, trial_width=0):
     cfg = _abi.EngineCfg()
     cfg.n, cfg.max_plans, cfg.max_states, cfg.heap_bytes = n, max_plans, max_states, heap_bytes
+    cfg.trial_width = trial_width
     return int(_abi.load().pgvimp_arena_bytes(C.byref(cfg)))
 
 
@@ -145,7 +146,8 @@ def _heap_need(probs):
 
 
 def pgvimp_create(problems, n=None, precision=FP64, max_plans=None, max_states=None, heap_bytes=None,
-                  device=0, use_torch=True, stream=None, segments=0, lanes=0, use_graph=True, mu_init=None):
+                  device=0, use_torch=True, stream=None, segments=0, lanes=0, use_graph=True, mu_init=None,
+                  trial_width=0):
     """Create a context holding `problems` (list of dicts); see pgvimp_create
     in include/pgvimp.h.  With use_torch the device arena is a torch uint8
     tensor and the work runs on a torch stream."""
@@ -160,6 +162,7 @@ def pgvimp_create(problems, n=None, precision=FP64, max_plans=None, max_states=N
     cfg.device, cfg.n, cfg.precision, cfg.max_plans = device, n, precision, max_plans
     cfg.max_states, cfg.heap_bytes = max_states, heap_bytes
     cfg.segments, cfg.lanes_per_factor, cfg.use_graph = segments, lanes, 1 if use_graph else 0
+    cfg.trial_width = trial_width
     arena = None
     tstream = None
     if use_torch:

@@ -17,6 +17,8 @@ using namespace pg;
 namespace {
 
 constexpr int64_t kAlign = 256;
+constexpr int kDefaultTrialWidth = 16;
+constexpr int kMaxTrialWidth = 64;
 
 struct PlanHost {
     bool active = false;
@@ -26,6 +28,7 @@ struct PlanHost {
     int coll_kind = 0, d = 0, p = 0;
     double dt = 0.0;
     int lanes = 0;
+    int max_bisect = 0;
 };
 
 struct ClassKey {
@@ -60,6 +63,7 @@ struct pgvimp_ctx {
     int g_iters = -1;
     int64_t g_hw = -1;
     bool g_restart = false;
+    int g_rounds = -1;
     std::vector<ClassKey> g_classes;
     bool g_profiled = false;
     // profiling
@@ -306,6 +310,11 @@ int64_t pgvimp_device_bytes(const pgvimp_ctx* ctx) { return ctx ? (int64_t)ctx->
 
 static int64_t layout_bytes(const pgvimp_engine_cfg* cfg);
 
+// Trial step sizes evaluated concurrently per plan (1..kMaxTrialWidth).
+static int64_t trial_width(const pgvimp_engine_cfg* cfg) {
+    return cfg->trial_width > 0 ? std::min<int64_t>(cfg->trial_width, kMaxTrialWidth) : kDefaultTrialWidth;
+}
+
 int64_t pgvimp_arena_bytes(const pgvimp_engine_cfg* cfg) {
     if (!cfg || !chain_supported(cfg->n) || cfg->max_plans < 1 || cfg->max_states < 1 || cfg->heap_bytes < 0)
         return PGVIMP_EINVAL;
@@ -327,18 +336,23 @@ static int64_t carve(pgvimp_ctx* c, const pgvimp_engine_cfg* cfg, DevState& st, 
     };
     take(&st.plans, P * (int64_t)sizeof(PlanDev));
     take(&st.state_plan, S * 4);
-    double** sq[] = {&st.KD, &st.KU, &st.Phi, &st.Qinv, &st.LD, &st.LU, &st.SD, &st.SU, &st.TD, &st.TU, &st.TSD, &st.TSU};
+    const int64_t W = trial_width(cfg);
+    double** sq[] = {&st.KD, &st.KU, &st.KH, &st.Phi, &st.Qinv, &st.LD, &st.LU, &st.SD, &st.SU};
     for (auto p : sq) take(p, S * n * n * 8);
-    double** vec[] = {&st.eta, &st.abar, &st.mu, &st.Tmu, &st.rb, &st.Lmu};
+    double** vec[] = {&st.eta, &st.abar, &st.mu, &st.rb, &st.Lmu};
     for (auto p : vec) take(p, S * n * 8);
+    take(&st.TSD, W * S * n * n * 8);
+    take(&st.TSU, W * S * n * n * 8);
+    take(&st.Tmu, W * S * n * 8);
+    take(&st.tres, P * W * 4 * 8);
     take(&st.Ecol, S * 8);
     take(&st.gcol, S * dmax * 8);
     take(&st.Hcol, S * dmax * dmax * 8);
     take(&st.Epri, (S + P) * 8);
-    take(&st.ws, S * ws_stride * 8);
-    take(&st.seg, P * kMaxSeg * (int64_t)seg_stride * 8);
+    take(&st.ws, 2 * W * S * ws_stride * 8);
+    take(&st.seg, P * W * 2 * kMaxSeg * (int64_t)seg_stride * 8);
     const int64_t tws_stride = (int64_t)kTwsBlocks * n * n + (int64_t)kTwsVecs * n;
-    take(&st.tws, P * kChainThreads * tws_stride * 8);
+    take(&st.tws, P * W * kTrialThreads * tws_stride * 8);
     take(&st.gh_x64, (kMaxGH + 1) * kMaxGH * 8);
     take(&st.gh_w64, (kMaxGH + 1) * kMaxGH * 8);
     take(&st.gh_x32, (kMaxGH + 1) * kMaxGH * 4);
@@ -354,6 +368,7 @@ static int64_t carve(pgvimp_ctx* c, const pgvimp_engine_cfg* cfg, DevState& st, 
     st.ws_stride = ws_stride;
     st.seg_stride = seg_stride;
     st.tws_stride = tws_stride;
+    st.W = (int32_t)W;
     return off;
 }
 
@@ -611,6 +626,7 @@ int pgvimp_add_plan(pgvimp_ctx* c, const pgvimp_problem* p, int32_t* plan_out) {
     ph.d = pd.d;
     ph.p = p->gh_points;
     ph.dt = p->dt;
+    ph.max_bisect = p->max_bisect;
     ph.lanes = coll ? (c->cfg.lanes_per_factor > 0 ? c->cfg.lanes_per_factor
                                                    : default_lanes(p->coll_kind, pd.d, p->gh_points))
                     : 0;
@@ -724,8 +740,17 @@ static int max_live_N(pgvimp_ctx* c) {
     return m;
 }
 
+// Windows of trial step sizes needed by the live plans.
+static int trial_rounds(pgvimp_ctx* c) {
+    int mb = 1;
+    for (auto& ph : c->plans)
+        if (ph.active) mb = std::max(mb, ph.max_bisect);
+    return (mb + c->st.W - 1) / c->st.W;
+}
+
 static int enqueue_iters(pgvimp_ctx* c, int n_iters, const std::vector<ClassKey>& cls, int64_t shw, int phw,
                          bool timed, bool restart) {
+    const int rounds = trial_rounds(c);
     if (restart) {
         // every live plan: prior from its stored dynamics, mu_0 = prior mean,
         // Lambda_0 = K^-1, marginals, budget reset (Alg. 1 set-up)
@@ -762,7 +787,7 @@ static int enqueue_iters(pgvimp_ctx* c, int n_iters, const std::vector<ClassKey>
             e = ev_pair(1);
             HCK(c, hipEventRecord(e.first, c->stream));
         }
-        HCK(c, launch_chain(c->st, CHAIN_PROX, 0, phw, c->stream));
+        HCK(c, launch_iteration(c->st, phw, rounds, c->stream));
         if (timed) HCK(c, hipEventRecord(e.second, c->stream));
     }
     return PGVIMP_OK;
@@ -807,7 +832,7 @@ static int run_iters(pgvimp_ctx* c, int32_t n_iters, pgvimp_stats* per_plan, boo
         // cannot be queried for elapsed time.
         if (c->cfg.use_graph && !timed) {
             if (!c->gexec || c->g_iters != n_iters || c->g_hw != shw || !(c->g_classes == cls) ||
-                c->g_profiled != timed || c->g_restart != restart) {
+                c->g_profiled != timed || c->g_restart != restart || c->g_rounds != trial_rounds(c)) {
                 drop_graph(c);
                 HCK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
                 rc = enqueue_iters(c, n_iters, cls, shw, (int)c->plans.size(), timed, restart);
@@ -823,6 +848,7 @@ static int run_iters(pgvimp_ctx* c, int32_t n_iters, pgvimp_stats* per_plan, boo
                 c->g_iters = n_iters;
                 c->g_hw = shw;
                 c->g_restart = restart;
+                c->g_rounds = trial_rounds(c);
                 c->g_classes = cls;
                 c->g_profiled = timed;
             }

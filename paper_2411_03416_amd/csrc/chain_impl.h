@@ -20,6 +20,14 @@
 //
 // The same elimination with a right-hand side solves
 // (K^-1 + Lambda_k / beta) mu' = eta - g + Lambda_k mu_k / beta.
+//
+// Step-size selection.  Halving from beta_max accepts the first trial step
+// that passes (Alg. 1, App. C), so the trials are independent of each
+// other: one iteration evaluates a window of W consecutive trial step sizes
+// at once, one workgroup per (plan, trial), and a select kernel takes the
+// first passing trial of the window in order.  Plans still pending after a
+// window continue with the next W step sizes.  The chosen step and every
+// result are the same as trying the step sizes one after another.
 #pragma once
 #include "blockmath.h"
 #include "ctx.h"
@@ -52,8 +60,10 @@ struct WsLayout {
     static constexpr int STRIDE = 3 * n * n + n;
 };
 
-// Blocks of the matrix being factored: D_i = D0_i + c1 * D1_i, U likewise
-// (D1/U1 may be null).  The right-hand side r_i = R0_i + c1 * R1_i.
+// Blocks of the matrix being factored: D_i = a0 D0_i + a1 D1_i, U likewise
+// (D1/U1 may be null), right-hand side r_i = a0 R0_i + a1 R1_i.  Inputs are
+// SoA with stride S; the element for output index s is read at s + shift
+// (outputs of trial slot t live t * S further on).
 struct BlockSrc {
     const double* D0;
     const double* D1;
@@ -61,9 +71,13 @@ struct BlockSrc {
     const double* U1;
     const double* R0;
     const double* R1;
-    double c1;
-    int64_t S;
+    double a0, a1;
+    int64_t S, shift;
 };
+
+// Entry e of a matrix built as a0 X0 + a1 X1 (the same expression is used
+// when the accepted trial precision is written back).
+__device__ __forceinline__ double lin2(double a0, double x0, double a1, double x1) { return fma(a1, x1, a0 * x0); }
 
 template <int n>
 __device__ __forceinline__ void ld_soa(const double* __restrict__ X, int64_t S, int64_t s, double* M) {
@@ -99,30 +113,24 @@ __device__ __forceinline__ void ld_aos(const double* __restrict__ p, double* M, 
 
 template <int n>
 __device__ __forceinline__ void src_D(const BlockSrc& b, int64_t s, double* M) {
+    s += b.shift;
 PG_UNROLL
-    for (int e = 0; e < n * n; ++e) {
-        double v = b.D0[e * b.S + s];
-        if (b.D1) v = fma(b.c1, b.D1[e * b.S + s], v);
-        M[e] = v;
-    }
+    for (int e = 0; e < n * n; ++e)
+        M[e] = b.D1 ? lin2(b.a0, b.D0[e * b.S + s], b.a1, b.D1[e * b.S + s]) : b.a0 * b.D0[e * b.S + s];
 }
 template <int n>
 __device__ __forceinline__ void src_U(const BlockSrc& b, int64_t s, double* M) {
+    s += b.shift;
 PG_UNROLL
-    for (int e = 0; e < n * n; ++e) {
-        double v = b.U0[e * b.S + s];
-        if (b.U1) v = fma(b.c1, b.U1[e * b.S + s], v);
-        M[e] = v;
-    }
+    for (int e = 0; e < n * n; ++e)
+        M[e] = b.U1 ? lin2(b.a0, b.U0[e * b.S + s], b.a1, b.U1[e * b.S + s]) : b.a0 * b.U0[e * b.S + s];
 }
 template <int n>
 __device__ __forceinline__ void src_r(const BlockSrc& b, int64_t s, double* v) {
+    s += b.shift;
 PG_UNROLL
-    for (int e = 0; e < n; ++e) {
-        double x = b.R0[e * b.S + s];
-        if (b.R1) x = fma(b.c1, b.R1[e * b.S + s], x);
-        v[e] = x;
-    }
+    for (int e = 0; e < n; ++e)
+        v[e] = b.R1 ? lin2(b.a0, b.R0[e * b.S + s], b.a1, b.R1[e * b.S + s]) : b.a0 * b.R0[e * b.S + s];
 }
 
 __device__ __forceinline__ void seg_bounds(int N, int nseg, int j, int& a, int& b, bool& hasL, bool& hasR) {
@@ -149,20 +157,23 @@ __device__ __forceinline__ bool seg_forward(const BlockSrc& M, int64_t off, int 
     PG_MAT(P, ts);
     PG_MAT(X, ts);
     PG_MAT(Z, ts);
-    PG_MAT(U, ts);
+    PG_MAT(U, ts);   // U_i of the current step
+    PG_MAT(Dn, ts);  // D_{i+1} and U_{i+1}, loaded one step ahead so the
+    PG_MAT(Un, ts);  // loads overlap the current step's arithmetic
     PG_MAT(Pinv, ts);
     PG_MAT(GU, ts);
     PG_MAT(HX, ts);
-    PG_VEC(y, ts); PG_VEC(yv, ts); PG_VEC(rL, ts);
+    PG_VEC(y, ts); PG_VEC(yv, ts); PG_VEC(rL, ts); PG_VEC(rn, ts);
     src_D<n>(M, off + a, P);
     if (hasL) {
-        src_U<n>(M, off + a - 1, U);
+        src_U<n>(M, off + a - 1, Un);
 PG_UNROLL
         for (int r = 0; r < n; ++r)
 PG_UNROLL
-            for (int c = 0; c < n; ++c) X[r * n + c] = U[c * n + r];
+            for (int c = 0; c < n; ++c) X[r * n + c] = Un[c * n + r];
         mzero<n>(Z);
     }
+    if (a < b || hasR) src_U<n>(M, off + a, U);
     if (RHS) {
         src_r<n>(M, off + a, y);
 PG_UNROLL
@@ -171,13 +182,17 @@ PG_UNROLL
     bool ok = true;
     for (int i = a; i <= b; ++i) {
         TS lt = ts;
+        const bool hasNext = (i < b) || hasR;
+        if (i < b) {
+            src_D<n>(M, off + i + 1, Dn);
+            if (i + 1 < b || hasR) src_U<n>(M, off + i + 1, Un);
+            if (RHS) src_r<n>(M, off + i + 1, rn);
+        }
         ok = spd_inverse<n>(P, Pinv, logdet, lt) && ok;
         double* w = ws + (off + i) * (int64_t)wsst;
 PG_UNROLL
         for (int e = 0; e < n * n; ++e) w[W::PINV + e] = Pinv[e];
-        const bool hasNext = (i < b) || hasR;
         if (hasNext) {
-            src_U<n>(M, off + i, U);
             mmul<n>(Pinv, U, GU);
 PG_UNROLL
             for (int e = 0; e < n * n; ++e) w[W::GU + e] = GU[e];
@@ -195,7 +210,7 @@ PG_UNROLL
             if (hasL) mvec_tn_sub<n>(X, yv, rL);
         }
         if (i < b) {
-            src_D<n>(M, off + i + 1, P);
+            mcopy<n>(Dn, P);
             msub_tn<n>(U, GU, P);
             if (hasL) {
                 PG_MAT(T, lt);
@@ -204,9 +219,11 @@ PG_UNROLL
                 for (int e = 0; e < n * n; ++e) X[e] = -T[e];
             }
             if (RHS) {
-                src_r<n>(M, off + i + 1, y);
+PG_UNROLL
+                for (int e = 0; e < n; ++e) y[e] = rn[e];
                 mvec_tn_sub<n>(U, yv, y);
             }
+            if (i + 1 < b || hasR) mcopy<n>(Un, U);
         } else {
             double* g = sg + (int64_t)j * G::STRIDE;
             if (hasR) {
@@ -504,12 +521,12 @@ PG_UNROLL
 
 // Workgroup-wide GBP: marginals of (D, U) from src into (SDo, SUo).
 template <int n>
-__device__ __forceinline__ bool wg_gbp(const BlockSrc& M, const DevState& st, int64_t off, int N, int nseg, double* sg,
-                       double* SDo, double* SUo, double* logdet_out, double* sh_ld, int* sh_ok, TS ts) {
-    const int tid = threadIdx.x;
+__device__ __forceinline__ bool wg_gbp(const BlockSrc& M, const DevState& st, double* ws, int tid, int64_t off,
+                                       int64_t So, int N, int nseg, double* sg, double* SDo, double* SUo,
+                                       double* logdet_out, double* sh_ld, int* sh_ok, TS ts) {
     double ld = 0.0;
     bool ok = true;
-    if (tid < nseg) ok = seg_forward<n, false>(M, off, N, nseg, tid, st.ws, st.ws_stride, sg, &ld, ts);
+    if (tid < nseg) ok = seg_forward<n, false>(M, off, N, nseg, tid, ws, st.ws_stride, sg, &ld, ts);
     sh_ld[tid] = ld;
     sh_ok[tid] = ok ? 1 : 0;
     __syncthreads();
@@ -521,38 +538,37 @@ __device__ __forceinline__ bool wg_gbp(const BlockSrc& M, const DevState& st, in
             all &= sh_ok[t];
         }
         double ldr = 0.0;
-        bool okr = all ? reduced_chain<n, false, true>(M, off, N, nseg, sg, SDo, nullptr, st.S, &ldr, ts) : false;
+        bool okr = all ? reduced_chain<n, false, true>(M, off, N, nseg, sg, SDo, nullptr, So, &ldr, ts) : false;
         sh_ld[kChainThreads] = tot + ldr;
         sh_ok[kChainThreads] = (all && okr) ? 1 : 0;
     }
     __syncthreads();
     const bool okall = sh_ok[kChainThreads] != 0;
     *logdet_out = sh_ld[kChainThreads];
-    if (okall && tid < nseg) seg_backward_cov<n>(off, N, nseg, tid, st.ws, st.ws_stride, sg, SDo, SUo, st.S, ts);
+    if (okall && tid < nseg) seg_backward_cov<n>(off, N, nseg, tid, ws, st.ws_stride, sg, SDo, SUo, So, ts);
     __syncthreads();
     return okall;
 }
 
 // Workgroup-wide solve of (D, U) x = r into xo.
 template <int n>
-__device__ __forceinline__ bool wg_solve(const BlockSrc& M, const DevState& st, int64_t off, int N, int nseg, double* sg,
-                         double* xo, int* sh_ok, TS ts) {
-    const int tid = threadIdx.x;
+__device__ __forceinline__ bool wg_solve(const BlockSrc& M, const DevState& st, double* ws, int tid, int64_t off,
+                                         int64_t So, int N, int nseg, double* sg, double* xo, int* sh_ok, TS ts) {
     double ld = 0.0;
     bool ok = true;
-    if (tid < nseg) ok = seg_forward<n, true>(M, off, N, nseg, tid, st.ws, st.ws_stride, sg, &ld, ts);
+    if (tid < nseg) ok = seg_forward<n, true>(M, off, N, nseg, tid, ws, st.ws_stride, sg, &ld, ts);
     sh_ok[tid] = ok ? 1 : 0;
     __syncthreads();
     if (tid == 0) {
         int all = 1;
         for (int t = 0; t < kChainThreads; ++t) all &= sh_ok[t];
         double ldr = 0.0;
-        bool okr = all ? reduced_chain<n, true, false>(M, off, N, nseg, sg, nullptr, xo, st.S, &ldr, ts) : false;
+        bool okr = all ? reduced_chain<n, true, false>(M, off, N, nseg, sg, nullptr, xo, So, &ldr, ts) : false;
         sh_ok[kChainThreads] = (all && okr) ? 1 : 0;
     }
     __syncthreads();
     const bool okall = sh_ok[kChainThreads] != 0;
-    if (okall && tid < nseg) seg_backward_rhs<n>(off, N, nseg, tid, st.ws, st.ws_stride, sg, xo, st.S, ts);
+    if (okall && tid < nseg) seg_backward_rhs<n>(off, N, nseg, tid, ws, st.ws_stride, sg, xo, So, ts);
     __syncthreads();
     return okall;
 }
@@ -645,21 +661,40 @@ PG_UNROLL
     return tot;
 }
 
+// Sum over the workgroup in a fixed order (sh holds blockDim.x + 1 doubles).
 __device__ __forceinline__ double wg_sum(double v, double* sh) {
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, nt = blockDim.x;
     sh[tid] = v;
     __syncthreads();
     if (tid == 0) {
         double t = 0.0;
-        for (int k = 0; k < kChainThreads; ++k) t += sh[k];
-        sh[kChainThreads] = t;
+        for (int k = 0; k < nt; ++k) t += sh[k];
+        sh[nt] = t;
     }
     __syncthreads();
-    const double r = sh[kChainThreads];
+    const double r = sh[nt];
     __syncthreads();
     return r;
 }
 
+// Scratch of (plan, trial slot, half): half 0 serves the marginals, half 1
+// the mean solve of the same trial, which run side by side.
+template <int n>
+__device__ __forceinline__ double* seg_scratch(const DevState& st, int pid, int t, int half) {
+    return st.seg + ((((int64_t)pid * st.W + t) * 2 + half) * kMaxSeg) * st.seg_stride;
+}
+template <int n>
+__device__ __forceinline__ TS thread_ws(const DevState& st, int pid, int t) {
+    return TS{st.tws + (((int64_t)pid * st.W + t) * kTrialThreads + threadIdx.x) * st.tws_stride};
+}
+__device__ __forceinline__ double* state_ws(const DevState& st, int half) {
+    return st.ws + (int64_t)half * st.W * st.S * st.ws_stride;
+}
+
+// Set-up and marginals of a plan (trial slot 0 of its scratch):
+// CHAIN_INIT: Lambda = K^-1, mean = solve(K^-1, eta), marginals, budget reset;
+// CHAIN_REINIT: Lambda = K^-1 (mean kept), marginals;
+// CHAIN_MARGINALS: marginals of the current Lambda.
 template <int n>
 __global__ void __launch_bounds__(kChainThreads) chain_kernel(DevState st, int mode, int plan_lo) {
     __shared__ double sh_d[kChainThreads + 1];
@@ -667,16 +702,15 @@ __global__ void __launch_bounds__(kChainThreads) chain_kernel(DevState st, int m
     const int pid = plan_lo + blockIdx.x;
     PlanDev& p = st.plans[pid];
     if (!p.active) return;
-    if (mode == CHAIN_PROX && p.iters_left <= 0) return;
     const int tid = threadIdx.x;
     const int N = p.N;
     const int64_t off = p.off;
     const int64_t S = st.S;
     const int nseg = p.nseg;
-    double* sg = st.seg + (int64_t)pid * kMaxSeg * st.seg_stride;
-    TS ts{st.tws + ((int64_t)pid * kChainThreads + tid) * st.tws_stride};
+    double* sg = seg_scratch<n>(st, pid, 0, 0);
+    double* ws = state_ws(st, 0);
+    TS ts = thread_ws<n>(st, pid, 0);
     const int n2 = n * n;
-
     if (mode == CHAIN_INIT || mode == CHAIN_REINIT) {
         for (int i = tid; i < N; i += kChainThreads) {
             for (int e = 0; e < n2; ++e) {
@@ -686,8 +720,8 @@ __global__ void __launch_bounds__(kChainThreads) chain_kernel(DevState st, int m
         }
         __syncthreads();
         if (mode == CHAIN_INIT) {
-            BlockSrc M{st.KD, nullptr, st.KU, nullptr, st.eta, nullptr, 0.0, S};
-            wg_solve<n>(M, st, off, N, nseg, sg, st.mu, sh_i, ts);
+            BlockSrc M{st.KD, nullptr, st.KU, nullptr, st.eta, nullptr, 1.0, 0.0, S, 0};
+            wg_solve<n>(M, st, ws, tid, off, S, N, nseg, sg, st.mu, sh_i, ts);
             if (tid == 0) {
                 p.iters_left = p.n_iters;
                 p.iters_done = 0;
@@ -695,33 +729,56 @@ __global__ void __launch_bounds__(kChainThreads) chain_kernel(DevState st, int m
             }
         }
     }
-    if (mode != CHAIN_PROX) {
-        BlockSrc M{st.LD, nullptr, st.LU, nullptr, nullptr, nullptr, 0.0, S};
-        double ld = 0.0;
-        const bool ok = wg_gbp<n>(M, st, off, N, nseg, sg, st.SD, st.SU, &ld, sh_d, sh_i, ts);
-        if (tid == 0) {
-            p.logdet = ok ? ld : NAN;
-            p.status = ok ? 0 : PGVIMP_ENOTPD;
-        }
+    BlockSrc M{st.LD, nullptr, st.LU, nullptr, nullptr, nullptr, 1.0, 0.0, S, 0};
+    double ld = 0.0;
+    const bool ok = wg_gbp<n>(M, st, ws, tid, off, S, N, nseg, sg, st.SD, st.SU, &ld, sh_d, sh_i, ts);
+    if (tid == 0) {
+        p.logdet = ok ? ld : NAN;
+        p.status = ok ? 0 : PGVIMP_ENOTPD;
+    }
+}
+
+// One proximal iteration (Alg. 1), part 1: per-state quantities shared by all
+// trial step sizes -- KH = K^-1 + H (collision Hessians on the diagonal
+// blocks), rb = eta - g, Lmu = Lambda_k mu_k -- and the expected costs.
+template <int n>
+__global__ void __launch_bounds__(kChainThreads) prep_kernel(DevState st) {
+    __shared__ double sh_d[kChainThreads + 1];
+    const int pid = blockIdx.x;
+    PlanDev& p = st.plans[pid];
+    if (!p.active) return;
+    const int tid = threadIdx.x;
+    if (p.iters_left <= 0) {
+        if (tid == 0) p.phase = 1;
         return;
     }
-
-    // ---------------- one proximal iteration (Alg. 1) ----------------
-    const int d = p.d;
-    // per-state preparation: rb = eta - g_emb, Lmu = Lambda_k mu_k, costs
+    const int N = p.N, d = p.d;
+    const int64_t off = p.off, S = st.S;
+    const int n2 = n * n;
+    TS ts = thread_ws<n>(st, pid, 0);
     double ecol = 0.0, epri = 0.0;
     for (int i = tid; i < N; i += kChainThreads) {
         TS lt = ts;
         const int64_t s = off + i;
+        const bool act = coll_active<n>(p, i);
+        for (int e = 0; e < n2; ++e) st.KH[e * S + s] = st.KD[e * S + s];
         PG_VEC(r, lt);
         ld_vec<n>(st.eta, S, s, r);
-        if (coll_active<n>(p, i)) {
+        if (act) {
             ecol += st.Ecol[s];
-            for (int a = 0; a < d; ++a) r[p.coll_index[a]] -= st.gcol[a * S + s];
+            for (int a = 0; a < d; ++a) {
+                r[p.coll_index[a]] -= st.gcol[a * S + s];
+                for (int b2 = 0; b2 < d; ++b2) {
+                    const int e = p.coll_index[a] * n + p.coll_index[b2];
+                    st.KH[e * S + s] = st.KD[e * S + s] + st.Hcol[(a * d + b2) * S + s];
+                }
+            }
         }
         st_vec<n>(st.rb, S, s, r);
         PG_MAT(Dm, lt);
-        PG_VEC(m, lt); PG_VEC(t, lt); PG_VEC(acc, lt);
+        PG_VEC(m, lt);
+        PG_VEC(t, lt);
+        PG_VEC(acc, lt);
         ld_soa<n>(st.LD, S, s, Dm);
         ld_vec<n>(st.mu, S, s, m);
         mvec<n>(Dm, m, acc);
@@ -746,125 +803,170 @@ PG_UNROLL
     }
     ecol = wg_sum(ecol, sh_d);
     epri = wg_sum(epri, sh_d);
-
-    const double T = p.temperature;
-    double beta = p.beta_max;
-    bool accepted = false;
-    int trials = 0;
-    double kl = NAN, ld_new = 0.0;
-    for (int t = 0; t < p.max_bisect; ++t) {
-        trials = t + 1;
-        const double c = 1.0 / fma(beta, T, 1.0);
-        // trial precision Lambda' = (beta (K^-1 + H) + Lambda_k) / (beta T + 1)
-        for (int i = tid; i < N; i += kChainThreads) {
-            const int64_t s = off + i;
-            const bool act = coll_active<n>(p, i);
-            for (int r = 0; r < n; ++r)
-                for (int q = 0; q < n; ++q) {
-                    const int e = r * n + q;
-                    double k = st.KD[e * S + s];
-                    st.TD[e * S + s] = c * fma(beta, k, st.LD[e * S + s]);
-                }
-            if (act) {
-                for (int a = 0; a < d; ++a)
-                    for (int b2 = 0; b2 < d; ++b2) {
-                        const int e = p.coll_index[a] * n + p.coll_index[b2];
-                        const double k = st.KD[e * S + s] + st.Hcol[(a * d + b2) * S + s];
-                        st.TD[e * S + s] = c * fma(beta, k, st.LD[e * S + s]);
-                    }
-            }
-            if (i < N - 1) {
-                for (int e = 0; e < n2; ++e) st.TU[e * S + s] = c * fma(beta, st.KU[e * S + s], st.LU[e * S + s]);
-            }
-        }
-        __syncthreads();
-        BlockSrc MT{st.TD, nullptr, st.TU, nullptr, nullptr, nullptr, 0.0, S};
-        double ldt = 0.0;
-        const bool pd = wg_gbp<n>(MT, st, off, N, nseg, sg, st.TSD, st.TSU, &ldt, sh_d, sh_i, ts);
-        if (!pd) {
-            beta *= 0.5;
-            continue;
-        }
-        // mean: (K^-1 + Lambda_k / beta) mu' = rb + Lmu / beta
-        const double ib = 1.0 / beta;
-        BlockSrc MM{st.KD, st.LD, st.KU, st.LU, st.rb, st.Lmu, ib, S};
-        wg_solve<n>(MM, st, off, N, nseg, sg, st.Tmu, sh_i, ts);
-        // KL(q' || q_k) = 1/2 [beta (T dim - tr((K^-1+H) Sigma')) + dmu^T Lambda_k dmu
-        //                    + log det Lambda' - log det Lambda_k]
-        double trKH = 0.0, quad = 0.0;
-        for (int i = tid; i < N; i += kChainThreads) {
-            TS lt = ts;
-            const int64_t s = off + i;
-            const bool act = coll_active<n>(p, i);
-            PG_MAT(Sg, lt);
-            ld_soa<n>(st.TSD, S, s, Sg);
-            for (int r = 0; r < n; ++r)
-                for (int q = 0; q < n; ++q) trKH = fma(st.KD[(r * n + q) * S + s], Sg[q * n + r], trKH);
-            if (act) {
-                for (int a = 0; a < d; ++a)
-                    for (int b2 = 0; b2 < d; ++b2)
-                        trKH = fma(st.Hcol[(a * d + b2) * S + s], Sg[p.coll_index[b2] * n + p.coll_index[a]], trKH);
-            }
-            PG_MAT(Dm, lt);
-            PG_VEC(dm, lt); PG_VEC(t, lt);
-            for (int e = 0; e < n; ++e) dm[e] = st.Tmu[e * S + s] - st.mu[e * S + s];
-            ld_soa<n>(st.LD, S, s, Dm);
-            mvec<n>(Dm, dm, t);
-            for (int e = 0; e < n; ++e) quad = fma(dm[e], t[e], quad);
-            if (i < N - 1) {
-                PG_MAT(Su, lt);
-                PG_VEC(dn, lt);
-                ld_soa<n>(st.TSU, S, s, Su);
-                for (int e = 0; e < n2; ++e) trKH = fma(2.0 * st.KU[e * S + s], Su[e], trKH);
-                for (int e = 0; e < n; ++e) dn[e] = st.Tmu[e * S + s + 1] - st.mu[e * S + s + 1];
-                ld_soa<n>(st.LU, S, s, Dm);
-                mvec<n>(Dm, dn, t);
-                for (int e = 0; e < n; ++e) quad = fma(2.0 * dm[e], t[e], quad);
-            }
-        }
-        trKH = wg_sum(trKH, sh_d);
-        quad = wg_sum(quad, sh_d);
-        kl = 0.5 * (beta * (T * (double)N * n - trKH) + quad + ldt - p.logdet);
-        if (kl <= p.kl_bound) {
-            accepted = true;
-            ld_new = ldt;
-            break;
-        }
-        beta *= 0.5;
-    }
-    if (accepted) {
-        for (int i = tid; i < N; i += kChainThreads) {
-            const int64_t s = off + i;
-            for (int e = 0; e < n2; ++e) {
-                st.LD[e * S + s] = st.TD[e * S + s];
-                st.SD[e * S + s] = st.TSD[e * S + s];
-                if (i < N - 1) {
-                    st.LU[e * S + s] = st.TU[e * S + s];
-                    st.SU[e * S + s] = st.TSU[e * S + s];
-                }
-            }
-            for (int e = 0; e < n; ++e) st.mu[e * S + s] = st.Tmu[e * S + s];
-        }
-    }
-    __syncthreads();
     if (tid == 0) {
         p.E_coll = ecol;
         p.E_prior = epri;
-        p.trials = trials;
-        p.trials_total += trials;
-        if (accepted) {
-            p.logdet = ld_new;
+        p.phase = 0;
+    }
+}
+
+// Part 2: trial step size number round * W + blockIdx.y for plan blockIdx.x:
+//   Lambda' = (beta (K^-1 + H) + Lambda_k) / (beta T + 1)  -> marginals, log det, PD
+//   (K^-1 + Lambda_k / beta) mu' = eta - g + Lambda_k mu_k / beta
+//   KL(q' || q_k) = 1/2 [beta (T dim - tr((K^-1 + H) Sigma')) + dmu^T Lambda_k dmu
+//                        + log det Lambda' - log det Lambda_k]
+// (the trace term uses Lambda_k = (beta T + 1) Lambda' - beta (K^-1 + H) and
+// tr(Lambda' Sigma') = dim).  Results go to the trial slot and st.tres.
+template <int n>
+__global__ void __launch_bounds__(kTrialThreads) trial_kernel(DevState st, int round) {
+    __shared__ double sh_d[kTrialThreads + 1];
+    __shared__ int sh_i[kChainThreads + 1];
+    __shared__ int sh_j[kChainThreads + 1];
+    const int pid = blockIdx.x, t = blockIdx.y;
+    const PlanDev& p = st.plans[pid];
+    if (!p.active || p.phase != 0) return;
+    const int tt = round * st.W + t;
+    if (tt >= p.max_bisect) return;
+    const int tid = threadIdx.x;
+    const int half = tid / kChainThreads, lane = tid % kChainThreads;
+    const int N = p.N, nseg = p.nseg;
+    const int64_t S = st.S, off = p.off;
+    const int64_t SW = S * st.W, offt = (int64_t)t * S + off, shift = -(int64_t)t * S;
+    double* sg = seg_scratch<n>(st, pid, t, half);
+    double* ws = state_ws(st, half);
+    TS ts = thread_ws<n>(st, pid, t);
+    double* res = st.tres + ((int64_t)pid * st.W + t) * 4;
+    const double beta = ldexp(p.beta_max, -tt);
+    const double T = p.temperature;
+    const double c = 1.0 / fma(beta, T, 1.0);
+    // wave 0: marginals and PD test of the trial precision; wave 1: trial mean.
+    // Both helpers pass the same three workgroup barriers.
+    double ldt = 0.0;
+    if (half == 0) {
+        BlockSrc MT{st.KH, st.LD, st.KU, st.LU, nullptr, nullptr, c * beta, c, S, shift};
+        wg_gbp<n>(MT, st, ws, lane, offt, SW, N, nseg, sg, st.TSD, st.TSU, &ldt, sh_d, sh_i, ts);
+    } else {
+        BlockSrc MM{st.KD, st.LD, st.KU, st.LU, st.rb, st.Lmu, 1.0, 1.0 / beta, S, shift};
+        wg_solve<n>(MM, st, ws, lane, offt, SW, N, nseg, sg, st.Tmu, sh_j, ts);
+    }
+    __syncthreads();
+    const bool pd = sh_i[kChainThreads] != 0;
+    ldt = sh_d[kChainThreads];
+    __syncthreads();
+    if (!pd) {
+        if (tid == 0) {
+            res[0] = 0.0;
+            res[1] = NAN;
+            res[2] = NAN;
+            res[3] = beta;
+        }
+        return;
+    }
+    double trKH = 0.0, quad = 0.0;
+    const int n2 = n * n;
+    for (int i = tid; i < N; i += kTrialThreads) {
+        TS lt = ts;
+        const int64_t s = off + i, q = offt + i;
+        PG_MAT(Sg, lt);
+        PG_MAT(Dm, lt);
+        PG_VEC(dm, lt);
+        PG_VEC(tv, lt);
+        ld_soa<n>(st.TSD, SW, q, Sg);
+        for (int r = 0; r < n; ++r)
+            for (int k = 0; k < n; ++k) trKH = fma(st.KH[(r * n + k) * S + s], Sg[k * n + r], trKH);
+        for (int e = 0; e < n; ++e) dm[e] = st.Tmu[e * SW + q] - st.mu[e * S + s];
+        ld_soa<n>(st.LD, S, s, Dm);
+        mvec<n>(Dm, dm, tv);
+        for (int e = 0; e < n; ++e) quad = fma(dm[e], tv[e], quad);
+        if (i < N - 1) {
+            PG_MAT(Su, lt);
+            PG_VEC(dn, lt);
+            ld_soa<n>(st.TSU, SW, q, Su);
+            for (int e = 0; e < n2; ++e) trKH = fma(2.0 * st.KU[e * S + s], Su[e], trKH);
+            for (int e = 0; e < n; ++e) dn[e] = st.Tmu[e * SW + q + 1] - st.mu[e * S + s + 1];
+            ld_soa<n>(st.LU, S, s, Dm);
+            mvec<n>(Dm, dn, tv);
+            for (int e = 0; e < n; ++e) quad = fma(2.0 * dm[e], tv[e], quad);
+        }
+    }
+    trKH = wg_sum(trKH, sh_d);
+    quad = wg_sum(quad, sh_d);
+    if (tid == 0) {
+        res[0] = 1.0;
+        res[1] = 0.5 * (beta * (T * (double)N * n - trKH) + quad + ldt - p.logdet);
+        res[2] = ldt;
+        res[3] = beta;
+    }
+}
+
+// Part 3: take the first passing trial of this window (in step-size order)
+// and write it back as the new iterate; finish the iteration of plans whose
+// step sizes are exhausted (state unchanged, ENOCONV).
+template <int n>
+__global__ void __launch_bounds__(kChainThreads) select_kernel(DevState st, int round) {
+    const int pid = blockIdx.x;
+    PlanDev& p = st.plans[pid];
+    if (!p.active || p.phase != 0) return;
+    const int tid = threadIdx.x;
+    const int W = st.W;
+    int pick = -1;
+    int tried = 0;
+    double last_kl = NAN;
+    for (int t = 0; t < W; ++t) {
+        const int tt = round * W + t;
+        if (tt >= p.max_bisect) break;
+        const double* res = st.tres + ((int64_t)pid * W + t) * 4;
+        tried = tt + 1;
+        last_kl = res[1];
+        if (res[0] != 0.0 && res[1] <= p.kl_bound) {
+            pick = t;
+            break;
+        }
+    }
+    const bool exhausted = (round + 1) * W >= p.max_bisect;
+    if (pick < 0 && !exhausted) return;  // next window
+    __syncthreads();
+    const int N = p.N;
+    const int64_t S = st.S, off = p.off, SW = S * W;
+    const int n2 = n * n;
+    double beta = 0.0, kl = last_kl, ld = 0.0;
+    if (pick >= 0) {
+        const double* res = st.tres + ((int64_t)pid * W + pick) * 4;
+        beta = res[3];
+        kl = res[1];
+        ld = res[2];
+        const double c = 1.0 / fma(beta, p.temperature, 1.0);
+        const double a0 = c * beta, a1 = c;
+        const int64_t tq = (int64_t)pick * S;
+        for (int i = tid; i < N; i += kChainThreads) {
+            const int64_t s = off + i, q = tq + s;
+            for (int e = 0; e < n2; ++e) {
+                st.LD[e * S + s] = lin2(a0, st.KH[e * S + s], a1, st.LD[e * S + s]);
+                st.SD[e * S + s] = st.TSD[e * SW + q];
+                if (i < N - 1) {
+                    st.LU[e * S + s] = lin2(a0, st.KU[e * S + s], a1, st.LU[e * S + s]);
+                    st.SU[e * S + s] = st.TSU[e * SW + q];
+                }
+            }
+            for (int e = 0; e < n; ++e) st.mu[e * S + s] = st.Tmu[e * SW + q];
+        }
+    }
+    if (tid == 0) {
+        p.trials = pick >= 0 ? round * W + pick + 1 : tried;
+        p.trials_total += p.trials;
+        p.kl = kl;
+        if (pick >= 0) {
+            p.logdet = ld;
             p.beta = beta;
-            p.kl = kl;
             p.status = 0;
         } else {
             p.beta = 0.0;
-            p.kl = kl;
             p.status = PGVIMP_ENOCONV;
         }
         p.entropy = 0.5 * (double)N * n * (1.0 + 1.8378770664093453) - 0.5 * p.logdet;
         p.iters_left -= 1;
         p.iters_done += 1;
+        p.phase = 1;
     }
 }
 
@@ -872,7 +974,7 @@ PG_UNROLL
 template <int n>
 __global__ void __launch_bounds__(kChainThreads) prior_cost_kernel(DevState st, int plan) {
     const PlanDev& p = st.plans[plan];
-    const TS ts{st.tws + ((int64_t)plan * kChainThreads + threadIdx.x) * st.tws_stride};
+    const TS ts = thread_ws<n>(st, plan, 0);
     for (int i = threadIdx.x; i < p.N; i += kChainThreads) {
         double tr = 0.0, s0 = 0.0, g0 = 0.0;
         prior_cost_state<n>(st, p, i, &tr, &s0, &g0, ts);
@@ -886,6 +988,17 @@ template <int n>
 hipError_t launch_chain_n(const DevState& st, int mode, int lo, int hi, hipStream_t s) {
     if (hi <= lo) return hipSuccess;
     hipLaunchKernelGGL(chain_kernel<n>, dim3(hi - lo), dim3(kChainThreads), 0, s, st, mode, lo);
+    return hipGetLastError();
+}
+
+template <int n>
+hipError_t launch_iteration_n(const DevState& st, int phw, int rounds, hipStream_t s) {
+    if (phw <= 0) return hipSuccess;
+    hipLaunchKernelGGL(prep_kernel<n>, dim3(phw), dim3(kChainThreads), 0, s, st);
+    for (int r = 0; r < rounds; ++r) {
+        hipLaunchKernelGGL(trial_kernel<n>, dim3(phw, st.W), dim3(kTrialThreads), 0, s, st, r);
+        hipLaunchKernelGGL(select_kernel<n>, dim3(phw), dim3(kChainThreads), 0, s, st, r);
+    }
     return hipGetLastError();
 }
 

@@ -13,11 +13,12 @@ namespace pg {
 
 constexpr int kMaxSeg = 64;      // chain segments per plan (upper bound)
 constexpr int kChainThreads = 64; // one wavefront per plan in the chain kernel
+constexpr int kTrialThreads = 128; // trial kernel: marginals and mean solve side by side
 constexpr int kMaxGH = 10;        // Gauss-Hermite points per dimension
 // n x n temporaries a chain-kernel thread may hold at once.  Deepest call
-// paths: kernel loop body 1 + prior cost 8 = 9; segment elimination 7 +
-// Cholesky inverse 2 = 9; segment backward sweep 3 + 6 = 9.
-constexpr int kTwsBlocks = 12;
+// paths: kernel loop body 1 + prior cost 8 = 9; segment elimination 9 +
+// Cholesky inverse 2 = 11; segment backward sweep 3 + 6 = 9.
+constexpr int kTwsBlocks = 14;
 constexpr int kTwsVecs = 16;  // n-vector temporaries (deepest path: 8)
 
 // Per-plan parameters and statistics, read by every kernel.  One entry per
@@ -28,6 +29,7 @@ struct PlanDev {
     int32_t d, gh_points, gx, gy;
     int32_t gz, n_spheres, coll_states, status;
     int32_t trials, m, n_iters, trials_total;
+    int32_t phase, pad0;  // phase: 0 = step pending this iteration, 1 = done
     int32_t coll_index[PGVIMP_MAX_COLL_DIM];
     double temperature, beta_max, kl_bound, cell, dt;
     double inv_cell, hinge_eps, obs_weight, logdet;
@@ -62,8 +64,12 @@ struct DevState {
     // current iterate
     double *LD, *LU, *mu;  // precision blocks and mean
     double *SD, *SU;       // marginal covariances
-    // trial iterate
-    double *TD, *TU, *Tmu, *TSD, *TSU;
+    // K^-1 + H (collision Hessians added on the diagonal blocks)
+    double* KH;
+    // trial iterates: W slots, slot t of state s at t * S + s (stride W * S)
+    double *Tmu, *TSD, *TSU;
+    double* tres;  // per (plan, slot): passed, KL, log det, beta
+    int32_t W;     // trial step sizes evaluated concurrently
     // collision expectations (d-dim, not embedded): E [S], g [d][S], H [d*d][S]
     double *Ecol, *gcol, *Hcol;
     // mean-solve right-hand side parts: rb = eta - g, Lmu = Lambda_k mu_k
@@ -148,6 +154,8 @@ namespace pg {
 hipError_t launch_prior_build(const DevState& st, int plan_lo, int plan_hi, int maxN, hipStream_t s);
 hipError_t launch_prior_assemble(const DevState& st, int plan_lo, int plan_hi, int maxN, hipStream_t s);
 hipError_t launch_chain(const DevState& st, int mode, int plan_lo, int plan_hi, hipStream_t s);
+// one proximal iteration for plans [0, phw): prep, then rounds x (trials, select)
+hipError_t launch_iteration(const DevState& st, int phw, int rounds, hipStream_t s);
 hipError_t launch_expect(const DevState& st, int coll_kind, int d, int p, int precision, int lanes,
                          int64_t s_lo, int64_t s_hi, int respect_budget, hipStream_t s);
 hipError_t launch_prior_costs(const DevState& st, int plan, int N, hipStream_t s);
@@ -160,7 +168,7 @@ bool expect_supported(int coll_kind, int d, int p, int lanes);
 int default_lanes(int coll_kind, int d, int p);
 
 // modes of the chain kernel
-enum ChainMode { CHAIN_INIT = 0, CHAIN_MARGINALS = 1, CHAIN_PROX = 2, CHAIN_REINIT = 3 };
+enum ChainMode { CHAIN_INIT = 0, CHAIN_MARGINALS = 1, CHAIN_REINIT = 3 };
 // what to gather/scatter between SoA device arrays and [N][..] host layouts
 enum GatherWhat {
     G_SD = 0, G_SU = 1, G_MU = 2, G_LD = 3, G_LU = 4, G_ECOL = 5, G_GEMB = 6, G_HEMB = 7, G_EPRI = 8

@@ -399,3 +399,23 @@ def test_slr_matches_oracle(pg):
     mu, D2, U2 = pg.pgvimp_get_state(ctx, 0)
     assert rel(D2, pri["D"]) < 1e-9 and rel(U2, pri["U"]) < 1e-9
     assert np.array_equal(mu, p["nominal_mean"])
+
+
+def test_trial_window_does_not_change_results(pg):
+    # evaluating the halving sequence one step at a time or in windows gives
+    # the same chosen steps and bitwise the same iterates
+    probs = [workloads.point2d_problem(s, N=N) for s, N in [(5, 60), (6, 31)]]
+    ref = None
+    for w in (1, 3, 16):
+        ctx = pg.pgvimp_create(probs, use_graph=True, trial_width=w)
+        stats = [pg.pgvimp_prox_step(ctx, 1) for _ in range(8)]
+        states = [pg.pgvimp_get_state(ctx, k) for k in range(len(probs))]
+        if ref is None:
+            ref = (stats, states)
+            continue
+        for a, b in zip(stats, ref[0]):
+            for k in a:
+                assert a[k]["beta"] == b[k]["beta"] and a[k]["trials"] == b[k]["trials"]
+        for sa, sb in zip(states, ref[1]):
+            for x, y in zip(sa, sb):
+                assert np.array_equal(x, y), w
