@@ -126,6 +126,8 @@ typedef struct pgvimp_problem {
     const double *fk_base, *fk_link_len, *fk_sphere_frac;
     const int32_t *fk_axes, *fk_sphere_link;
     const double *mu_init; /* optional [N][n] initial mean; NULL -> prior mean */
+    int32_t segments;      /* chain segments for this plan (0 = context default) */
+    int32_t lanes_per_factor; /* expectation lanes per factor (0 = default)  */
 } pgvimp_problem;
 
 /*
@@ -139,7 +141,10 @@ typedef struct pgvimp_problem {
  * from that caller-owned buffer of arena_bytes bytes (which must outlive
  * the context); otherwise it allocates its own.  segments and
  * lanes_per_factor override the tuned launch shapes (0 = tuned default);
- * use_graph = 1 captures pgvimp_prox_step's iterations in a HIP graph.
+ * use_graph = 1 captures pgvimp_prox_step's iterations in a HIP graph sized
+ * to the plans present (re-captured when they change); use_graph = 2 sizes
+ * the graph to the full capacity so plans can join and leave without a new
+ * capture (serving).
  * trial_width (0 = 16, at most 64) is the number of step sizes of the
  * halving sequence evaluated concurrently per plan and iteration; it changes
  * speed and memory (the trial scratch scales with it), never results.

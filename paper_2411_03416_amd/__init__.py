@@ -20,7 +20,8 @@ __all__ = [
     "PgvimpError", "Context", "pgvimp_create", "pgvimp_destroy", "pgvimp_add_plan", "pgvimp_remove_plan",
     "pgvimp_marginals", "pgvimp_factor_expectations", "pgvimp_prox_step", "pgvimp_solve", "pgvimp_slr_linearize",
     "pgvimp_get_state", "pgvimp_set_state", "pgvimp_set_budget", "pgvimp_kernel_times", "pgvimp_profile",
-    "pgvimp_launch_shape", "pgvimp_arena_bytes", "problem_struct", "library_path",
+    "pgvimp_launch_shape", "pgvimp_arena_bytes", "problem_struct", "library_path", "ipgvimp_begin",
+    "ipgvimp_next_round",
 ]
 
 _KIND = {"none": COLL_NONE, "point2d": COLL_POINT2D, "point3d": COLL_POINT3D, "arm3d": COLL_ARM3D}
@@ -107,7 +108,35 @@ def problem_struct(prob, mu_init=None):
             s.fk_sphere_link = arr(fk["sphere_link"], np.int32).ctypes.data_as(C.POINTER(C.c_int32))
     if mu_init is not None:
         s.mu_init = _dptr(arr(np.asarray(mu_init).reshape(N, n)))
+    seg, lanes = _tuned_shape(prob)
+    s.segments = int(prob.get("segments", seg))
+    s.lanes_per_factor = int(prob.get("lanes_per_factor", lanes))
     return s, keep
+
+
+_TUNED = None
+
+
+def _tuned_shape(prob):
+    """Launch shape for a plan from the autotuner's table (tuned.json next
+    to this file), keyed by the plan's own state dimension, length and
+    quadrature class only; (0, 0) = library defaults."""
+    global _TUNED
+    if _TUNED is None:
+        import json
+        import os
+        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
+        _TUNED = json.load(open(path)) if os.path.exists(path) else {}
+    seg = 0
+    table = _TUNED.get("segments", {}).get(str(int(prob["n"])))
+    if table:
+        # entries [N, segments] sorted by N: take the nearest tuned length
+        N = int(prob["N"])
+        seg = min(table, key=lambda e: abs(e[0] - N))[1]
+    lanes = 0
+    key = f'{prob.get("coll_kind", "none")}/{int(prob.get("gh_points", 0))}'
+    lanes = int(_TUNED.get("lanes", {}).get(key, 0))
+    return seg, lanes
 
 
 class Context:
@@ -161,7 +190,8 @@ def pgvimp_create(problems, n=None, precision=FP64, max_plans=None, max_states=N
     cfg = _abi.EngineCfg()
     cfg.device, cfg.n, cfg.precision, cfg.max_plans = device, n, precision, max_plans
     cfg.max_states, cfg.heap_bytes = max_states, heap_bytes
-    cfg.segments, cfg.lanes_per_factor, cfg.use_graph = segments, lanes, 1 if use_graph else 0
+    cfg.segments, cfg.lanes_per_factor = segments, lanes
+    cfg.use_graph = int(use_graph) if not isinstance(use_graph, bool) else (1 if use_graph else 0)
     cfg.trial_width = trial_width
     arena = None
     tstream = None
@@ -255,6 +285,32 @@ def pgvimp_slr_linearize(ctx, plan, gravity=9.81, gh_points=3, rebuild_prior=Tru
     prm = np.array([gravity], dtype=np.float64)
     _check(_abi.load().pgvimp_slr_linearize(ctx.handle, plan, _abi.MODEL_QUAD2D, _dptr(prm), gh_points,
                                             1 if rebuild_prior else 0, A.ctypes.data, a.ctypes.data), ctx.handle)
+    return A, a
+
+
+def ipgvimp_begin(ctx, plan, prob):
+    """First round of Alg. 2 for a nonlinear plan: linearise the drift about
+    the nominal trajectory (mean prob['nominal_mean'], covariance
+    prob['nominal_cov'] per state), rebuild the prior, restart the precision
+    from the new K^-1 keeping the nominal mean, and give the plan its
+    iteration budget.  Returns (A_t, a_t)."""
+    N, n = ctx.plan_N[plan], ctx.n
+    cov = np.asarray(prob["nominal_cov"], dtype=np.float64).reshape(N, n, n)
+    prec = np.linalg.inv(cov)
+    pgvimp_set_state(ctx, plan, prob["nominal_mean"], prec, np.zeros((max(N - 1, 0), n, n)))
+    A, a = pgvimp_slr_linearize(ctx, plan, gravity=prob["quad"]["gravity"], gh_points=prob.get("slr_points", 3),
+                                rebuild_prior=True)
+    pgvimp_set_budget(ctx, plan, int(prob["n_iters"]))
+    return A, a
+
+
+def ipgvimp_next_round(ctx, plan, prob):
+    """Later rounds of Alg. 2: linearise about the plan's current marginals,
+    rebuild the prior (precision restarts from K^-1, mean kept) and reset the
+    iteration budget."""
+    A, a = pgvimp_slr_linearize(ctx, plan, gravity=prob["quad"]["gravity"], gh_points=prob.get("slr_points", 3),
+                                rebuild_prior=True)
+    pgvimp_set_budget(ctx, plan, int(prob["n_iters"]))
     return A, a
 
 

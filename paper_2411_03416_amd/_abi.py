@@ -43,6 +43,7 @@ class Problem(C.Structure):
         ("fk_base", _dp), ("fk_link_len", _dp), ("fk_sphere_frac", _dp),
         ("fk_axes", _ip), ("fk_sphere_link", _ip),
         ("mu_init", _dp),
+        ("segments", C.c_int32), ("lanes_per_factor", C.c_int32),
     ]
 
 

@@ -188,8 +188,8 @@ bool host_spd(const double* A, int n) {
 
 // Segments of the chain for a plan of N states: about sqrt(N), at most
 // N/2 (every segment keeps an interior state) and kMaxSeg.
-int choose_segments(const pgvimp_ctx* c, int N) {
-    int s = c->cfg.segments > 0 ? c->cfg.segments : (int)ceil(sqrt((double)N));
+int choose_segments(const pgvimp_ctx* c, int N, int requested = 0) {
+    int s = requested > 0 ? requested : c->cfg.segments > 0 ? c->cfg.segments : (int)ceil(sqrt((double)N));
     s = std::min(s, kMaxSeg);
     s = std::min(s, std::max(1, N / 2));
     return std::max(s, 1);
@@ -273,7 +273,9 @@ int validate_problem(pgvimp_ctx* c, const pgvimp_problem* p) {
     if (d == 0 || p->coll_dim != d || d > n) FAIL(c, PGVIMP_EINVAL, "collision kind/dim mismatch");
     for (int k = 0; k < d; ++k)
         if (p->coll_index[k] < 0 || p->coll_index[k] >= n) FAIL(c, PGVIMP_EINVAL, "coll_index out of range");
-    const int lanes = c->cfg.lanes_per_factor > 0 ? c->cfg.lanes_per_factor : default_lanes(p->coll_kind, d, p->gh_points);
+    const int lanes = p->lanes_per_factor > 0   ? p->lanes_per_factor
+                      : c->cfg.lanes_per_factor > 0 ? c->cfg.lanes_per_factor
+                                                    : default_lanes(p->coll_kind, d, p->gh_points);
     if (!expect_supported(p->coll_kind, d, p->gh_points, lanes))
         FAIL(c, PGVIMP_EINVAL, "unsupported quadrature shape kind=%d d=%d p=%d lanes=%d", p->coll_kind, d,
              p->gh_points, lanes);
@@ -421,6 +423,7 @@ int pgvimp_create(const pgvimp_problem* probs, int32_t n_probs, const pgvimp_eng
     if (!cfg) FAIL((pgvimp_ctx*)nullptr, PGVIMP_EINVAL, "null config");
     if (!chain_supported(cfg->n)) FAIL((pgvimp_ctx*)nullptr, PGVIMP_EINVAL, "state dim %d not supported", cfg->n);
     if (cfg->max_plans < 1 || cfg->max_states < 1 || cfg->heap_bytes < 0 || n_probs < 0 || n_probs > cfg->max_plans ||
+        cfg->use_graph < 0 || cfg->use_graph > 2 || cfg->trial_width < 0 ||
         (n_probs > 0 && !probs) || (cfg->precision != PGVIMP_FP64 && cfg->precision != PGVIMP_MIXED) ||
         cfg->segments < 0 || cfg->segments > kMaxSeg)
         FAIL((pgvimp_ctx*)nullptr, PGVIMP_EINVAL, "invalid engine configuration");
@@ -576,7 +579,7 @@ int pgvimp_add_plan(pgvimp_ctx* c, const pgvimp_problem* p, int32_t* plan_out) {
     pd.active = 1;
     pd.N = N;
     pd.off = (int32_t)soff;
-    pd.nseg = choose_segments(c, N);
+    pd.nseg = choose_segments(c, N, p->segments);
     pd.iters_left = p->n_iters;
     pd.n_iters = p->n_iters;
     pd.dt = p->dt;
@@ -627,9 +630,10 @@ int pgvimp_add_plan(pgvimp_ctx* c, const pgvimp_problem* p, int32_t* plan_out) {
     ph.p = p->gh_points;
     ph.dt = p->dt;
     ph.max_bisect = p->max_bisect;
-    ph.lanes = coll ? (c->cfg.lanes_per_factor > 0 ? c->cfg.lanes_per_factor
-                                                   : default_lanes(p->coll_kind, pd.d, p->gh_points))
-                    : 0;
+    ph.lanes = !coll                      ? 0
+               : p->lanes_per_factor > 0   ? p->lanes_per_factor
+               : c->cfg.lanes_per_factor > 0 ? c->cfg.lanes_per_factor
+                                             : default_lanes(p->coll_kind, pd.d, p->gh_points);
     // prior (Alg. 1) and initial state
     HCK(c, launch_prior_build(c->st, slot, slot + 1, N, c->stream));
     HCK(c, launch_prior_assemble(c->st, slot, slot + 1, N, c->stream));
@@ -823,7 +827,7 @@ static int run_iters(pgvimp_ctx* c, int32_t n_iters, pgvimp_stats* per_plan, boo
     if (!c || n_iters < 0) return PGVIMP_EINVAL;
     HCK(c, hipSetDevice(c->cfg.device));
     const std::vector<ClassKey> cls = live_classes(c);
-    const int64_t shw = c->states.high_water();
+    const int64_t shw = c->cfg.use_graph == 2 ? c->cfg.max_states : c->states.high_water();
     const int phw = plan_high_water(c);
     const bool timed = c->profile;
     int rc;

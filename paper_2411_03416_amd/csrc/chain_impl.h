@@ -405,59 +405,84 @@ PG_UNROLL
                 for (int c = 0; c < n; ++c) SnL[r * n + c] = cr[c * n + r];
         }
     }
+    // blocks of the forward sweep for the current state (c) and, loaded one
+    // step ahead, for the next state down the segment (n)
+    PG_MAT(Pc, ts);
+    PG_MAT(Gc, ts);
+    PG_MAT(Hc, ts);
+    PG_MAT(Pn, ts);
+    PG_MAT(Gn, ts);
+    PG_MAT(Hn, ts);
+    {
+        const double* w = ws + (off + b) * (int64_t)wsst;
+PG_UNROLL
+        for (int e = 0; e < n * n; ++e) Pc[e] = w[W::PINV + e];
+        if (hasR) {
+PG_UNROLL
+            for (int e = 0; e < n * n; ++e) Gc[e] = w[W::GU + e];
+        }
+        if (hasL) {
+PG_UNROLL
+            for (int e = 0; e < n * n; ++e) Hc[e] = w[W::HX + e];
+        }
+    }
     for (int i = b; i >= a; --i) {
         TS lt = ts;
-        const double* w = ws + (off + i) * (int64_t)wsst;
         const bool hasNext = (i < b) || hasR;
-        PG_MAT(Sii, lt);
+        if (i > a) {
+            const double* w = ws + (off + i - 1) * (int64_t)wsst;
+PG_UNROLL
+            for (int e = 0; e < n * n; ++e) Pn[e] = w[W::PINV + e];
+PG_UNROLL
+            for (int e = 0; e < n * n; ++e) Gn[e] = w[W::GU + e];
+            if (hasL) {
+PG_UNROLL
+                for (int e = 0; e < n * n; ++e) Hn[e] = w[W::HX + e];
+            }
+        }
+        // Pc becomes Sigma_ii in place
         PG_MAT(SiL, lt);
         PG_MAT(Sin, lt);
         PG_MAT(T, lt);
-PG_UNROLL
-        for (int e = 0; e < n * n; ++e) Sii[e] = w[W::PINV + e];
         if (hasNext) {
-            PG_MAT(GUi, lt);
-PG_UNROLL
-            for (int e = 0; e < n * n; ++e) GUi[e] = w[W::GU + e];
             // Cov(i, next) = -GU Snn - HX SnL^T
-            mmul<n>(GUi, Snn, Sin);
+            mmul<n>(Gc, Snn, Sin);
             if (hasL) {
-                PG_MAT(HXi, lt);
-PG_UNROLL
-                for (int e = 0; e < n * n; ++e) HXi[e] = w[W::HX + e];
-                mmul_nt<n>(HXi, SnL, T);
+                mmul_nt<n>(Hc, SnL, T);
 PG_UNROLL
                 for (int e = 0; e < n * n; ++e) Sin[e] += T[e];
                 // Cov(i, L) = -GU SnL - HX SLL
-                mmul<n>(GUi, SnL, SiL);
-                mmul<n>(HXi, SLL, T);
+                mmul<n>(Gc, SnL, SiL);
+                mmul<n>(Hc, SLL, T);
 PG_UNROLL
                 for (int e = 0; e < n * n; ++e) SiL[e] = -(SiL[e] + T[e]);
-                // Sii -= HX SiL^T  (sign: Sii = Pinv + G Sin^T + Hh SiL^T, G=-GU, Hh=-HX)
-                mmul_nt<n>(HXi, SiL, T);
+                // Sigma_ii = Pinv + G Sin^T + Hh SiL^T with G = -GU, Hh = -HX
+                mmul_nt<n>(Hc, SiL, T);
 PG_UNROLL
-                for (int e = 0; e < n * n; ++e) Sii[e] -= T[e];
+                for (int e = 0; e < n * n; ++e) Pc[e] -= T[e];
             }
 PG_UNROLL
             for (int e = 0; e < n * n; ++e) Sin[e] = -Sin[e];
-            mmul_nt<n>(GUi, Sin, T);
+            mmul_nt<n>(Gc, Sin, T);
 PG_UNROLL
-            for (int e = 0; e < n * n; ++e) Sii[e] -= T[e];
+            for (int e = 0; e < n * n; ++e) Pc[e] -= T[e];
             st_soa<n>(SUo, S, off + i, Sin);
         } else if (hasL) {
-            PG_MAT(HXi, lt);
-PG_UNROLL
-            for (int e = 0; e < n * n; ++e) HXi[e] = w[W::HX + e];
-            mmul<n>(HXi, SLL, SiL);
+            mmul<n>(Hc, SLL, SiL);
 PG_UNROLL
             for (int e = 0; e < n * n; ++e) SiL[e] = -SiL[e];
-            mmul_nt<n>(HXi, SiL, T);
+            mmul_nt<n>(Hc, SiL, T);
 PG_UNROLL
-            for (int e = 0; e < n * n; ++e) Sii[e] -= T[e];
+            for (int e = 0; e < n * n; ++e) Pc[e] -= T[e];
         }
-        st_soa_sym<n>(SDo, S, off + i, Sii);
-        mcopy<n>(Sii, Snn);
+        st_soa_sym<n>(SDo, S, off + i, Pc);
+        mcopy<n>(Pc, Snn);
         if (hasL) mcopy<n>(SiL, SnL);
+        if (i > a) {
+            mcopy<n>(Pn, Pc);
+            mcopy<n>(Gn, Gc);
+            if (hasL) mcopy<n>(Hn, Hc);
+        }
     }
     if (hasL) {
         // Cov(L, a) = Cov(a, L)^T

@@ -17,7 +17,7 @@ constexpr int kTrialThreads = 128; // trial kernel: marginals and mean solve sid
 constexpr int kMaxGH = 10;        // Gauss-Hermite points per dimension
 // n x n temporaries a chain-kernel thread may hold at once.  Deepest call
 // paths: kernel loop body 1 + prior cost 8 = 9; segment elimination 9 +
-// Cholesky inverse 2 = 11; segment backward sweep 3 + 6 = 9.
+// Cholesky inverse 2 = 11; segment backward sweep 9 + 3 = 12.
 constexpr int kTwsBlocks = 14;
 constexpr int kTwsVecs = 16;  // n-vector temporaries (deepest path: 8)
 
