@@ -41,7 +41,35 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
     ap.add_argument("--segments", type=int, default=0)
     ap.add_argument("--lanes", type=int, default=0)
+    ap.add_argument("--serve", action="store_true",
+                    help="run the serving mix (Poisson arrivals of configs 0-3) instead of the batch solve")
+    ap.add_argument("--qps", type=float, default=20.0)
+    ap.add_argument("--requests", type=int, default=60)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first copy 512 MiB device-to-device once (a kernel of known traffic for counters)")
     return ap.parse_args()
+
+
+def serve(args, pg):
+    """Serving mix: Poisson arrivals, each request a config 0-3 shape with
+    N ~ U{50..max}; continuous batching vs one plan at a time (FP64)."""
+    import workloads
+    from paper_2411_03416_amd.serve import ServingEngine
+    reqs = workloads.serving_mix(seed=0, count=args.requests, qps=args.qps, n_range=(50, args.N))
+    for _, p in reqs:
+        p["n_iters"] = min(p["n_iters"], args.iters)
+    out = {"metric": METRIC + " (serving mix)", "unit": "plans/s", "n_gpus": 1, "higher_is_better": True,
+           "data": "synthetic", "scaling": "weak", "vs_baseline": None,
+           "config": {"workload": f"serving mix: {args.requests} Poisson requests at {args.qps} QPS, configs 0-3, "
+                                  f"N ~ U{{50..{args.N}}}", "qps": args.qps}}
+    for name, prec, serial in (("mixed", pg.MIXED, False), ("fp64", pg.FP64, False), ("serial_fp64", pg.FP64, True)):
+        eng = ServingEngine(precision=prec, hbm_budget=24 << 30, max_plans=64, chunk=2, max_N=args.N, serial=serial)
+        m, _ = eng.run(reqs, timeout_s=240)
+        eng.close()
+        out[name] = m
+    out["value"] = out["mixed"]["plans_per_s"]
+    out["dtype"] = "fp32 quadrature + fp64"
+    print(json.dumps(out), flush=True)
 
 
 def make_batch(n_plans, N, iters):
@@ -134,6 +162,16 @@ def main():
               "(plans are independent and would shard by request, see the design notes)", file=sys.stderr)
         sys.exit(2)
     import paper_2411_03416_amd as pg
+    if args.calibrate_copy:
+        import torch
+        src = torch.ones(512 << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    if args.serve:
+        serve(args, pg)
+        return
 
     probs = make_batch(args.plans, args.N, args.iters)
     B, N, K = args.plans, args.N, args.iters

@@ -134,14 +134,15 @@ PG_UNROLL
 }
 
 // Inverse of an SPD matrix through its Cholesky factor A = L L^T:
-// Ainv = L^-T L^-1.  Adds log det A to *logdet.  Returns false (and leaves
-// Ainv unspecified) if a pivot is not positive or not finite.
+// Ainv = L^-T L^-1.  If logdet is not null, adds log det A (the log of the
+// product of the pivots, one logarithm per block).  Returns false (and
+// leaves Ainv unspecified) if a pivot is not positive or not finite.
 template <int n>
 __device__ __forceinline__ bool spd_inverse(const double* A, double* Ainv, double* logdet, TS ts) {
     PG_MAT(L, ts);
 PG_UNROLL
     for (int e = 0; e < n * n; ++e) L[e] = 0.0;
-    double ld = 0.0;
+    double det = 1.0;
     bool ok = true;
 PG_UNROLL
     for (int j = 0; j < n; ++j) {
@@ -152,7 +153,7 @@ PG_UNROLL
         d = ok ? d : 1.0;
         const double ljj = sqrt(d);
         const double inv = 1.0 / ljj;
-        ld += log(d);
+        det *= d;
         L[j * n + j] = ljj;
 PG_UNROLL
         for (int i = j + 1; i < n; ++i) {
@@ -189,7 +190,7 @@ PG_UNROLL
             Ainv[i * n + j] = s;
             Ainv[j * n + i] = s;
         }
-    *logdet += ld;
+    if (logdet) *logdet += log(det);
     return ok;
 }
 

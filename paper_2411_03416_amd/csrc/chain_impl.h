@@ -188,7 +188,7 @@ PG_UNROLL
             if (i + 1 < b || hasR) src_U<n>(M, off + i + 1, Un);
             if (RHS) src_r<n>(M, off + i + 1, rn);
         }
-        ok = spd_inverse<n>(P, Pinv, logdet, lt) && ok;
+        ok = spd_inverse<n>(P, Pinv, RHS ? nullptr : logdet, lt) && ok;
         double* w = ws + (off + i) * (int64_t)wsst;
 PG_UNROLL
         for (int e = 0; e < n * n; ++e) w[W::PINV + e] = Pinv[e];
@@ -274,39 +274,41 @@ __device__ __forceinline__ bool reduced_chain(const BlockSrc& M, int64_t off, in
     PG_MAT(Pinv, ts);
     PG_MAT(Ut, ts);
     PG_MAT(Gt, ts);
-    PG_VEC(y, ts); PG_VEC(z, ts);
+    PG_MAT(Dn, ts);  // next separator's assembled diagonal block, one step ahead
+    PG_MAT(Un, ts);  // next coupling block
+    PG_VEC(y, ts); PG_VEC(z, ts); PG_VEC(rn, ts);
+    // assembled diagonal block (and rhs) of separator j into Dd, rd
+    auto assemble = [&](int j, double* Dd, double* rd) {
+        const int s = sep_state(N, nseg, j);
+        const double* gj = sg + (int64_t)j * G::STRIDE;
+        const double* gn = sg + (int64_t)(j + 1) * G::STRIDE;
+        src_D<n>(M, off + s, Dd);
+PG_UNROLL
+        for (int e = 0; e < n * n; ++e) Dd[e] += gj[G::DR + e] + gn[G::DL + e];
+        if (RHS) {
+            src_r<n>(M, off + s, rd);
+PG_UNROLL
+            for (int e = 0; e < n; ++e) rd[e] += gj[G::RR + e] + gn[G::RL + e];
+        }
+    };
+    assemble(0, P, y);
+    if (nsep > 1) {
+        const double* g1 = sg + (int64_t)1 * G::STRIDE;
+PG_UNROLL
+        for (int e = 0; e < n * n; ++e) Ut[e] = g1[G::CLR + e];
+    }
     for (int j = 0; j < nsep; ++j) {
         TS lt = ts;
-        const int s = sep_state(N, nseg, j);
         double* gj = sg + (int64_t)j * G::STRIDE;
-        double* gn = sg + (int64_t)(j + 1) * G::STRIDE;
-        PG_MAT(D, lt);
-        src_D<n>(M, off + s, D);
+        if (j + 1 < nsep) {
+            assemble(j + 1, Dn, rn);
+            if (j + 2 < nsep) {
+                const double* g2 = sg + (int64_t)(j + 2) * G::STRIDE;
 PG_UNROLL
-        for (int e = 0; e < n * n; ++e) D[e] += gj[G::DR + e] + gn[G::DL + e];
-        PG_VEC(r, lt);
-        if (RHS) {
-            src_r<n>(M, off + s, r);
-PG_UNROLL
-            for (int e = 0; e < n; ++e) r[e] += gj[G::RR + e] + gn[G::RL + e];
-        }
-        if (j == 0) {
-            mcopy<n>(D, P);
-            if (RHS) {
-PG_UNROLL
-                for (int e = 0; e < n; ++e) y[e] = r[e];
-            }
-        } else {
-            // P = D - Ut^T Gt with Ut, Gt of the previous separator
-            mcopy<n>(D, P);
-            msub_tn<n>(Ut, Gt, P);
-            if (RHS) {
-PG_UNROLL
-                for (int e = 0; e < n; ++e) y[e] = r[e];
-                mvec_tn_sub<n>(Ut, z, y);
+                for (int e = 0; e < n * n; ++e) Un[e] = g2[G::CLR + e];
             }
         }
-        ok = spd_inverse<n>(P, Pinv, logdet, lt) && ok;
+        ok = spd_inverse<n>(P, Pinv, RHS ? nullptr : logdet, lt) && ok;
 PG_UNROLL
         for (int e = 0; e < n * n; ++e) gj[G::RPINV + e] = Pinv[e];
         if (RHS) {
@@ -314,13 +316,20 @@ PG_UNROLL
 PG_UNROLL
             for (int e = 0; e < n; ++e) gj[G::RZ + e] = z[e];
         }
-        if (j < nsep - 1) {
-            // coupling between separator j and j+1 lives in segment j+1
-PG_UNROLL
-            for (int e = 0; e < n * n; ++e) Ut[e] = gn[G::CLR + e];
+        if (j + 1 < nsep) {
+            // coupling between separator j and j+1 lives in segment j+1;
+            // next pivot P = D_{j+1} - Ut^T Pinv Ut, next rhs y = r_{j+1} - Ut^T z
             mmul<n>(Pinv, Ut, Gt);
 PG_UNROLL
             for (int e = 0; e < n * n; ++e) gj[G::RG + e] = Gt[e];
+            mcopy<n>(Dn, P);
+            msub_tn<n>(Ut, Gt, P);
+            if (RHS) {
+PG_UNROLL
+                for (int e = 0; e < n; ++e) y[e] = rn[e];
+                mvec_tn_sub<n>(Ut, z, y);
+            }
+            if (j + 2 < nsep) mcopy<n>(Un, Ut);
         }
     }
     if (!ok) return false;

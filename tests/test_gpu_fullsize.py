@@ -1,0 +1,94 @@
+"""Parity at the benchmark's full sizes, in the launch configuration bench.py
+times (one context, all plans, one graph per solve), on sampled outputs the
+oracle can compute one plan at a time.
+
+Tolerances come from the conditioning of the prior precision: at N = 750
+the marginals of K^-1 (cond ~3e10) carry ~1e-6 relative rounding in any
+FP64 implementation (see gpu_common.fp64_tol).
+"""
+import numpy as np
+import pytest
+
+import workloads
+from gpu_common import fp64_tol, rel
+from oracle import collision, gbp, prior, prox
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pg():
+    import paper_2411_03416_amd as m
+    return m
+
+
+def _kappa(pri):
+    return float(np.linalg.cond(prior.dense_from_blocks(pri["D"], pri["U"])))
+
+
+def test_config1_batch_first_iteration_sampled(pg):
+    probs = [workloads.config1_problem(seed=k) for k in range(32)]
+    for p in probs:
+        p["n_iters"] = 1
+    ctx = pg.pgvimp_create(probs, precision=pg.FP64, use_graph=True)
+    # expectations at the initial state for two sampled plans
+    for k in (0, 31):
+        p = probs[k]
+        pri = prior.build_prior(p)
+        Sr, Sor, ldr = gbp.gbp_marginals(pri["D"], pri["U"])
+        tol = fp64_tol(_kappa(pri))
+        S, So, ld = pg.pgvimp_marginals(ctx, k)
+        print("plan", k, "marginals", rel(S, Sr), rel(So, Sor), "tol", tol, flush=True)
+        assert rel(S, Sr) < tol and rel(So, Sor) < tol
+        assert abs(ld - ldr) < tol * abs(ldr)
+        E, g, H, _ = pg.pgvimp_factor_expectations(ctx, k)
+        idx = np.random.default_rng(k).choice(p["N"], size=40, replace=False)
+        for i in idx:
+            e, gi, Hi = collision.factor_expectation(p, pri["mu_bar"][i][:2], Sr[i][:2, :2])
+            scale = max(abs(e), 1e-300)
+            assert abs(E[i] - e) <= 10 * tol * scale + 1e-12, i
+            assert np.abs(g[i][:2] - gi).max() <= 10 * tol * max(np.abs(gi).max(), 1e-300) + 1e-9, i
+    # one full iteration in the benchmark's launch configuration
+    stats = pg.pgvimp_solve(ctx, 1)
+    for k in (0, 17):
+        p = probs[k]
+        pri = prior.build_prior(p)
+        st = prox.init_state(p, pri)
+        st1, so, _ = prox.prox_iteration(p, pri, st)
+        mu, D, U = pg.pgvimp_get_state(ctx, k)
+        tol = fp64_tol(_kappa(pri))
+        print("plan", k, "beta", stats[k]["beta"], so["beta"], "mu", rel(mu, st1["mu"]), "D", rel(D, st1["D"]),
+              "tol", tol, flush=True)
+        assert stats[k]["beta"] == so["beta"] and stats[k]["trials"] == so["trials"]
+        assert rel(mu, st1["mu"]) < 100 * tol and rel(D, st1["D"]) < 100 * tol
+
+
+def test_config2_arm_first_iteration(pg):
+    p = workloads.config2_problem(0)
+    p["n_iters"] = 1
+    ctx = pg.pgvimp_create([p], precision=pg.FP64, use_graph=True)
+    pg.pgvimp_solve(ctx, 1)
+    pri = prior.build_prior(p)
+    st = prox.init_state(p, pri)
+    st1, so, (E, g, H) = prox.prox_iteration(p, pri, st)
+    s = pg.pgvimp_prox_step(ctx, 0)[0]
+    mu, D, U = pg.pgvimp_get_state(ctx, 0)
+    tol = fp64_tol(_kappa(pri))
+    print("arm: beta", s["beta"], so["beta"], "mu", rel(mu, st1["mu"]), "D", rel(D, st1["D"]), "tol", tol)
+    assert s["beta"] == so["beta"]
+    assert rel(mu, st1["mu"]) < 100 * tol and rel(D, st1["D"]) < 100 * tol
+
+
+def test_config3_quadrotor_rounds(pg):
+    from oracle import slr
+    p = workloads.config3_problem(seed=3)
+    p["n_rounds"], p["n_iters"] = 2, 3
+    ctx = pg.pgvimp_create([p], use_graph=True)
+    pg.ipgvimp_begin(ctx, 0, p)
+    pg.pgvimp_prox_step(ctx, p["n_iters"])
+    pg.ipgvimp_next_round(ctx, 0, p)
+    pg.pgvimp_prox_step(ctx, p["n_iters"])
+    mu, D, U = pg.pgvimp_get_state(ctx, 0)
+    st, _ = slr.run_ipgvimp(p)
+    print("quadrotor N=%d: mu %.2e D %.2e" % (p["N"], rel(mu, st["mu"]), rel(D, st["D"])))
+    assert rel(mu, st["mu"]) < 1e-5 and rel(D, st["D"]) < 1e-5

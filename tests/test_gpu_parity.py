@@ -259,6 +259,28 @@ def test_prox_iteration_config0_fp64(pg):
         assert rel(D, st["D"]) < max((it + 1) * tol, 100 * dD_self), it
 
 
+def test_prox_iteration_mixed_precision(pg):
+    # mixed mode perturbs each collision expectation by ~1e-7 relative; the
+    # iterate must stay within the stated 1e-5 while the oracle perturbed at
+    # that scale keeps the same step decisions, and within 100x the oracle's
+    # own divergence under such a perturbation afterwards
+    p = workloads.config0_problem(0)
+    pri = prior.build_prior(p)
+    ref = _oracle_self_divergence(p, pri, 20, scale=1e-7)
+    ctx = pg.pgvimp_create([p], precision=pg.MIXED, use_graph=False)
+    for it, (st, so, dmu_self, dD_self, same) in enumerate(ref):
+        s = pg.pgvimp_prox_step(ctx, 1)[0]
+        mu, D, U = pg.pgvimp_get_state(ctx, 0)
+        e_mu, e_D = rel(mu, st["mu"]), rel(D, st["D"])
+        print(it, "mixed-oracle", e_mu, e_D, "oracle self (1e-7)", dmu_self, dD_self, flush=True)
+        if not same:
+            break
+        assert s["beta"] == so["beta"], it
+        assert e_mu < max(1e-5, 100 * dmu_self) and e_D < max(1e-5, 100 * dD_self), it
+        if it < 3:
+            assert e_mu < 1e-5 and e_D < 1e-5
+
+
 def test_obstacle_free_limit_is_closed_form_posterior(pg):
     T, beta = 1.7, 0.6
     p = workloads.free_problem(n_dof=2, N=20, temperature=T, beta_max=beta)
