@@ -193,29 +193,35 @@ def main():
         "status_ok": all(s == 0 for s in mixed["status"]),
     }
     kt = mixed["kt"]
-    if kt and kt["expect_launches"] and kt["chain_launches"]:
+    if kt and kt["expect"][1] and kt["trial"][1]:
         # expectation kernel: 88 B per factor of HBM traffic that the method
         # must move (marginal mean 2 + covariance 3 doubles in; E, g (2),
         # H (3) doubles out)
+        exp_ms = kt["expect"][0]
         exp_bytes = 88.0 * B * N
-        exp_gbs = exp_bytes / (kt["expect_ms"] * 1e-3) / 1e9
-        # chain kernel: FP64 flops of the plain block-tridiagonal algorithm per
-        # state and step-size trial (~10 n^3 for the marginals, ~5 n^3 for the
-        # mean solve) over the trials of the timed steps
-        chain_flops = 15.0 * n ** 3 * N * (mixed["trials"] / args.steps) / K
-        chain_tf = chain_flops / (kt["chain_ms"] * 1e-3) / 1e12
-        t_exp = kt["expect_ms"] * kt["expect_launches"]
-        t_chain = kt["chain_ms"] * kt["chain_launches"]
+        exp_gbs = exp_bytes / (exp_ms * 1e-3) / 1e9
+        # trial kernel: FP64 flops of the plain block-tridiagonal algorithm per
+        # state and step size the halving sequence tries (~10 n^3 for the
+        # marginals, ~5 n^3 for the mean solve); speculative trials beyond the
+        # accepted one are not counted
+        trial_ms, trial_launches = kt["trial"]
+        alg_flops = 15.0 * n ** 3 * N * mixed["trials"]  # over the timed steps
+        flops_per_launch = alg_flops / trial_launches
+        trial_tf = flops_per_launch / (trial_ms * 1e-3) / 1e12
+        totals = {k: v[0] * v[1] for k, v in kt.items() if isinstance(v, tuple)}
+        tot = sum(totals.values())
+        rtrial = {"kernel": "trial_kernel<4>", "bound": "alu", "achieved": trial_tf, "peak": FP64_PEAK_TFLOPS,
+                  "unit": "TFLOP/s", "frac": trial_tf / FP64_PEAK_TFLOPS, "traffic": None,
+                  "avg_ms": trial_ms, "flops_per_launch": flops_per_launch}
         rexp = {"kernel": "expect_kernel<float,2,5,32,point2d>", "bound": "hbm", "achieved": exp_gbs,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": exp_gbs / HBM_PEAK_GBS, "traffic": None,
-                "avg_ms": kt["expect_ms"], "bytes_per_launch": exp_bytes}
-        rchain = {"kernel": "chain_kernel<4>", "bound": "alu", "achieved": chain_tf, "peak": FP64_PEAK_TFLOPS,
-                  "unit": "TFLOP/s", "frac": chain_tf / FP64_PEAK_TFLOPS, "traffic": None,
-                  "avg_ms": kt["chain_ms"], "flops_per_launch": chain_flops}
-        dominant_is_chain = t_chain >= t_exp
-        out["roofline"] = rchain if dominant_is_chain else rexp
-        out["roofline_other"] = rexp if dominant_is_chain else rchain
-        out["kernel_share"] = {"expect": t_exp / (t_exp + t_chain), "chain": t_chain / (t_exp + t_chain)}
+                "avg_ms": exp_ms, "bytes_per_launch": exp_bytes}
+        dominant = max(totals, key=totals.get)
+        out["roofline"] = rtrial if dominant == "trial" else rexp
+        out["roofline_expect"] = rexp
+        out["kernel_share"] = {k: v / tot for k, v in totals.items()}
+        out["kernel_avg_ms"] = {k: v[0] for k, v in kt.items() if isinstance(v, tuple)}
+        out["eager_ms_per_step"] = kt["eager_ms_per_step"]
     if not args.no_fp64:
         f64 = timed_solve(pg, probs, pg.FP64, max(2, args.steps // 2), 1, K, args.segments, args.lanes,
                           profile=False)

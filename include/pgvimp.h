@@ -274,17 +274,25 @@ int pgvimp_sync(pgvimp_ctx *ctx);
  */
 int pgvimp_launch_shape(pgvimp_ctx *ctx, int32_t N, int32_t *segments, int32_t *lanes);
 
+/* kernel kinds reported by pgvimp_kernel_times */
+#define PGVIMP_K_EXPECT 0  /* collision-factor expectations                */
+#define PGVIMP_K_PREP 1    /* per-iteration set-up (K^-1 + H, rhs, costs)  */
+#define PGVIMP_K_TRIAL 2   /* a window of trial step sizes (GBP + solve)   */
+#define PGVIMP_K_SELECT 3  /* pick the first passing step, write back      */
+#define PGVIMP_K_RESTART 4 /* prior build + initial state (pgvimp_solve)   */
+#define PGVIMP_NKERNELS 5
+
 /*
- * Mean duration in milliseconds of the expectation kernel and of the chain
- * (step-size/update/GBP) kernel over the launches timed since the last call
- * with reset = 1, measured with HIP events on the context's stream when
- * pgvimp_profile(ctx, 1) enabled timing; counts in *n_expect, *n_chain.
- * While timing is enabled pgvimp_prox_step and pgvimp_solve launch their
- * kernels directly (not through a HIP graph) with events around each one.
+ * Kernel timing.  pgvimp_profile(ctx, 1) makes pgvimp_prox_step and
+ * pgvimp_solve launch their kernels directly (not through a HIP graph: events
+ * recorded inside a captured graph cannot be timed) with a HIP event pair on
+ * the context's stream around every launch.  pgvimp_kernel_times fills
+ * mean_ms[PGVIMP_NKERNELS] (mean duration per launch, milliseconds) and
+ * launches[PGVIMP_NKERNELS] over the launches timed since the last call with
+ * reset = 1; either pointer may be NULL.
  */
 int pgvimp_profile(pgvimp_ctx *ctx, int32_t enable);
-int pgvimp_kernel_times(pgvimp_ctx *ctx, int32_t reset, double *ms_expect, int64_t *n_expect,
-                        double *ms_chain, int64_t *n_chain);
+int pgvimp_kernel_times(pgvimp_ctx *ctx, int32_t reset, double *mean_ms, int64_t *launches);
 
 /* Bytes of device memory held by the context. */
 int64_t pgvimp_device_bytes(const pgvimp_ctx *ctx);

@@ -66,9 +66,10 @@ def linearised_problem(prob, A_t, a_t):
     return q
 
 
-def run_ipgvimp(prob, n_rounds=None, n_iters=None):
+def run_ipgvimp(prob, n_rounds=None, n_iters=None, history=False):
     """Alg. 2: alternate SLR and P-GVIMP; returns the final state and the
-    list of (A_t, a_t) per round."""
+    list of (A_t, a_t) per round (with history=True, (A_t, a_t, state after
+    the round's iterations) per round)."""
     f = lambda x: quadrotor_drift(x, prob["quad"])  # noqa: E731
     mu = np.array(prob["nominal_mean"], dtype=np.float64)
     Sig = np.array(prob["nominal_cov"], dtype=np.float64)
@@ -81,6 +82,6 @@ def run_ipgvimp(prob, n_rounds=None, n_iters=None):
         q = linearised_problem(prob, A_t, a_t)
         pri = prior_mod.build_prior(q)
         st = prox.run(q, n_iters=n_iters, pri=pri, mu0=mu)
-        rounds.append((A_t, a_t))
+        rounds.append((A_t, a_t, st) if history else (A_t, a_t))
         mu, Sig = st["mu"], st["Sig"]
     return st, rounds

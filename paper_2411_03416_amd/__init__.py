@@ -339,11 +339,12 @@ def pgvimp_profile(ctx, enable=True):
 
 
 def pgvimp_kernel_times(ctx, reset=True):
-    me, mc = C.c_double(), C.c_double()
-    ne, nc = C.c_int64(), C.c_int64()
-    _check(_abi.load().pgvimp_kernel_times(ctx.handle, 1 if reset else 0, C.byref(me), C.byref(ne),
-                                           C.byref(mc), C.byref(nc)), ctx.handle)
-    return {"expect_ms": me.value, "expect_launches": ne.value, "chain_ms": mc.value, "chain_launches": nc.value}
+    """{kind: (mean_ms, launches)} for kinds expect, prep, trial, select, restart."""
+    k = len(_abi.KERNEL_KINDS)
+    ms = (C.c_double * k)()
+    cnt = (C.c_int64 * k)()
+    _check(_abi.load().pgvimp_kernel_times(ctx.handle, 1 if reset else 0, ms, cnt), ctx.handle)
+    return {name: (ms[i], cnt[i]) for i, name in enumerate(_abi.KERNEL_KINDS)}
 
 
 def pgvimp_launch_shape(ctx, N):

@@ -16,6 +16,7 @@ FP64, MIXED = 0, 1
 COLL_NONE, COLL_POINT2D, COLL_POINT3D, COLL_ARM3D = 0, 1, 2, 3
 MODEL_QUAD2D = 1
 MAX_COLL_DIM, MAX_SPHERES, ARM_DOF = 8, 32, 7
+KERNEL_KINDS = ("expect", "prep", "trial", "select", "restart")
 
 _dp = C.POINTER(C.c_double)
 _fp = C.POINTER(C.c_float)
@@ -88,8 +89,7 @@ SIGNATURES = [
     ("pgvimp_sync", C.c_int, [C.c_void_p]),
     ("pgvimp_launch_shape", C.c_int, [C.c_void_p, C.c_int32, _ip, _ip]),
     ("pgvimp_profile", C.c_int, [C.c_void_p, C.c_int32]),
-    ("pgvimp_kernel_times", C.c_int, [C.c_void_p, C.c_int32, _dp, C.POINTER(C.c_int64), _dp,
-                                      C.POINTER(C.c_int64)]),
+    ("pgvimp_kernel_times", C.c_int, [C.c_void_p, C.c_int32, _dp, C.POINTER(C.c_int64)]),
     ("pgvimp_device_bytes", C.c_int64, [C.c_void_p]),
     ("pgvimp_arena_bytes", C.c_int64, [C.POINTER(EngineCfg)]),
     ("pgvimp_last_error", C.c_char_p, [C.c_void_p]),

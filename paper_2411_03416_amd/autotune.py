@@ -44,14 +44,12 @@ def _time_expect(pg, probs, iters, lanes):
     pg.pgvimp_solve(ctx, iters)
     kt = pg.pgvimp_kernel_times(ctx, reset=True)
     pg.pgvimp_destroy(ctx)
-    return kt["expect_ms"]
+    return kt["expect"][0]
 
 
 def tune(quick=False):
     import paper_2411_03416_amd as pg
     import workloads
-    for p in ("segments", "lanes_per_factor"):
-        pass
     out = {"segments": {}, "lanes": {}, "device": None}
     import torch
     out["device"] = torch.cuda.get_device_name(0)

@@ -69,9 +69,10 @@ struct pgvimp_ctx {
     // profiling
     bool profile = false;
     std::vector<hipEvent_t> ev;  // pairs per timed launch
-    std::vector<int> ev_kind;    // 0 = expect, 1 = chain
-    double t_exp = 0.0, t_chain = 0.0;
-    int64_t n_exp = 0, n_chain = 0;
+    std::vector<int> ev_kind;    // PGVIMP_K_* of each pair
+    double t_kind[PGVIMP_NKERNELS] = {};
+    int64_t n_kind[PGVIMP_NKERNELS] = {};
+    size_t ev_used = 0;
     std::string err;
 };
 
@@ -755,61 +756,66 @@ static int trial_rounds(pgvimp_ctx* c) {
 static int enqueue_iters(pgvimp_ctx* c, int n_iters, const std::vector<ClassKey>& cls, int64_t shw, int phw,
                          bool timed, bool restart) {
     const int rounds = trial_rounds(c);
+    c->ev_used = 0;
+    // record an event pair around each launch when timing (kind = PGVIMP_K_*)
+    auto begin = [&](int kind) -> int {
+        if (!timed) return PGVIMP_OK;
+        while (c->ev.size() < c->ev_used + 2) {
+            hipEvent_t e;
+            HCK(c, hipEventCreate(&e));
+            c->ev.push_back(e);
+            c->ev_kind.push_back(0);
+        }
+        c->ev_kind[c->ev_used] = kind;
+        HCK(c, hipEventRecord(c->ev[c->ev_used], c->stream));
+        return PGVIMP_OK;
+    };
+    auto end = [&]() -> int {
+        if (!timed) return PGVIMP_OK;
+        HCK(c, hipEventRecord(c->ev[c->ev_used + 1], c->stream));
+        c->ev_used += 2;
+        return PGVIMP_OK;
+    };
+    int rc;
     if (restart) {
         // every live plan: prior from its stored dynamics, mu_0 = prior mean,
         // Lambda_0 = K^-1, marginals, budget reset (Alg. 1 set-up)
         const int maxN = max_live_N(c);
+        if ((rc = begin(PGVIMP_K_RESTART))) return rc;
         HCK(c, launch_prior_build(c->st, 0, phw, maxN, c->stream));
         HCK(c, launch_prior_assemble(c->st, 0, phw, maxN, c->stream));
         HCK(c, launch_chain(c->st, CHAIN_INIT, 0, phw, c->stream));
+        if ((rc = end())) return rc;
     }
-    size_t evi = 0;
-    auto ev_pair = [&](int kind) -> std::pair<hipEvent_t, hipEvent_t> {
-        while (c->ev.size() < evi + 2) {
-            hipEvent_t e;
-            if (hipEventCreate(&e) != hipSuccess) return {nullptr, nullptr};
-            c->ev.push_back(e);
-            c->ev_kind.push_back(0);
-        }
-        c->ev_kind[evi] = kind;
-        auto pr = std::make_pair(c->ev[evi], c->ev[evi + 1]);
-        evi += 2;
-        return pr;
-    };
     for (int it = 0; it < n_iters; ++it) {
         for (auto& k : cls) {
-            std::pair<hipEvent_t, hipEvent_t> e{nullptr, nullptr};
-            if (timed) {
-                e = ev_pair(0);
-                HCK(c, hipEventRecord(e.first, c->stream));
-            }
+            if ((rc = begin(PGVIMP_K_EXPECT))) return rc;
             HCK(c, launch_expect(c->st, k.kind, k.d, k.p, c->cfg.precision, k.lanes, 0, shw, 1, c->stream));
-            if (timed) HCK(c, hipEventRecord(e.second, c->stream));
+            if ((rc = end())) return rc;
         }
-        std::pair<hipEvent_t, hipEvent_t> e{nullptr, nullptr};
-        if (timed) {
-            e = ev_pair(1);
-            HCK(c, hipEventRecord(e.first, c->stream));
+        if ((rc = begin(PGVIMP_K_PREP))) return rc;
+        HCK(c, launch_iteration(c->st, phw, 0, 0, c->stream));
+        if ((rc = end())) return rc;
+        for (int r = 0; r < rounds; ++r) {
+            if ((rc = begin(PGVIMP_K_TRIAL))) return rc;
+            HCK(c, launch_iteration(c->st, phw, 1, r, c->stream));
+            if ((rc = end())) return rc;
+            if ((rc = begin(PGVIMP_K_SELECT))) return rc;
+            HCK(c, launch_iteration(c->st, phw, 2, r, c->stream));
+            if ((rc = end())) return rc;
         }
-        HCK(c, launch_iteration(c->st, phw, rounds, c->stream));
-        if (timed) HCK(c, hipEventRecord(e.second, c->stream));
     }
     return PGVIMP_OK;
 }
 
-static int collect_times(pgvimp_ctx* c, size_t pairs) {
-    for (size_t k = 0; k < pairs && 2 * k + 1 < c->ev.size(); ++k) {
-        const size_t i = 2 * k;
+static int collect_times(pgvimp_ctx* c) {
+    for (size_t i = 0; i + 1 < c->ev_used; i += 2) {
         float ms = 0.f;
         HCK(c, hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]));
-        if (c->ev_kind[i] == 0) {
-            c->t_exp += ms;
-            c->n_exp++;
-        } else {
-            c->t_chain += ms;
-            c->n_chain++;
-        }
+        c->t_kind[c->ev_kind[i]] += ms;
+        c->n_kind[c->ev_kind[i]] += 1;
     }
+    c->ev_used = 0;
     return PGVIMP_OK;
 }
 
@@ -863,8 +869,8 @@ static int run_iters(pgvimp_ctx* c, int32_t n_iters, pgvimp_stats* per_plan, boo
         }
     }
     HCK(c, hipStreamSynchronize(c->stream));
-    if (timed && n_iters > 0 && phw > 0) {
-        rc = collect_times(c, (size_t)n_iters * (cls.size() + 1));
+    if (timed && phw > 0) {
+        rc = collect_times(c);
         if (rc) return rc;
     }
     rc = download_plans(c);
@@ -1004,16 +1010,15 @@ int pgvimp_profile(pgvimp_ctx* c, int32_t enable) {
     return PGVIMP_OK;
 }
 
-int pgvimp_kernel_times(pgvimp_ctx* c, int32_t reset, double* ms_expect, int64_t* n_expect, double* ms_chain,
-                        int64_t* n_chain) {
+int pgvimp_kernel_times(pgvimp_ctx* c, int32_t reset, double* mean_ms, int64_t* launches) {
     if (!c) return PGVIMP_EINVAL;
-    if (ms_expect) *ms_expect = c->n_exp ? c->t_exp / c->n_exp : 0.0;
-    if (n_expect) *n_expect = c->n_exp;
-    if (ms_chain) *ms_chain = c->n_chain ? c->t_chain / c->n_chain : 0.0;
-    if (n_chain) *n_chain = c->n_chain;
-    if (reset) {
-        c->t_exp = c->t_chain = 0.0;
-        c->n_exp = c->n_chain = 0;
+    for (int k = 0; k < PGVIMP_NKERNELS; ++k) {
+        if (mean_ms) mean_ms[k] = c->n_kind[k] ? c->t_kind[k] / c->n_kind[k] : 0.0;
+        if (launches) launches[k] = c->n_kind[k];
+        if (reset) {
+            c->t_kind[k] = 0.0;
+            c->n_kind[k] = 0;
+        }
     }
     return PGVIMP_OK;
 }

@@ -9,7 +9,7 @@ hipError_t launch_chain_n(const DevState& st, int mode, int lo, int hi, hipStrea
 template <int n>
 hipError_t launch_prior_costs_n(const DevState& st, int plan, int N, hipStream_t s);
 template <int n>
-hipError_t launch_iteration_n(const DevState& st, int phw, int rounds, hipStream_t s);
+hipError_t launch_iteration_n(const DevState& st, int phw, int part, int round, hipStream_t s);
 
 bool chain_supported(int n) { return n == 2 || n == 4 || n == 6 || n == 8 || n == 14; }
 
@@ -24,13 +24,13 @@ hipError_t launch_chain(const DevState& st, int mode, int lo, int hi, hipStream_
     }
 }
 
-hipError_t launch_iteration(const DevState& st, int phw, int rounds, hipStream_t s) {
+hipError_t launch_iteration(const DevState& st, int phw, int part, int round, hipStream_t s) {
     switch (st.n) {
-        case 2: return launch_iteration_n<2>(st, phw, rounds, s);
-        case 4: return launch_iteration_n<4>(st, phw, rounds, s);
-        case 6: return launch_iteration_n<6>(st, phw, rounds, s);
-        case 8: return launch_iteration_n<8>(st, phw, rounds, s);
-        case 14: return launch_iteration_n<14>(st, phw, rounds, s);
+        case 2: return launch_iteration_n<2>(st, phw, part, round, s);
+        case 4: return launch_iteration_n<4>(st, phw, part, round, s);
+        case 6: return launch_iteration_n<6>(st, phw, part, round, s);
+        case 8: return launch_iteration_n<8>(st, phw, part, round, s);
+        case 14: return launch_iteration_n<14>(st, phw, part, round, s);
         default: return hipErrorInvalidValue;
     }
 }

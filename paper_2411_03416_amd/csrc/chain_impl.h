@@ -1025,14 +1025,13 @@ hipError_t launch_chain_n(const DevState& st, int mode, int lo, int hi, hipStrea
     return hipGetLastError();
 }
 
+// part: 0 = prep, 1 = trial window `round`, 2 = select for window `round`
 template <int n>
-hipError_t launch_iteration_n(const DevState& st, int phw, int rounds, hipStream_t s) {
+hipError_t launch_iteration_n(const DevState& st, int phw, int part, int round, hipStream_t s) {
     if (phw <= 0) return hipSuccess;
-    hipLaunchKernelGGL(prep_kernel<n>, dim3(phw), dim3(kChainThreads), 0, s, st);
-    for (int r = 0; r < rounds; ++r) {
-        hipLaunchKernelGGL(trial_kernel<n>, dim3(phw, st.W), dim3(kTrialThreads), 0, s, st, r);
-        hipLaunchKernelGGL(select_kernel<n>, dim3(phw), dim3(kChainThreads), 0, s, st, r);
-    }
+    if (part == 0) hipLaunchKernelGGL(prep_kernel<n>, dim3(phw), dim3(kChainThreads), 0, s, st);
+    if (part == 1) hipLaunchKernelGGL(trial_kernel<n>, dim3(phw, st.W), dim3(kTrialThreads), 0, s, st, round);
+    if (part == 2) hipLaunchKernelGGL(select_kernel<n>, dim3(phw), dim3(kChainThreads), 0, s, st, round);
     return hipGetLastError();
 }
 

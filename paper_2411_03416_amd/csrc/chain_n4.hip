@@ -4,5 +4,5 @@
 namespace pg {
 template hipError_t launch_chain_n<4>(const DevState&, int, int, int, hipStream_t);
 template hipError_t launch_prior_costs_n<4>(const DevState&, int, int, hipStream_t);
-template hipError_t launch_iteration_n<4>(const DevState&, int, int, hipStream_t);
+template hipError_t launch_iteration_n<4>(const DevState&, int, int, int, hipStream_t);
 }  // namespace pg

@@ -154,8 +154,9 @@ namespace pg {
 hipError_t launch_prior_build(const DevState& st, int plan_lo, int plan_hi, int maxN, hipStream_t s);
 hipError_t launch_prior_assemble(const DevState& st, int plan_lo, int plan_hi, int maxN, hipStream_t s);
 hipError_t launch_chain(const DevState& st, int mode, int plan_lo, int plan_hi, hipStream_t s);
-// one proximal iteration for plans [0, phw): prep, then rounds x (trials, select)
-hipError_t launch_iteration(const DevState& st, int phw, int rounds, hipStream_t s);
+// parts of one proximal iteration for plans [0, phw): 0 = prep, 1 = trial
+// window `round`, 2 = select for window `round`
+hipError_t launch_iteration(const DevState& st, int phw, int part, int round, hipStream_t s);
 hipError_t launch_expect(const DevState& st, int coll_kind, int d, int p, int precision, int lanes,
                          int64_t s_lo, int64_t s_hi, int respect_budget, hipStream_t s);
 hipError_t launch_prior_costs(const DevState& st, int plan, int N, hipStream_t s);

@@ -300,13 +300,23 @@ def config2_problem(seed=0):
 
 
 def quadrotor_problem(seed, N=None, gh_points=3, slr_points=3, n_rounds=10,
-                      n_iters=15, qc=0.8, hinge_eps=0.5, sigma_obs=0.01):
+                      n_iters=15, qc=0.8, hinge_eps=0.5, sigma_obs=0.01, span=None,
+                      diffusion=0.01):
     """Nonlinear planar quadrotor (x, z, phi, vx, vz, phidot) over a 10x10 m
-    map of 6 seeded discs.  N ~ U{100..300} unless given.  The LTI fields
-    (A, a) hold the model's hover linearisation (phi = 0, zero velocity:
-    xdot = vx, zdot = vz, vxdot = -g phi, vzdot = -g) until the first
-    statistical linearisation replaces them; the nominal trajectory is the
-    straight line with covariance 1e-2 I."""
+    map of 6 seeded discs.  N ~ U{100..300} unless given, over a time span
+    T ~ U[4, 6] s (Sec. 7.3's range) unless given, so dt = T / (N - 1).  The
+    LTI fields (A, a) hold the model's hover linearisation (phi = 0, zero
+    velocity: xdot = vx, zdot = vz, vxdot = -g phi, vzdot = -g) until the
+    first statistical linearisation replaces them; the nominal trajectory is
+    the straight line with covariance 1e-2 I.
+
+    Noise: the thrusts' white noise (Qc = qc I through the input matrix of
+    eq. planar_quad) plus an isotropic diffusion floor diffusion^2 I on every
+    state, handed over as the square factor B = chol(B_u Qc B_u^T +
+    diffusion^2 I) with Qc = I.  Through the rank-2 input matrix alone the
+    position is a fourfold integral of the noise and cond(K^-1) grows like
+    2 N^7 (numerically singular in FP64 from N ~ 100); the floor bounds it
+    near 1e9 at N = 300.  diffusion=0 gives the plain rank-2 model."""
     rng = _rng(seed)
     if N is None:
         N = int(rng.integers(100, 301))
@@ -323,14 +333,20 @@ def quadrotor_problem(seed, N=None, gh_points=3, slr_points=3, n_rounds=10,
     while np.linalg.norm(s - g) < 4.0:
         g = free_point()
     params = quadrotor_params(rng)
-    B = quadrotor_B(params)
+    T = float(rng.uniform(4.0, 6.0)) if span is None else float(span)
+    B_u = quadrotor_B(params)
+    if diffusion > 0.0:
+        B = np.linalg.cholesky(qc * B_u @ B_u.T + diffusion ** 2 * np.eye(6))
+        Qc = np.eye(6)
+    else:
+        B, Qc = B_u, qc * np.eye(2)
     mu_s = np.array([s[0], s[1], 0.0, 0.0, 0.0, 0.0])
     mu_g = np.array([g[0], g[1], 0.0, 0.0, 0.0, 0.0])
     A_hover = np.zeros((6, 6))
     A_hover[0, 3] = A_hover[1, 4] = A_hover[2, 5] = 1.0
     A_hover[3, 2] = -params["gravity"]
     a_hover = np.array([0.0, 0.0, 0.0, 0.0, -params["gravity"], 0.0])
-    p = _base(6, 2, N, 0.1, A_hover, a_hover, B, qc * np.eye(2), mu_s, mu_g)
+    p = _base(6, B.shape[1], N, T / max(N - 1, 1), A_hover, a_hover, B, Qc, mu_s, mu_g)
     ts = np.linspace(0.0, 1.0, N)[:, None]
     nominal = (1.0 - ts) * mu_s[None, :] + ts * mu_g[None, :]
     p.update({
