@@ -269,8 +269,9 @@ int pgvimp_set_stream(pgvimp_ctx *ctx, void *stream);
 int pgvimp_sync(pgvimp_ctx *ctx);
 
 /*
- * Launch shapes in use: *segments = chain segments for a plan of N states,
- * *lanes = lanes per factor of the expectation kernel for this context.
+ * Launch shapes in use: *segments = chain segments of the first live plan of
+ * N states (the context default for N if there is none), *lanes = lanes
+ * per factor of the expectation kernel for this context.
  */
 int pgvimp_launch_shape(pgvimp_ctx *ctx, int32_t N, int32_t *segments, int32_t *lanes);
 

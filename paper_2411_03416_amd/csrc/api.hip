@@ -331,7 +331,7 @@ static int64_t carve(pgvimp_ctx* c, const pgvimp_engine_cfg* cfg, DevState& st, 
     const int64_t S = cfg->max_states, P = cfg->max_plans;
     const int dmax = std::min(n, PGVIMP_MAX_COLL_DIM);
     const int ws_stride = 3 * n * n + n;
-    const int seg_stride = 6 * n * n + 4 * n;
+    const int seg_stride = 7 * n * n + 5 * n;  // SegLayout<n>::STRIDE
     int64_t off = 0;
     auto take = [&](auto** ptr, int64_t bytes) {
         if (base) *ptr = (std::remove_reference_t<decltype(**ptr)>*)(base + off);
@@ -348,6 +348,7 @@ static int64_t carve(pgvimp_ctx* c, const pgvimp_engine_cfg* cfg, DevState& st, 
     take(&st.TSU, W * S * n * n * 8);
     take(&st.Tmu, W * S * n * 8);
     take(&st.tres, P * W * 4 * 8);
+    take(&st.psum, P * kIterBlocks * 2 * 8);
     take(&st.Ecol, S * 8);
     take(&st.gcol, S * dmax * 8);
     take(&st.Hcol, S * dmax * dmax * 8);
@@ -372,6 +373,7 @@ static int64_t carve(pgvimp_ctx* c, const pgvimp_engine_cfg* cfg, DevState& st, 
     st.seg_stride = seg_stride;
     st.tws_stride = tws_stride;
     st.W = (int32_t)W;
+    st.iter_blocks = (int32_t)std::min<int64_t>(kIterBlocks, W);
     return off;
 }
 
@@ -992,7 +994,15 @@ int pgvimp_slr_linearize(pgvimp_ctx* c, int32_t plan, int32_t model, const doubl
 
 int pgvimp_launch_shape(pgvimp_ctx* c, int32_t N, int32_t* segments, int32_t* lanes) {
     if (!c || N < 1) return PGVIMP_EINVAL;
-    if (segments) *segments = choose_segments(c, N);
+    if (segments) {
+        // the segments of the first live plan of N states, else the default
+        *segments = choose_segments(c, N);
+        for (size_t i = 0; i < c->plans.size(); ++i)
+            if (c->plans[i].active && c->plans[i].N == N) {
+                *segments = c->pdev[i].nseg;
+                break;
+            }
+    }
     if (lanes) {
         *lanes = c->cfg.lanes_per_factor;
         for (auto& ph : c->plans)

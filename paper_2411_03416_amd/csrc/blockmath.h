@@ -109,6 +109,46 @@ PG_UNROLL
         }
 }
 
+// C -= A B
+template <int n>
+__device__ __forceinline__ void msub(const double* A, const double* B, double* C) {
+PG_UNROLL
+    for (int i = 0; i < n; ++i)
+PG_UNROLL
+        for (int j = 0; j < n; ++j) {
+            double s = C[i * n + j];
+PG_UNROLL
+            for (int k = 0; k < n; ++k) s = fma(-A[i * n + k], B[k * n + j], s);
+            C[i * n + j] = s;
+        }
+}
+
+// C -= A B^T
+template <int n>
+__device__ __forceinline__ void msub_nt(const double* A, const double* B, double* C) {
+PG_UNROLL
+    for (int i = 0; i < n; ++i)
+PG_UNROLL
+        for (int j = 0; j < n; ++j) {
+            double s = C[i * n + j];
+PG_UNROLL
+            for (int k = 0; k < n; ++k) s = fma(-A[i * n + k], B[j * n + k], s);
+            C[i * n + j] = s;
+        }
+}
+
+// y -= A x
+template <int n>
+__device__ __forceinline__ void mvec_sub(const double* A, const double* x, double* y) {
+PG_UNROLL
+    for (int i = 0; i < n; ++i) {
+        double s = y[i];
+PG_UNROLL
+        for (int k = 0; k < n; ++k) s = fma(-A[i * n + k], x[k], s);
+        y[i] = s;
+    }
+}
+
 // y = A x
 template <int n>
 __device__ __forceinline__ void mvec(const double* A, const double* x, double* y) {

@@ -9,14 +9,17 @@
 // the last state of each segment but the last is a separator.  Each lane
 // eliminates the interior states of its segment (a forward sweep that
 // carries the fill towards the segment's left separator), producing the
-// Schur-complement contribution of the segment to its two separators.  Lane
-// 0 solves the reduced chain of separators sequentially (forward
-// elimination, backward selected inversion).  Each lane then recovers its
-// interior marginals by a backward sweep conditioned on the separators'
-// joint covariance.  Depth: N/nseg + 2 nseg + N/nseg dependent block steps
-// instead of 2N.  log det Lambda is the sum of the log determinants of all
-// pivots (interior Schur complements and reduced-chain pivots), and Lambda
-// is positive definite iff every pivot is.
+// Schur-complement contribution of the segment to its two separators.  The
+// reduced chain of the m = nseg - 1 separators is then factored by block
+// cyclic reduction across the lanes: lane j owns separator j, which is
+// eliminated at level ctz(j + 1) with neighbours j -/+ 2^level, so the
+// reduced chain takes floor(log2 m) + 1 levels forward and as many back.
+// Each lane finally recovers its interior marginals by a backward sweep
+// conditioned on the joint covariance of its two separators.  Depth:
+// 2 N / nseg block steps plus about 2 log2(nseg) levels, instead of 2 N.
+// log det Lambda is the sum of the log determinants of all pivots
+// (interior Schur complements and reduced-chain pivots), and Lambda is
+// positive definite iff every pivot is.
 //
 // The same elimination with a right-hand side solves
 // (K^-1 + Lambda_k / beta) mu' = eta - g + Lambda_k mu_k / beta.
@@ -35,19 +38,26 @@
 namespace pg {
 
 // Entry offsets in the per-segment scratch (stride DevState::seg_stride).
+// Slot j holds segment j's contributions to its separators and, for the
+// reduced chain, the data of separator j (node j).
 template <int n>
 struct SegLayout {
-    static constexpr int DL = 0;             // Schur contribution to left separator
-    static constexpr int DR = n * n;         // ... to right separator
-    static constexpr int CLR = 2 * n * n;    // coupling block (left sep, right sep)
-    static constexpr int CROSS = 3 * n * n;  // Cov(left sep, right sep)
-    static constexpr int RPINV = 4 * n * n;  // reduced-chain pivot inverse (right sep)
-    static constexpr int RG = 5 * n * n;     // reduced-chain pivot^-1 * coupling
-    static constexpr int RL = 6 * n * n;     // rhs contribution to left separator
-    static constexpr int RR = 6 * n * n + n;
-    static constexpr int RZ = 6 * n * n + 2 * n;  // reduced-chain pivot^-1 * rhs
-    static constexpr int XS = 6 * n * n + 3 * n;  // solution at right separator
-    static constexpr int STRIDE = 6 * n * n + 4 * n;
+    static constexpr int DL = 0;              // Schur contribution to left separator
+    static constexpr int DR = n * n;          // ... to right separator
+    static constexpr int CLR = 2 * n * n;     // coupling block (left sep, right sep)
+    // node j; NGL/NGR reuse DL/DR, which are consumed when the nodes are assembled
+    static constexpr int NGL = 0;             // pivot^-1 M(j, left neighbour)
+    static constexpr int NGR = n * n;         // pivot^-1 M(j, right neighbour)
+    static constexpr int NA = 3 * n * n;      // current diagonal block; Sigma_jj after the backward pass
+    static constexpr int NC = 4 * n * n;      // coupling M(j, right neighbour at the current level)
+    static constexpr int NP = 5 * n * n;      // pivot inverse at elimination
+    static constexpr int NX = 6 * n * n;      // Cov(j, right neighbour at j's level); Cov(j, j+1) at the end
+    static constexpr int RL = 7 * n * n;      // rhs contribution to left separator
+    static constexpr int RR = 7 * n * n + n;  // ... to right separator
+    static constexpr int NR = 7 * n * n + 2 * n;  // current rhs of node j
+    static constexpr int NZ = 7 * n * n + 3 * n;  // pivot^-1 rhs at elimination
+    static constexpr int XS = 7 * n * n + 4 * n;  // solution at separator j
+    static constexpr int STRIDE = 7 * n * n + 5 * n;
 };
 
 // Entry offsets in the per-state scratch (stride DevState::ws_stride).
@@ -259,136 +269,260 @@ PG_UNROLL
     return ok;
 }
 
-// Reduced chain over the nseg-1 separators (run by one lane).  COV: write
-// the separators' marginals into SDo and their cross-covariances into the
-// segment scratch.  RHS: solve and write the separator solutions into xo
-// and the segment scratch.
-template <int n, bool RHS, bool COV>
-__device__ __forceinline__ bool reduced_chain(const BlockSrc& M, int64_t off, int N, int nseg, double* sg, double* SDo,
-                              double* xo, int64_t S, double* logdet, TS ts) {
+// Reduced chain of the m = nseg - 1 separators by block cyclic reduction.
+// Lane j < m owns separator j; it is eliminated at level lv(j) = ctz(j + 1),
+// where its neighbours are j - 2^lv and j + 2^lv (when inside [0, m)).
+// Every lane of the calling half must call these (they contain workgroup
+// barriers; the count depends on m only).
+__device__ __forceinline__ int cr_levels(int m) { return m > 0 ? 32 - __clz(m) : 0; }
+
+template <int n>
+__device__ __forceinline__ void ld_blk(const double* p, double* M) {
+PG_UNROLL
+    for (int e = 0; e < n * n; ++e) M[e] = p[e];
+}
+template <int n>
+__device__ __forceinline__ void st_blk(double* p, const double* M) {
+PG_UNROLL
+    for (int e = 0; e < n * n; ++e) p[e] = M[e];
+}
+
+// Node j's diagonal block, right coupling and rhs from its separator state
+// and the two adjacent segments.
+template <int n, bool RHS>
+__device__ __forceinline__ void cr_assemble(const BlockSrc& M, int64_t off, int N, int nseg, int j, double* sg, TS ts) {
     using G = SegLayout<n>;
-    const int nsep = nseg - 1;
-    if (nsep <= 0) return true;
-    bool ok = true;
-    PG_MAT(P, ts);
-    PG_MAT(Pinv, ts);
-    PG_MAT(Ut, ts);
-    PG_MAT(Gt, ts);
-    PG_MAT(Dn, ts);  // next separator's assembled diagonal block, one step ahead
-    PG_MAT(Un, ts);  // next coupling block
-    PG_VEC(y, ts); PG_VEC(z, ts); PG_VEC(rn, ts);
-    // assembled diagonal block (and rhs) of separator j into Dd, rd
-    auto assemble = [&](int j, double* Dd, double* rd) {
-        const int s = sep_state(N, nseg, j);
-        const double* gj = sg + (int64_t)j * G::STRIDE;
-        const double* gn = sg + (int64_t)(j + 1) * G::STRIDE;
-        src_D<n>(M, off + s, Dd);
+    const int m = nseg - 1;
+    const int s = sep_state(N, nseg, j);
+    double* gj = sg + (int64_t)j * G::STRIDE;
+    const double* gn = sg + (int64_t)(j + 1) * G::STRIDE;
+    PG_MAT(A, ts);
+    src_D<n>(M, off + s, A);
 PG_UNROLL
-        for (int e = 0; e < n * n; ++e) Dd[e] += gj[G::DR + e] + gn[G::DL + e];
-        if (RHS) {
-            src_r<n>(M, off + s, rd);
+    for (int e = 0; e < n * n; ++e) A[e] += gj[G::DR + e] + gn[G::DL + e];
+    st_blk<n>(gj + G::NA, A);
+    if (j + 1 < m) {
 PG_UNROLL
-            for (int e = 0; e < n; ++e) rd[e] += gj[G::RR + e] + gn[G::RL + e];
-        }
-    };
-    assemble(0, P, y);
-    if (nsep > 1) {
-        const double* g1 = sg + (int64_t)1 * G::STRIDE;
-PG_UNROLL
-        for (int e = 0; e < n * n; ++e) Ut[e] = g1[G::CLR + e];
-    }
-    for (int j = 0; j < nsep; ++j) {
-        TS lt = ts;
-        double* gj = sg + (int64_t)j * G::STRIDE;
-        if (j + 1 < nsep) {
-            assemble(j + 1, Dn, rn);
-            if (j + 2 < nsep) {
-                const double* g2 = sg + (int64_t)(j + 2) * G::STRIDE;
-PG_UNROLL
-                for (int e = 0; e < n * n; ++e) Un[e] = g2[G::CLR + e];
-            }
-        }
-        ok = spd_inverse<n>(P, Pinv, RHS ? nullptr : logdet, lt) && ok;
-PG_UNROLL
-        for (int e = 0; e < n * n; ++e) gj[G::RPINV + e] = Pinv[e];
-        if (RHS) {
-            mvec<n>(Pinv, y, z);
-PG_UNROLL
-            for (int e = 0; e < n; ++e) gj[G::RZ + e] = z[e];
-        }
-        if (j + 1 < nsep) {
-            // coupling between separator j and j+1 lives in segment j+1;
-            // next pivot P = D_{j+1} - Ut^T Pinv Ut, next rhs y = r_{j+1} - Ut^T z
-            mmul<n>(Pinv, Ut, Gt);
-PG_UNROLL
-            for (int e = 0; e < n * n; ++e) gj[G::RG + e] = Gt[e];
-            mcopy<n>(Dn, P);
-            msub_tn<n>(Ut, Gt, P);
-            if (RHS) {
-PG_UNROLL
-                for (int e = 0; e < n; ++e) y[e] = rn[e];
-                mvec_tn_sub<n>(Ut, z, y);
-            }
-            if (j + 2 < nsep) mcopy<n>(Un, Ut);
-        }
-    }
-    if (!ok) return false;
-    if (COV) {
-        PG_MAT(Sn, ts);
-        {
-            const int j = nsep - 1;
-            double* gj = sg + (int64_t)j * G::STRIDE;
-PG_UNROLL
-            for (int e = 0; e < n * n; ++e) Sn[e] = gj[G::RPINV + e];
-            st_soa_sym<n>(SDo, S, off + sep_state(N, nseg, j), Sn);
-        }
-        for (int j = nsep - 2; j >= 0; --j) {
-            TS lt = ts;
-            double* gj = sg + (int64_t)j * G::STRIDE;
-            double* gn = sg + (int64_t)(j + 1) * G::STRIDE;
-            PG_MAT(Gj, lt);
-            PG_MAT(C, lt);
-            PG_MAT(Sj, lt);
-PG_UNROLL
-            for (int e = 0; e < n * n; ++e) Gj[e] = gj[G::RG + e];
-            mmul<n>(Gj, Sn, C);  // C = Gj Sn ; Cov(j, j+1) = -C
-PG_UNROLL
-            for (int e = 0; e < n * n; ++e) gn[G::CROSS + e] = -C[e];
-            // Sj = Pinv_j + C Gj^T
-            mmul_nt<n>(C, Gj, Sj);
-PG_UNROLL
-            for (int e = 0; e < n * n; ++e) Sj[e] += gj[G::RPINV + e];
-            st_soa_sym<n>(SDo, S, off + sep_state(N, nseg, j), Sj);
-            mcopy<n>(Sj, Sn);
-        }
+        for (int e = 0; e < n * n; ++e) gj[G::NC + e] = gn[G::CLR + e];
     }
     if (RHS) {
-        PG_VEC(x, ts);
-        {
-            const int j = nsep - 1;
-            double* gj = sg + (int64_t)j * G::STRIDE;
+        PG_VEC(r, ts);
+        src_r<n>(M, off + s, r);
 PG_UNROLL
-            for (int e = 0; e < n; ++e) x[e] = gj[G::RZ + e];
-PG_UNROLL
-            for (int e = 0; e < n; ++e) gj[G::XS + e] = x[e];
-            st_vec<n>(xo, S, off + sep_state(N, nseg, j), x);
-        }
-        for (int j = nsep - 2; j >= 0; --j) {
-            TS lt = ts;
-            double* gj = sg + (int64_t)j * G::STRIDE;
-            PG_MAT(Gj, lt);
-            PG_VEC(t, lt);
-PG_UNROLL
-            for (int e = 0; e < n * n; ++e) Gj[e] = gj[G::RG + e];
-            mvec<n>(Gj, x, t);
-PG_UNROLL
-            for (int e = 0; e < n; ++e) x[e] = gj[G::RZ + e] - t[e];
-PG_UNROLL
-            for (int e = 0; e < n; ++e) gj[G::XS + e] = x[e];
-            st_vec<n>(xo, S, off + sep_state(N, nseg, j), x);
-        }
+        for (int e = 0; e < n; ++e) gj[G::NR + e] = r[e] + gj[G::RR + e] + gn[G::RL + e];
     }
-    return true;
+}
+
+// Forward elimination.  Level l: the nodes eliminated at l store their pivot
+// inverse P, G_L = P M(k, L), G_R = P M(k, R) and z = P r (barrier); the
+// surviving nodes then take the Schur updates of their eliminated
+// neighbours and their new right coupling -M(j, k) P M(k, R) (barrier).
+template <int n, bool RHS>
+__device__ __forceinline__ bool cr_forward(int m, int j, double* sg, double* logdet, TS ts) {
+    using G = SegLayout<n>;
+    const int levels = cr_levels(m);
+    const bool own = j < m;
+    const int lv = own ? __builtin_ctz(j + 1) : -1;
+    double* gj = sg + (int64_t)(own ? j : 0) * G::STRIDE;
+    bool ok = true;
+    for (int l = 0; l < levels; ++l) {
+        const int h = 1 << l;
+        if (own && lv == l) {
+            TS lt = ts;
+            PG_MAT(A, lt);
+            PG_MAT(P, lt);
+            PG_MAT(C, lt);
+            PG_MAT(T, lt);
+            ld_blk<n>(gj + G::NA, A);
+            ok = spd_inverse<n>(A, P, RHS ? nullptr : logdet, lt) && ok;
+            st_blk<n>(gj + G::NP, P);
+            if (j - h >= 0) {
+                ld_blk<n>(sg + (int64_t)(j - h) * G::STRIDE + G::NC, C);  // M(L, k)
+                mmul_nt<n>(P, C, T);
+                st_blk<n>(gj + G::NGL, T);
+            }
+            if (j + h < m) {
+                ld_blk<n>(gj + G::NC, C);  // M(k, R)
+                mmul<n>(P, C, T);
+                st_blk<n>(gj + G::NGR, T);
+            }
+            if (RHS) {
+                PG_VEC(r, lt);
+                PG_VEC(z, lt);
+PG_UNROLL
+                for (int e = 0; e < n; ++e) r[e] = gj[G::NR + e];
+                mvec<n>(P, r, z);
+PG_UNROLL
+                for (int e = 0; e < n; ++e) gj[G::NZ + e] = z[e];
+            }
+        }
+        __syncthreads();
+        if (own && lv > l && ((j + 1) & (h - 1)) == 0) {
+            TS lt = ts;
+            PG_MAT(A, lt);
+            PG_MAT(C, lt);
+            PG_MAT(Gk, lt);
+            PG_VEC(r, lt);
+            PG_VEC(z, lt);
+            ld_blk<n>(gj + G::NA, A);
+            if (RHS) {
+PG_UNROLL
+                for (int e = 0; e < n; ++e) r[e] = gj[G::NR + e];
+            }
+            if (j + h < m) {
+                // right neighbour k = j + h: A -= M(j,k) G_L(k), r -= M(j,k) z_k,
+                // new coupling to k + h: -M(j,k) G_R(k)
+                const double* gk = sg + (int64_t)(j + h) * G::STRIDE;
+                ld_blk<n>(gj + G::NC, C);
+                ld_blk<n>(gk + G::NGL, Gk);
+                msub<n>(C, Gk, A);
+                if (RHS) {
+PG_UNROLL
+                    for (int e = 0; e < n; ++e) z[e] = gk[G::NZ + e];
+                    mvec_sub<n>(C, z, r);
+                }
+                if (j + 2 * h < m) {
+                    PG_MAT(T, lt);
+                    ld_blk<n>(gk + G::NGR, Gk);
+                    mmul<n>(C, Gk, T);
+PG_UNROLL
+                    for (int e = 0; e < n * n; ++e) gj[G::NC + e] = -T[e];
+                }
+            }
+            if (j - h >= 0) {
+                // left neighbour k = j - h: A -= M(k,j)^T G_R(k), r -= M(k,j)^T z_k
+                const double* gk = sg + (int64_t)(j - h) * G::STRIDE;
+                ld_blk<n>(gk + G::NC, C);
+                ld_blk<n>(gk + G::NGR, Gk);
+                msub_tn<n>(C, Gk, A);
+                if (RHS) {
+PG_UNROLL
+                    for (int e = 0; e < n; ++e) z[e] = gk[G::NZ + e];
+                    mvec_tn_sub<n>(C, z, r);
+                }
+            }
+            st_blk<n>(gj + G::NA, A);
+            if (RHS) {
+PG_UNROLL
+                for (int e = 0; e < n; ++e) gj[G::NR + e] = r[e];
+            }
+        }
+        __syncthreads();
+    }
+    return ok;
+}
+
+// Backward selected inversion, top level first: node k eliminated at level l
+// with neighbours L, R (whose covariances are known from higher levels):
+//   Cov(k, L) = -(G_L S_LL + G_R S_RL),  Cov(k, R) = -(G_L S_LR + G_R S_RR),
+//   S_kk = P - Cov(k, L) G_L^T - Cov(k, R) G_R^T.
+// Writes S_kk (node and SDo) and the cross-covariances of the two new
+// adjacent pairs (L, k) and (k, R).  run = false keeps the barriers only.
+template <int n>
+__device__ __forceinline__ void cr_backward_cov(int m, int j, bool run, int64_t off, int N, int nseg, double* sg,
+                                                double* SDo, int64_t S, TS ts) {
+    using G = SegLayout<n>;
+    const int levels = cr_levels(m);
+    const bool own = run && j < m;
+    const int lv = own ? __builtin_ctz(j + 1) : -1;
+    double* gj = sg + (int64_t)(own ? j : 0) * G::STRIDE;
+    for (int l = levels - 1; l >= 0; --l) {
+        const int h = 1 << l;
+        if (own && lv == l) {
+            TS lt = ts;
+            const bool hasL = j - h >= 0, hasR = j + h < m;
+            double* gl = sg + (int64_t)(hasL ? j - h : j) * G::STRIDE;
+            const double* gr = sg + (int64_t)(hasR ? j + h : j) * G::STRIDE;
+            PG_MAT(Sk, lt);
+            PG_MAT(GL, lt);
+            PG_MAT(GR, lt);
+            PG_MAT(CL, lt);
+            PG_MAT(CR, lt);
+            PG_MAT(X, lt);
+            PG_MAT(T, lt);
+            ld_blk<n>(gj + G::NP, Sk);
+            if (hasL) ld_blk<n>(gj + G::NGL, GL);
+            if (hasR) ld_blk<n>(gj + G::NGR, GR);
+            if (hasL && hasR) ld_blk<n>(gl + G::NX, X);  // Cov(L, R)
+            if (hasL) {
+                ld_blk<n>(gl + G::NA, T);  // S_LL
+                mmul<n>(GL, T, CL);
+                if (hasR) {
+                    // + G_R S_RL, S_RL = X^T
+                    PG_MAT(U, lt);
+                    mmul_nt<n>(GR, X, U);
+PG_UNROLL
+                    for (int e = 0; e < n * n; ++e) CL[e] += U[e];
+                }
+PG_UNROLL
+                for (int e = 0; e < n * n; ++e) CL[e] = -CL[e];
+                msub_nt<n>(CL, GL, Sk);
+            }
+            if (hasR) {
+                ld_blk<n>(gr + G::NA, T);  // S_RR
+                mmul<n>(GR, T, CR);
+                if (hasL) {
+                    PG_MAT(U, lt);
+                    mmul<n>(GL, X, U);
+PG_UNROLL
+                    for (int e = 0; e < n * n; ++e) CR[e] += U[e];
+                }
+PG_UNROLL
+                for (int e = 0; e < n * n; ++e) CR[e] = -CR[e];
+                msub_nt<n>(CR, GR, Sk);
+            }
+            st_blk<n>(gj + G::NA, Sk);
+            st_soa_sym<n>(SDo, S, off + sep_state(N, nseg, j), Sk);
+            if (hasL) {
+PG_UNROLL
+                for (int r = 0; r < n; ++r)
+PG_UNROLL
+                    for (int c = 0; c < n; ++c) gl[G::NX + r * n + c] = CL[c * n + r];  // Cov(L, k)
+            }
+            if (hasR) st_blk<n>(gj + G::NX, CR);  // Cov(k, R)
+        }
+        __syncthreads();
+    }
+}
+
+// Backward substitution: x_k = z_k - G_L x_L - G_R x_R, top level first.
+template <int n>
+__device__ __forceinline__ void cr_backward_rhs(int m, int j, bool run, int64_t off, int N, int nseg, double* sg,
+                                                double* xo, int64_t S, TS ts) {
+    using G = SegLayout<n>;
+    const int levels = cr_levels(m);
+    const bool own = run && j < m;
+    const int lv = own ? __builtin_ctz(j + 1) : -1;
+    double* gj = sg + (int64_t)(own ? j : 0) * G::STRIDE;
+    for (int l = levels - 1; l >= 0; --l) {
+        const int h = 1 << l;
+        if (own && lv == l) {
+            TS lt = ts;
+            PG_VEC(x, lt);
+            PG_VEC(y, lt);
+            PG_MAT(Gk, lt);
+PG_UNROLL
+            for (int e = 0; e < n; ++e) x[e] = gj[G::NZ + e];
+            if (j - h >= 0) {
+                const double* gl = sg + (int64_t)(j - h) * G::STRIDE;
+                ld_blk<n>(gj + G::NGL, Gk);
+PG_UNROLL
+                for (int e = 0; e < n; ++e) y[e] = gl[G::XS + e];
+                mvec_sub<n>(Gk, y, x);
+            }
+            if (j + h < m) {
+                const double* gr = sg + (int64_t)(j + h) * G::STRIDE;
+                ld_blk<n>(gj + G::NGR, Gk);
+PG_UNROLL
+                for (int e = 0; e < n; ++e) y[e] = gr[G::XS + e];
+                mvec_sub<n>(Gk, y, x);
+            }
+PG_UNROLL
+            for (int e = 0; e < n; ++e) gj[G::XS + e] = x[e];
+            st_vec<n>(xo, S, off + sep_state(N, nseg, j), x);
+        }
+        __syncthreads();
+    }
 }
 
 // Backward recovery of segment j's interior marginals.
@@ -407,7 +541,7 @@ __device__ __forceinline__ void seg_backward_cov(int64_t off, int N, int nseg, i
     if (hasR) {
         ld_soa<n>(SDo, S, off + b + 1, Snn);
         if (hasL) {
-            const double* cr = sg + (int64_t)j * G::STRIDE + G::CROSS;  // Cov(L, R)
+            const double* cr = sg + (int64_t)(j - 1) * G::STRIDE + G::NX;  // Cov(L, R)
 PG_UNROLL
             for (int r = 0; r < n; ++r)
 PG_UNROLL
@@ -553,14 +687,21 @@ PG_UNROLL
     }
 }
 
-// Workgroup-wide GBP: marginals of (D, U) from src into (SDo, SUo).
+// Workgroup-wide GBP: marginals of (D, U) from src into (SDo, SUo).  Called
+// by every lane of the half (tid = lane); sh_ld / sh_ok hold
+// kChainThreads + 1 entries.
 template <int n>
 __device__ __forceinline__ bool wg_gbp(const BlockSrc& M, const DevState& st, double* ws, int tid, int64_t off,
                                        int64_t So, int N, int nseg, double* sg, double* SDo, double* SUo,
                                        double* logdet_out, double* sh_ld, int* sh_ok, TS ts) {
+    const int m = nseg - 1;
     double ld = 0.0;
     bool ok = true;
     if (tid < nseg) ok = seg_forward<n, false>(M, off, N, nseg, tid, ws, st.ws_stride, sg, &ld, ts);
+    __syncthreads();
+    if (tid < m) cr_assemble<n, false>(M, off, N, nseg, tid, sg, ts);
+    __syncthreads();
+    ok = cr_forward<n, false>(m, tid, sg, &ld, ts) && ok;
     sh_ld[tid] = ld;
     sh_ok[tid] = ok ? 1 : 0;
     __syncthreads();
@@ -571,37 +712,40 @@ __device__ __forceinline__ bool wg_gbp(const BlockSrc& M, const DevState& st, do
             tot += sh_ld[t];
             all &= sh_ok[t];
         }
-        double ldr = 0.0;
-        bool okr = all ? reduced_chain<n, false, true>(M, off, N, nseg, sg, SDo, nullptr, So, &ldr, ts) : false;
-        sh_ld[kChainThreads] = tot + ldr;
-        sh_ok[kChainThreads] = (all && okr) ? 1 : 0;
+        sh_ld[kChainThreads] = tot;
+        sh_ok[kChainThreads] = all;
     }
     __syncthreads();
     const bool okall = sh_ok[kChainThreads] != 0;
     *logdet_out = sh_ld[kChainThreads];
+    cr_backward_cov<n>(m, tid, okall, off, N, nseg, sg, SDo, So, ts);
     if (okall && tid < nseg) seg_backward_cov<n>(off, N, nseg, tid, ws, st.ws_stride, sg, SDo, SUo, So, ts);
     __syncthreads();
     return okall;
 }
 
-// Workgroup-wide solve of (D, U) x = r into xo.
+// Workgroup-wide solve of (D, U) x = r into xo (same barriers as wg_gbp).
 template <int n>
 __device__ __forceinline__ bool wg_solve(const BlockSrc& M, const DevState& st, double* ws, int tid, int64_t off,
                                          int64_t So, int N, int nseg, double* sg, double* xo, int* sh_ok, TS ts) {
+    const int m = nseg - 1;
     double ld = 0.0;
     bool ok = true;
     if (tid < nseg) ok = seg_forward<n, true>(M, off, N, nseg, tid, ws, st.ws_stride, sg, &ld, ts);
+    __syncthreads();
+    if (tid < m) cr_assemble<n, true>(M, off, N, nseg, tid, sg, ts);
+    __syncthreads();
+    ok = cr_forward<n, true>(m, tid, sg, &ld, ts) && ok;
     sh_ok[tid] = ok ? 1 : 0;
     __syncthreads();
     if (tid == 0) {
         int all = 1;
         for (int t = 0; t < kChainThreads; ++t) all &= sh_ok[t];
-        double ldr = 0.0;
-        bool okr = all ? reduced_chain<n, true, false>(M, off, N, nseg, sg, nullptr, xo, So, &ldr, ts) : false;
-        sh_ok[kChainThreads] = (all && okr) ? 1 : 0;
+        sh_ok[kChainThreads] = all;
     }
     __syncthreads();
     const bool okall = sh_ok[kChainThreads] != 0;
+    cr_backward_rhs<n>(m, tid, okall, off, N, nseg, sg, xo, So, ts);
     if (okall && tid < nseg) seg_backward_rhs<n>(off, N, nseg, tid, ws, st.ws_stride, sg, xo, So, ts);
     __syncthreads();
     return okall;
@@ -772,26 +916,31 @@ __global__ void __launch_bounds__(kChainThreads) chain_kernel(DevState st, int m
     }
 }
 
+// Sum over the block in a fixed order (sh holds blockDim.x + 1 doubles).
+__device__ __forceinline__ double block_sum(double v, double* sh) { return wg_sum(v, sh); }
+
 // One proximal iteration (Alg. 1), part 1: per-state quantities shared by all
 // trial step sizes -- KH = K^-1 + H (collision Hessians on the diagonal
-// blocks), rb = eta - g, Lmu = Lambda_k mu_k -- and the expected costs.
+// blocks), rb = eta - g, Lmu = Lambda_k mu_k -- and the expected costs
+// (per-block partial sums; the select kernel adds them in block order).
+// Grid (plans, iter_blocks), kIterThreads threads, grid-stride over states.
 template <int n>
-__global__ void __launch_bounds__(kChainThreads) prep_kernel(DevState st) {
-    __shared__ double sh_d[kChainThreads + 1];
-    const int pid = blockIdx.x;
+__global__ void __launch_bounds__(kIterThreads) prep_kernel(DevState st) {
+    __shared__ double sh_d[kIterThreads + 1];
+    const int pid = blockIdx.x, y = blockIdx.y, nb = gridDim.y;
     PlanDev& p = st.plans[pid];
     if (!p.active) return;
     const int tid = threadIdx.x;
     if (p.iters_left <= 0) {
-        if (tid == 0) p.phase = 1;
+        if (y == 0 && tid == 0) p.phase = 1;
         return;
     }
     const int N = p.N, d = p.d;
     const int64_t off = p.off, S = st.S;
     const int n2 = n * n;
-    TS ts = thread_ws<n>(st, pid, 0);
+    TS ts = thread_ws<n>(st, pid, y);
     double ecol = 0.0, epri = 0.0;
-    for (int i = tid; i < N; i += kChainThreads) {
+    for (int i = y * kIterThreads + tid; i < N; i += nb * kIterThreads) {
         TS lt = ts;
         const int64_t s = off + i;
         const bool act = coll_active<n>(p, i);
@@ -835,12 +984,12 @@ PG_UNROLL
         st_vec<n>(st.Lmu, S, s, acc);
         epri += prior_cost_state<n>(st, p, i, nullptr, nullptr, nullptr, lt);
     }
-    ecol = wg_sum(ecol, sh_d);
-    epri = wg_sum(epri, sh_d);
+    ecol = block_sum(ecol, sh_d);
+    epri = block_sum(epri, sh_d);
     if (tid == 0) {
-        p.E_coll = ecol;
-        p.E_prior = epri;
-        p.phase = 0;
+        st.psum[((int64_t)pid * nb + y) * 2 + 0] = ecol;
+        st.psum[((int64_t)pid * nb + y) * 2 + 1] = epri;
+        if (y == 0) p.phase = 0;
     }
 }
 
@@ -935,12 +1084,18 @@ __global__ void __launch_bounds__(kTrialThreads) trial_kernel(DevState st, int r
 
 // Part 3: take the first passing trial of this window (in step-size order)
 // and write it back as the new iterate; finish the iteration of plans whose
-// step sizes are exhausted (state unchanged, ENOCONV).
+// step sizes are exhausted (state unchanged, ENOCONV).  Grid (plans,
+// iter_blocks): every block finds the same pick from the trial results and
+// copies its share of the states; block 0 does the bookkeeping and tags
+// the plan with phase 2 + round, which the other blocks of this launch still
+// read as pending.
 template <int n>
-__global__ void __launch_bounds__(kChainThreads) select_kernel(DevState st, int round) {
-    const int pid = blockIdx.x;
+__global__ void __launch_bounds__(kIterThreads) select_kernel(DevState st, int round) {
+    const int pid = blockIdx.x, y = blockIdx.y, nb = gridDim.y;
     PlanDev& p = st.plans[pid];
-    if (!p.active || p.phase != 0) return;
+    if (!p.active) return;
+    const int ph = p.phase;
+    if (ph != 0 && ph != 2 + round) return;
     const int tid = threadIdx.x;
     const int W = st.W;
     int pick = -1;
@@ -959,7 +1114,6 @@ __global__ void __launch_bounds__(kChainThreads) select_kernel(DevState st, int 
     }
     const bool exhausted = (round + 1) * W >= p.max_bisect;
     if (pick < 0 && !exhausted) return;  // next window
-    __syncthreads();
     const int N = p.N;
     const int64_t S = st.S, off = p.off, SW = S * W;
     const int n2 = n * n;
@@ -972,7 +1126,7 @@ __global__ void __launch_bounds__(kChainThreads) select_kernel(DevState st, int 
         const double c = 1.0 / fma(beta, p.temperature, 1.0);
         const double a0 = c * beta, a1 = c;
         const int64_t tq = (int64_t)pick * S;
-        for (int i = tid; i < N; i += kChainThreads) {
+        for (int i = y * kIterThreads + tid; i < N; i += nb * kIterThreads) {
             const int64_t s = off + i, q = tq + s;
             for (int e = 0; e < n2; ++e) {
                 st.LD[e * S + s] = lin2(a0, st.KH[e * S + s], a1, st.LD[e * S + s]);
@@ -985,7 +1139,14 @@ __global__ void __launch_bounds__(kChainThreads) select_kernel(DevState st, int 
             for (int e = 0; e < n; ++e) st.mu[e * S + s] = st.Tmu[e * SW + q];
         }
     }
-    if (tid == 0) {
+    if (y == 0 && tid == 0) {
+        double ecol = 0.0, epri = 0.0;
+        for (int k = 0; k < nb; ++k) {
+            ecol += st.psum[((int64_t)pid * nb + k) * 2 + 0];
+            epri += st.psum[((int64_t)pid * nb + k) * 2 + 1];
+        }
+        p.E_coll = ecol;
+        p.E_prior = epri;
         p.trials = pick >= 0 ? round * W + pick + 1 : tried;
         p.trials_total += p.trials;
         p.kl = kl;
@@ -1000,7 +1161,7 @@ __global__ void __launch_bounds__(kChainThreads) select_kernel(DevState st, int 
         p.entropy = 0.5 * (double)N * n * (1.0 + 1.8378770664093453) - 0.5 * p.logdet;
         p.iters_left -= 1;
         p.iters_done += 1;
-        p.phase = 1;
+        p.phase = 2 + round;
     }
 }
 
@@ -1029,9 +1190,10 @@ hipError_t launch_chain_n(const DevState& st, int mode, int lo, int hi, hipStrea
 template <int n>
 hipError_t launch_iteration_n(const DevState& st, int phw, int part, int round, hipStream_t s) {
     if (phw <= 0) return hipSuccess;
-    if (part == 0) hipLaunchKernelGGL(prep_kernel<n>, dim3(phw), dim3(kChainThreads), 0, s, st);
+    const dim3 it(phw, st.iter_blocks);
+    if (part == 0) hipLaunchKernelGGL(prep_kernel<n>, it, dim3(kIterThreads), 0, s, st);
     if (part == 1) hipLaunchKernelGGL(trial_kernel<n>, dim3(phw, st.W), dim3(kTrialThreads), 0, s, st, round);
-    if (part == 2) hipLaunchKernelGGL(select_kernel<n>, dim3(phw), dim3(kChainThreads), 0, s, st, round);
+    if (part == 2) hipLaunchKernelGGL(select_kernel<n>, it, dim3(kIterThreads), 0, s, st, round);
     return hipGetLastError();
 }
 

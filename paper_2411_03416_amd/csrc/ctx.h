@@ -14,6 +14,8 @@ namespace pg {
 constexpr int kMaxSeg = 64;      // chain segments per plan (upper bound)
 constexpr int kChainThreads = 64; // one wavefront per plan in the chain kernel
 constexpr int kTrialThreads = 128; // trial kernel: marginals and mean solve side by side
+constexpr int kIterThreads = 128;  // prep/select kernels (uses the trial kernel's per-thread slots)
+constexpr int kIterBlocks = 8;     // prep/select blocks per plan (at most W)
 constexpr int kMaxGH = 10;        // Gauss-Hermite points per dimension
 // n x n temporaries a chain-kernel thread may hold at once.  Deepest call
 // paths: kernel loop body 1 + prior cost 8 = 9; segment elimination 9 +
@@ -29,7 +31,8 @@ struct PlanDev {
     int32_t d, gh_points, gx, gy;
     int32_t gz, n_spheres, coll_states, status;
     int32_t trials, m, n_iters, trials_total;
-    int32_t phase, pad0;  // phase: 0 = step pending this iteration, 1 = done
+    int32_t phase, pad0;  // 0 = step pending this iteration, 1 = no step this iteration,
+                          // 2 + r = step taken (or exhausted) in trial window r
     int32_t coll_index[PGVIMP_MAX_COLL_DIM];
     double temperature, beta_max, kl_bound, cell, dt;
     double inv_cell, hinge_eps, obs_weight, logdet;
@@ -70,6 +73,8 @@ struct DevState {
     double *Tmu, *TSD, *TSU;
     double* tres;  // per (plan, slot): passed, KL, log det, beta
     int32_t W;     // trial step sizes evaluated concurrently
+    int32_t iter_blocks;  // blocks per plan of the prep and select kernels
+    double* psum;         // per (plan, prep block): partial E_coll, E_prior
     // collision expectations (d-dim, not embedded): E [S], g [d][S], H [d*d][S]
     double *Ecol, *gcol, *Hcol;
     // mean-solve right-hand side parts: rb = eta - g, Lmu = Lambda_k mu_k
