@@ -41,12 +41,13 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
     ap.add_argument("--segments", type=int, default=0)
     ap.add_argument("--lanes", type=int, default=0)
+    ap.add_argument("--trial-width", type=int, default=0, help="trial step sizes per window (0 = library default)")
     ap.add_argument("--serve", action="store_true",
                     help="run the serving mix (Poisson arrivals of configs 0-3) instead of the batch solve")
     ap.add_argument("--qps", type=float, default=20.0)
     ap.add_argument("--requests", type=int, default=60)
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="first copy 512 MiB device-to-device once (a kernel of known traffic for counters)")
+                    help="first run a 512 MiB copy kernel once (known traffic, to scale memory counters)")
     return ap.parse_args()
 
 
@@ -82,14 +83,15 @@ def make_batch(n_plans, N, iters):
     return probs
 
 
-def timed_solve(pg, probs, precision, steps, warmup, iters, segments=0, lanes=0, profile=True):
+def timed_solve(pg, probs, precision, steps, warmup, iters, segments=0, lanes=0, profile=True, trial_width=0):
     """Create one context for the batch, warm up, then time `steps` solves,
     each one HIP graph replay.  With profile, the same number of solves is
     then run with HIP events around every kernel on the context's stream
     (launched directly, since events inside a graph cannot be timed) to get
     each kernel's mean duration."""
     import torch
-    ctx = pg.pgvimp_create(probs, precision=precision, use_graph=True, segments=segments, lanes=lanes)
+    ctx = pg.pgvimp_create(probs, precision=precision, use_graph=True, segments=segments, lanes=lanes,
+                           trial_width=trial_width)
     for _ in range(warmup):
         pg.pgvimp_solve(ctx, iters)
     torch.cuda.synchronize()
@@ -164,8 +166,10 @@ def main():
     import paper_2411_03416_amd as pg
     if args.calibrate_copy:
         import torch
+        # a plain copy kernel of known traffic (512 MiB read, 512 MiB written):
+        # a dtype-converting copy runs as a kernel, a same-dtype one may not
         src = torch.ones(512 << 20, dtype=torch.uint8, device="cuda")
-        dst = torch.empty_like(src)
+        dst = torch.empty(512 << 20, dtype=torch.int8, device="cuda")
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
@@ -176,7 +180,8 @@ def main():
     probs = make_batch(args.plans, args.N, args.iters)
     B, N, K = args.plans, args.N, args.iters
     n = probs[0]["n"]
-    mixed = timed_solve(pg, probs, pg.MIXED, args.steps, args.warmup, K, args.segments, args.lanes)
+    mixed = timed_solve(pg, probs, pg.MIXED, args.steps, args.warmup, K, args.segments, args.lanes,
+                        trial_width=args.trial_width)
     ms = 1e3 * mixed["wall_s"] / args.steps
     factors_per_step = B * N * K
     value = factors_per_step / (ms / 1e3)
@@ -224,7 +229,7 @@ def main():
         out["eager_ms_per_step"] = kt["eager_ms_per_step"]
     if not args.no_fp64:
         f64 = timed_solve(pg, probs, pg.FP64, max(2, args.steps // 2), 1, K, args.segments, args.lanes,
-                          profile=False)
+                          profile=False, trial_width=args.trial_width)
         ms64 = 1e3 * f64["wall_s"] / max(2, args.steps // 2)
         out["fp64"] = {"value": factors_per_step / (ms64 / 1e3), "ms_per_step": ms64,
                        "plans_per_s": B / (ms64 / 1e3),

@@ -24,6 +24,7 @@ struct PlanHost {
     bool active = false;
     int N = 0;
     int64_t off = -1;
+    int64_t coff = -1;  // chain-order range
     int64_t heap_off = -1;
     int coll_kind = 0, d = 0, p = 0;
     double dt = 0.0;
@@ -51,7 +52,7 @@ struct pgvimp_ctx {
     char* heap = nullptr;
     int64_t heap_bytes = 0;
     DevState st{};
-    RangeAlloc states, heapalloc;
+    RangeAlloc states, cstates, heapalloc;  // states, chain-order ranges, heap
     std::vector<PlanHost> plans;
     std::vector<PlanDev> pdev;  // host mirror of the device plan table
     // staging for host I/O
@@ -340,20 +341,28 @@ static int64_t carve(pgvimp_ctx* c, const pgvimp_engine_cfg* cfg, DevState& st, 
     take(&st.plans, P * (int64_t)sizeof(PlanDev));
     take(&st.state_plan, S * 4);
     const int64_t W = trial_width(cfg);
-    double** sq[] = {&st.KD, &st.KU, &st.KH, &st.Phi, &st.Qinv, &st.LD, &st.LU, &st.SD, &st.SU};
+    // chain-order capacity: each plan's range is rounded up to whole rows of
+    // its segments and to whole tiles of 32 positions, and starts on a tile
+    // (fewer than kMaxSeg + 2 * 32 extra positions per plan)
+    const int64_t Sc = (S + (kMaxSeg + 64) * P + 31) / 32 * 32;
+    double** sq[] = {&st.KD, &st.KU, &st.Phi, &st.Qinv, &st.LD, &st.LU, &st.SD, &st.SU};
     for (auto p : sq) take(p, S * n * n * 8);
-    double** vec[] = {&st.eta, &st.abar, &st.mu, &st.rb, &st.Lmu};
+    double** vec[] = {&st.eta, &st.abar, &st.mu};
     for (auto p : vec) take(p, S * n * 8);
-    take(&st.TSD, W * S * n * n * 8);
-    take(&st.TSU, W * S * n * n * 8);
-    take(&st.Tmu, W * S * n * 8);
+    double** csq[] = {&st.cKH, &st.cKD, &st.cLD, &st.cKU, &st.cLU};
+    for (auto p : csq) take(p, Sc * n * n * 8);
+    double** cvec[] = {&st.crb, &st.cLmu, &st.cmu};
+    for (auto p : cvec) take(p, Sc * n * 8);
+    take(&st.TSD, W * Sc * n * n * 8);
+    take(&st.TSU, W * Sc * n * n * 8);
+    take(&st.Tmu, W * Sc * n * 8);
     take(&st.tres, P * W * 4 * 8);
     take(&st.psum, P * kIterBlocks * 2 * 8);
     take(&st.Ecol, S * 8);
     take(&st.gcol, S * dmax * 8);
     take(&st.Hcol, S * dmax * dmax * 8);
     take(&st.Epri, (S + P) * 8);
-    take(&st.ws, 2 * W * S * ws_stride * 8);
+    take(&st.ws, 2 * W * Sc * ws_stride * 8);
     take(&st.seg, P * W * 2 * kMaxSeg * (int64_t)seg_stride * 8);
     const int64_t tws_stride = (int64_t)kTwsBlocks * n * n + (int64_t)kTwsVecs * n;
     take(&st.tws, P * W * kTrialThreads * tws_stride * 8);
@@ -367,6 +376,7 @@ static int64_t carve(pgvimp_ctx* c, const pgvimp_engine_cfg* cfg, DevState& st, 
     }
     off += align_up(cfg->heap_bytes);
     st.S = S;
+    st.Sc = Sc;
     st.n = n;
     st.P = (int32_t)P;
     st.ws_stride = ws_stride;
@@ -403,6 +413,7 @@ static int ctx_alloc(pgvimp_ctx* c) {
     c->arena_bytes = total;
     carve(c, &c->cfg, st, c->arena);
     c->states.reset(S);
+    c->cstates.reset(c->st.Sc);
     c->heapalloc.reset(c->heap_bytes);
     c->plans.assign(P, PlanHost{});
     c->pdev.assign(P, PlanDev{});
@@ -527,9 +538,17 @@ int pgvimp_add_plan(pgvimp_ctx* c, const pgvimp_problem* p, int32_t* plan_out) {
     const int64_t bytes = sdf_bytes + align_up(model_count * 8);
     const int64_t soff = c->states.alloc(N);
     if (soff < 0) FAIL(c, PGVIMP_ENOMEM, "no room for %d states", N);
+    const int nseg = choose_segments(c, N, p->segments);
+    const int64_t clen = ((int64_t)((N + nseg - 1) / nseg) * nseg + 31) / 32 * 32;
+    const int64_t coff = c->cstates.alloc(clen, 32);
+    if (coff < 0) {
+        c->states.release(soff);
+        FAIL(c, PGVIMP_ENOMEM, "no room for %lld chain positions", (long long)clen);
+    }
     const int64_t hoff = c->heapalloc.alloc(bytes, kAlign);
     if (hoff < 0) {
         c->states.release(soff);
+        c->cstates.release(coff);
         FAIL(c, PGVIMP_ENOMEM, "no heap room for %lld bytes of map/model data", (long long)bytes);
     }
     char* base = c->heap + hoff;
@@ -582,7 +601,8 @@ int pgvimp_add_plan(pgvimp_ctx* c, const pgvimp_problem* p, int32_t* plan_out) {
     pd.active = 1;
     pd.N = N;
     pd.off = (int32_t)soff;
-    pd.nseg = choose_segments(c, N, p->segments);
+    pd.nseg = nseg;
+    pd.coff = (int32_t)coff;
     pd.iters_left = p->n_iters;
     pd.n_iters = p->n_iters;
     pd.dt = p->dt;
@@ -627,6 +647,7 @@ int pgvimp_add_plan(pgvimp_ctx* c, const pgvimp_problem* p, int32_t* plan_out) {
     ph.active = true;
     ph.N = N;
     ph.off = soff;
+    ph.coff = coff;
     ph.heap_off = hoff;
     ph.coll_kind = p->coll_kind;
     ph.d = pd.d;
@@ -668,6 +689,7 @@ int pgvimp_remove_plan(pgvimp_ctx* c, int32_t plan) {
     if (rc) return rc;
     HCK(c, hipStreamSynchronize(c->stream));
     c->states.release(ph.off);
+    c->cstates.release(ph.coff);
     c->heapalloc.release(ph.heap_off);
     ph = PlanHost{};
     return PGVIMP_OK;

@@ -1,7 +1,7 @@
 // Chain kernels: marginal covariances of the block-tridiagonal precision
 // (Gaussian belief propagation on the chain, Sec. 5.1), the block-
 // tridiagonal mean solve of Theorem 1, and the fused step-size loop of
-// Alg. 1 / App. C.  One workgroup of one wavefront serves one plan.
+// Alg. 1 / App. C.  One wavefront (64 lanes) factors one matrix of one plan.
 //
 // Parallel form.  GBP on a chain is exact and equals the block-tridiagonal
 // selected inverse (Sigma_ii, Sigma_{i,i+1}).  Instead of one sequential
@@ -21,6 +21,16 @@
 // (interior Schur complements and reduced-chain pivots), and Lambda is
 // positive definite iff every pivot is.
 //
+// Chain order.  The lanes of a wavefront walk their segments in lock step,
+// so the blocks they touch at one step belong to nseg different segments.
+// The data the sweeps read and write is therefore kept in chain order:
+// state i of segment j (local index il = i - start_j) sits at position
+// il * nseg + j of the plan's chain range, which makes every per-step load
+// and store of a wavefront contiguous.  The prep kernel writes the
+// iteration's inputs in chain order, the sweeps' temporaries and the trial
+// results stay in chain order, and the select kernel writes the accepted
+// trial back in state order.
+//
 // The same elimination with a right-hand side solves
 // (K^-1 + Lambda_k / beta) mu' = eta - g + Lambda_k mu_k / beta.
 //
@@ -37,9 +47,10 @@
 
 namespace pg {
 
-// Entry offsets in the per-segment scratch (stride DevState::seg_stride).
-// Slot j holds segment j's contributions to its separators and, for the
-// reduced chain, the data of separator j (node j).
+// Entry offsets in the per-segment scratch, stored field-major:
+// sg[f * kMaxSeg + j] is field f of slot j.  Slot j holds segment j's
+// contributions to its separators and, for the reduced chain, the data of
+// separator j (node j).
 template <int n>
 struct SegLayout {
     static constexpr int DL = 0;              // Schur contribution to left separator
@@ -60,20 +71,41 @@ struct SegLayout {
     static constexpr int STRIDE = 7 * n * n + 5 * n;
 };
 
-// Entry offsets in the per-state scratch (stride DevState::ws_stride).
-template <int n>
-struct WsLayout {
-    static constexpr int PINV = 0;      // inverse of the interior pivot
-    static constexpr int GU = n * n;    // pivot^-1 U_i
-    static constexpr int HX = 2 * n * n;  // pivot^-1 X_i (fill towards left sep)
-    static constexpr int YV = 3 * n * n;  // pivot^-1 y_i
-    static constexpr int STRIDE = 3 * n * n + n;
+// Field f of slot j of the segment scratch.
+__device__ __forceinline__ double& sgv(double* sg, int j, int f) { return sg[(uint32_t)(f * kMaxSeg + j)]; }
+
+// Chain-order arrays are tiled in groups of kTile positions: entry e of
+// position q (E entries per position) is element ((q >> 5) * E + e) * 32 +
+// (q & 31).  A wave reading entry e of consecutive positions reads 256
+// contiguous bytes, and all entries of one position share one per-lane byte
+// offset (entry e adds the constant e * 256).  Views (plan range, trial
+// slot) start at a multiple of kTile positions.
+constexpr int kTile = 32;
+template <int E>
+__device__ __forceinline__ uint32_t toff(uint32_t pl) {
+    return ((pl >> 5) * (uint32_t)(E * kTile) + (pl & 31u)) * 8u;
+}
+template <int E>
+__device__ __forceinline__ int64_t tidx(int64_t q, int e) {
+    return ((q >> 5) * E + e) * kTile + (q & 31);
+}
+__device__ __forceinline__ double ldo(const double* base, uint32_t off, int e) {
+    return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + off + e * (kTile * 8));
+}
+__device__ __forceinline__ void sto(double* base, uint32_t off, int e, double v) {
+    *reinterpret_cast<double*>(reinterpret_cast<char*>(base) + off + e * (kTile * 8)) = v;
+}
+
+// Per-state temporaries of one sweep (views over the same positions): the
+// interior pivot inverse, pivot^-1 U_i, pivot^-1 X_i (fill towards the left
+// separator) and pivot^-1 y_i.
+struct Ws {
+    double *P, *G, *H, *Y;
 };
 
-// Blocks of the matrix being factored: D_i = a0 D0_i + a1 D1_i, U likewise
-// (D1/U1 may be null), right-hand side r_i = a0 R0_i + a1 R1_i.  Inputs are
-// SoA with stride S; the element for output index s is read at s + shift
-// (outputs of trial slot t live t * S further on).
+// Blocks of the matrix being factored: D_i = a0 D0_i + a1 D1_i, U likewise,
+// right-hand side r_i = a0 R0_i + a1 R1_i (a single source is passed twice
+// with a1 = 0).  All are chain-order views of the plan's range.
 struct BlockSrc {
     const double* D0;
     const double* D1;
@@ -82,13 +114,13 @@ struct BlockSrc {
     const double* R0;
     const double* R1;
     double a0, a1;
-    int64_t S, shift;
 };
 
 // Entry e of a matrix built as a0 X0 + a1 X1 (the same expression is used
 // when the accepted trial precision is written back).
 __device__ __forceinline__ double lin2(double a0, double x0, double a1, double x1) { return fma(a1, x1, a0 * x0); }
 
+// SoA blocks and vectors at 64-bit state indices (per-state kernels).
 template <int n>
 __device__ __forceinline__ void ld_soa(const double* __restrict__ X, int64_t S, int64_t s, double* M) {
 PG_UNROLL
@@ -100,13 +132,6 @@ PG_UNROLL
     for (int e = 0; e < n * n; ++e) X[e * S + s] = M[e];
 }
 template <int n>
-__device__ __forceinline__ void st_soa_sym(double* __restrict__ X, int64_t S, int64_t s, const double* M) {
-PG_UNROLL
-    for (int i = 0; i < n; ++i)
-PG_UNROLL
-        for (int j = 0; j < n; ++j) X[(i * n + j) * S + s] = 0.5 * (M[i * n + j] + M[j * n + i]);
-}
-template <int n>
 __device__ __forceinline__ void ld_vec(const double* __restrict__ X, int64_t S, int64_t s, double* v) {
 PG_UNROLL
     for (int e = 0; e < n; ++e) v[e] = X[e * S + s];
@@ -116,31 +141,55 @@ __device__ __forceinline__ void st_vec(double* __restrict__ X, int64_t S, int64_
 PG_UNROLL
     for (int e = 0; e < n; ++e) X[e * S + s] = v[e];
 }
-template <int n>
-__device__ __forceinline__ void ld_aos(const double* __restrict__ p, double* M, int cnt) {
-    for (int e = 0; e < cnt; ++e) M[e] = p[e];
-}
 
-template <int n>
-__device__ __forceinline__ void src_D(const BlockSrc& b, int64_t s, double* M) {
-    s += b.shift;
+// Blocks (CNT = n*n) and vectors (CNT = n) of a chain-order view at the
+// per-lane byte offset off (toff<CNT> of the position).
+template <int n, int CNT>
+__device__ __forceinline__ void ldt(const double* X, uint32_t off, double* M) {
 PG_UNROLL
-    for (int e = 0; e < n * n; ++e)
-        M[e] = b.D1 ? lin2(b.a0, b.D0[e * b.S + s], b.a1, b.D1[e * b.S + s]) : b.a0 * b.D0[e * b.S + s];
+    for (int e = 0; e < CNT; ++e) M[e] = ldo(X, off, e);
+}
+template <int n, int CNT>
+__device__ __forceinline__ void stt(double* X, uint32_t off, const double* M) {
+PG_UNROLL
+    for (int e = 0; e < CNT; ++e) sto(X, off, e, M[e]);
 }
 template <int n>
-__device__ __forceinline__ void src_U(const BlockSrc& b, int64_t s, double* M) {
-    s += b.shift;
+__device__ __forceinline__ void stt_sym(double* X, uint32_t off, const double* M) {
 PG_UNROLL
-    for (int e = 0; e < n * n; ++e)
-        M[e] = b.U1 ? lin2(b.a0, b.U0[e * b.S + s], b.a1, b.U1[e * b.S + s]) : b.a0 * b.U0[e * b.S + s];
+    for (int i = 0; i < n; ++i)
+PG_UNROLL
+        for (int j = 0; j < n; ++j) sto(X, off, i * n + j, 0.5 * (M[i * n + j] + M[j * n + i]));
+}
+// Raw loads of the two sources of a block (or vector) and their combination,
+// split so that loads issued one step ahead are combined one step later.
+template <int n, int CNT>
+__device__ __forceinline__ void ld2(const double* X0, const double* X1, uint32_t off, double* M0, double* M1) {
+PG_UNROLL
+    for (int e = 0; e < CNT; ++e) {
+        M0[e] = ldo(X0, off, e);
+        M1[e] = ldo(X1, off, e);
+    }
+}
+template <int n, int CNT>
+__device__ __forceinline__ void comb(double a0, const double* M0, double a1, const double* M1, double* M) {
+PG_UNROLL
+    for (int e = 0; e < CNT; ++e) M[e] = lin2(a0, M0[e], a1, M1[e]);
 }
 template <int n>
-__device__ __forceinline__ void src_r(const BlockSrc& b, int64_t s, double* v) {
-    s += b.shift;
+__device__ __forceinline__ void src_D(const BlockSrc& b, uint32_t off, double* M) {
 PG_UNROLL
-    for (int e = 0; e < n; ++e)
-        v[e] = b.R1 ? lin2(b.a0, b.R0[e * b.S + s], b.a1, b.R1[e * b.S + s]) : b.a0 * b.R0[e * b.S + s];
+    for (int e = 0; e < n * n; ++e) M[e] = lin2(b.a0, ldo(b.D0, off, e), b.a1, ldo(b.D1, off, e));
+}
+template <int n>
+__device__ __forceinline__ void src_U(const BlockSrc& b, uint32_t off, double* M) {
+PG_UNROLL
+    for (int e = 0; e < n * n; ++e) M[e] = lin2(b.a0, ldo(b.U0, off, e), b.a1, ldo(b.U1, off, e));
+}
+template <int n>
+__device__ __forceinline__ void src_r(const BlockSrc& b, uint32_t off, double* v) {
+PG_UNROLL
+    for (int e = 0; e < n; ++e) v[e] = lin2(b.a0, ldo(b.R0, off, e), b.a1, ldo(b.R1, off, e));
 }
 
 __device__ __forceinline__ void seg_bounds(int N, int nseg, int j, int& a, int& b, bool& hasL, bool& hasR) {
@@ -151,119 +200,151 @@ __device__ __forceinline__ void seg_bounds(int N, int nseg, int j, int& a, int& 
     a = st;
     b = hasR ? en - 2 : en - 1;
 }
-__device__ __forceinline__ int sep_state(int N, int nseg, int j) {
-    return (int)(((int64_t)(j + 1) * N) / nseg) - 1;
+
+__device__ __forceinline__ int seg_start(int N, int nseg, int j) { return (int)(((int64_t)j * N) / nseg); }
+__device__ __forceinline__ int sep_state(int N, int nseg, int j) { return seg_start(N, nseg, j + 1) - 1; }
+// Segment of state i: the largest j with seg_start(j) <= i.
+__device__ __forceinline__ int seg_of(int N, int nseg, int i) {
+    return (int)((((int64_t)i + 1) * nseg + N - 1) / N) - 1;
+}
+// Plan-local position of state i in the plan's chain range.
+__device__ __forceinline__ int64_t chain_pos(int N, int nseg, int i) {
+    const int j = seg_of(N, nseg, i);
+    return (int64_t)(i - seg_start(N, nseg, j)) * nseg + j;
+}
+// Length of the chain range: nseg columns of the longest segment's length.
+__device__ __forceinline__ int chain_len(int N, int nseg) { return (N + nseg - 1) / nseg * nseg; }
+
+// Plan-local positions of the states of segment j.
+struct SegPos {
+    int nseg, j, a0;
+    __device__ __forceinline__ uint32_t at(int i) const { return (uint32_t)((i - a0) * nseg + j); }
+};
+__device__ __forceinline__ SegPos seg_pos(int N, int nseg, int j) { return SegPos{nseg, j, seg_start(N, nseg, j)}; }
+// Position of separator j (the last state of segment j).
+__device__ __forceinline__ uint32_t sep_pos(int N, int nseg, int j) {
+    return seg_pos(N, nseg, j).at(sep_state(N, nseg, j));
 }
 
-// Forward elimination of the interior states of segment j.
+// Forward elimination of the interior states of segment j.  Matrix blocks
+// come from M, temporaries go to ws; both are chain-order views indexed
+// by plan-local positions.  The loop body has no branches: a missing left
+// separator is a zero fill X, the missing coupling after the last state is
+// a zero U; the blocks of state i + 1 are loaded at the top of step i and
+// combined at its end.
 template <int n, bool RHS>
-__device__ __forceinline__ bool seg_forward(const BlockSrc& M, int64_t off, int N, int nseg, int j, double* ws, int wsst,
-                            double* sg, double* logdet, TS ts) {
-    using W = WsLayout<n>;
+__device__ __forceinline__ bool seg_forward(const BlockSrc& M, int N, int nseg, int j, const Ws& ws, double* sg,
+                                            double* logdet, TS ts) {
     using G = SegLayout<n>;
+    constexpr int NN = n * n;
     int a, b;
     bool hasL, hasR;
     seg_bounds(N, nseg, j, a, b, hasL, hasR);
+    const SegPos ps = seg_pos(N, nseg, j);
     PG_MAT(P, ts);
     PG_MAT(X, ts);
     PG_MAT(Z, ts);
-    PG_MAT(U, ts);   // U_i of the current step
-    PG_MAT(Dn, ts);  // D_{i+1} and U_{i+1}, loaded one step ahead so the
-    PG_MAT(Un, ts);  // loads overlap the current step's arithmetic
+    PG_MAT(U, ts);
     PG_MAT(Pinv, ts);
     PG_MAT(GU, ts);
     PG_MAT(HX, ts);
-    PG_VEC(y, ts); PG_VEC(yv, ts); PG_VEC(rL, ts); PG_VEC(rn, ts);
-    src_D<n>(M, off + a, P);
-    if (hasL) {
-        src_U<n>(M, off + a - 1, Un);
+    PG_MAT(D0n, ts);  // raw blocks of the next state, loaded one step ahead
+    PG_MAT(D1n, ts);
+    PG_MAT(U0n, ts);
+    PG_MAT(U1n, ts);
+    PG_VEC(y, ts); PG_VEC(yv, ts); PG_VEC(rL, ts); PG_VEC(R0n, ts); PG_VEC(R1n, ts);
+    src_D<n>(M, toff<NN>(ps.at(a)), P);
+    src_U<n>(M, toff<NN>(ps.at(a)), U);  // every segment has >= 2 states, so U_a exists
+    {
+        PG_MAT(UL, ts);
+        src_U<n>(M, toff<NN>(hasL ? sep_pos(N, nseg, j - 1) : ps.at(a)), UL);
 PG_UNROLL
         for (int r = 0; r < n; ++r)
 PG_UNROLL
-            for (int c = 0; c < n; ++c) X[r * n + c] = Un[c * n + r];
-        mzero<n>(Z);
+            for (int c = 0; c < n; ++c) X[r * n + c] = hasL ? UL[c * n + r] : 0.0;
     }
-    if (a < b || hasR) src_U<n>(M, off + a, U);
+    mzero<n>(Z);
     if (RHS) {
-        src_r<n>(M, off + a, y);
+        src_r<n>(M, toff<n>(ps.at(a)), y);
 PG_UNROLL
         for (int e = 0; e < n; ++e) rL[e] = 0.0;
     }
     bool ok = true;
-    for (int i = a; i <= b; ++i) {
+    for (int i = a; i < b; ++i) {
         TS lt = ts;
-        const bool hasNext = (i < b) || hasR;
-        if (i < b) {
-            src_D<n>(M, off + i + 1, Dn);
-            if (i + 1 < b || hasR) src_U<n>(M, off + i + 1, Un);
-            if (RHS) src_r<n>(M, off + i + 1, rn);
-        }
+        const uint32_t q = ps.at(i), qn = ps.at(i + 1);
+        const uint32_t oB = toff<NN>(q), oV = toff<n>(q), oBn = toff<NN>(qn), oVn = toff<n>(qn);
+        const bool hasUn = (i + 1 < b) || hasR;
+        ld2<n, NN>(M.D0, M.D1, oBn, D0n, D1n);
+        ld2<n, NN>(M.U0, M.U1, oBn, U0n, U1n);
+        if (RHS) ld2<n, n>(M.R0, M.R1, oVn, R0n, R1n);
         ok = spd_inverse<n>(P, Pinv, RHS ? nullptr : logdet, lt) && ok;
-        double* w = ws + (off + i) * (int64_t)wsst;
-PG_UNROLL
-        for (int e = 0; e < n * n; ++e) w[W::PINV + e] = Pinv[e];
-        if (hasNext) {
-            mmul<n>(Pinv, U, GU);
-PG_UNROLL
-            for (int e = 0; e < n * n; ++e) w[W::GU + e] = GU[e];
-        }
-        if (hasL) {
-            mmul<n>(Pinv, X, HX);
-PG_UNROLL
-            for (int e = 0; e < n * n; ++e) w[W::HX + e] = HX[e];
-            msub_tn<n>(X, HX, Z);
-        }
+        if (!RHS) stt<n, NN>(ws.P, oB, Pinv);
+        mmul<n>(Pinv, U, GU);
+        stt<n, NN>(ws.G, oB, GU);
+        mmul<n>(Pinv, X, HX);
+        stt<n, NN>(ws.H, oB, HX);
+        msub_tn<n>(X, HX, Z);
         if (RHS) {
             mvec<n>(Pinv, y, yv);
-PG_UNROLL
-            for (int e = 0; e < n; ++e) w[W::YV + e] = yv[e];
-            if (hasL) mvec_tn_sub<n>(X, yv, rL);
+            stt<n, n>(ws.Y, oV, yv);
+            mvec_tn_sub<n>(X, yv, rL);
         }
-        if (i < b) {
-            mcopy<n>(Dn, P);
-            msub_tn<n>(U, GU, P);
-            if (hasL) {
-                PG_MAT(T, lt);
-                mmul_tn<n>(U, HX, T);
+        // X_{i+1} = -U^T HX, P_{i+1} = D_{i+1} - U^T GU, y_{i+1} = r_{i+1} - U^T yv
+        mmul_tn<n>(U, HX, X);
 PG_UNROLL
-                for (int e = 0; e < n * n; ++e) X[e] = -T[e];
+        for (int e = 0; e < n * n; ++e) X[e] = -X[e];
+        comb<n, n * n>(M.a0, D0n, M.a1, D1n, P);
+        msub_tn<n>(U, GU, P);
+        if (RHS) {
+            comb<n, n>(M.a0, R0n, M.a1, R1n, y);
+            mvec_tn_sub<n>(U, yv, y);
+        }
+PG_UNROLL
+        for (int e = 0; e < n * n; ++e) U[e] = hasUn ? lin2(M.a0, U0n[e], M.a1, U1n[e]) : 0.0;
+    }
+    {
+        // last interior state b: its Schur contributions to the separators
+        TS lt = ts;
+        const uint32_t q = ps.at(b), oB = toff<NN>(q), oV = toff<n>(q);
+        ok = spd_inverse<n>(P, Pinv, RHS ? nullptr : logdet, lt) && ok;
+        if (!RHS) stt<n, NN>(ws.P, oB, Pinv);
+        mmul<n>(Pinv, U, GU);
+        stt<n, NN>(ws.G, oB, GU);
+        mmul<n>(Pinv, X, HX);
+        stt<n, NN>(ws.H, oB, HX);
+        msub_tn<n>(X, HX, Z);
+        if (RHS) {
+            mvec<n>(Pinv, y, yv);
+            stt<n, n>(ws.Y, oV, yv);
+            mvec_tn_sub<n>(X, yv, rL);
+        }
+        PG_MAT(T, lt);
+        if (hasR) {
+            mmul_tn<n>(U, GU, T);
+PG_UNROLL
+            for (int e = 0; e < n * n; ++e) sgv(sg, j, G::DR + e) = -T[e];
+            if (RHS) {
+                PG_VEC(t, lt);
+PG_UNROLL
+                for (int e = 0; e < n; ++e) t[e] = 0.0;
+                mvec_tn_sub<n>(U, yv, t);
+PG_UNROLL
+                for (int e = 0; e < n; ++e) sgv(sg, j, G::RR + e) = t[e];
             }
+        }
+        if (hasL) {
+PG_UNROLL
+            for (int e = 0; e < n * n; ++e) sgv(sg, j, G::DL + e) = Z[e];
             if (RHS) {
 PG_UNROLL
-                for (int e = 0; e < n; ++e) y[e] = rn[e];
-                mvec_tn_sub<n>(U, yv, y);
+                for (int e = 0; e < n; ++e) sgv(sg, j, G::RL + e) = rL[e];
             }
-            if (i + 1 < b || hasR) mcopy<n>(Un, U);
-        } else {
-            double* g = sg + (int64_t)j * G::STRIDE;
-            if (hasR) {
-                PG_MAT(T, lt);
-                mmul_tn<n>(U, GU, T);
+        }
+        if (hasL && hasR) {
+            mmul_tn<n>(X, GU, T);
 PG_UNROLL
-                for (int e = 0; e < n * n; ++e) g[G::DR + e] = -T[e];
-                if (RHS) {
-                    PG_VEC(t, lt);
-PG_UNROLL
-                    for (int e = 0; e < n; ++e) t[e] = 0.0;
-                    mvec_tn_sub<n>(U, yv, t);
-PG_UNROLL
-                    for (int e = 0; e < n; ++e) g[G::RR + e] = t[e];
-                }
-            }
-            if (hasL) {
-PG_UNROLL
-                for (int e = 0; e < n * n; ++e) g[G::DL + e] = Z[e];
-                if (RHS) {
-PG_UNROLL
-                    for (int e = 0; e < n; ++e) g[G::RL + e] = rL[e];
-                }
-            }
-            if (hasL && hasR) {
-                PG_MAT(T, lt);
-                mmul_tn<n>(X, GU, T);
-PG_UNROLL
-                for (int e = 0; e < n * n; ++e) g[G::CLR + e] = -T[e];
-            }
+            for (int e = 0; e < n * n; ++e) sgv(sg, j, G::CLR + e) = -T[e];
         }
     }
     return ok;
@@ -277,39 +358,37 @@ PG_UNROLL
 __device__ __forceinline__ int cr_levels(int m) { return m > 0 ? 32 - __clz(m) : 0; }
 
 template <int n>
-__device__ __forceinline__ void ld_blk(const double* p, double* M) {
+__device__ __forceinline__ void ld_node(double* sg, int j, int f, double* M) {
 PG_UNROLL
-    for (int e = 0; e < n * n; ++e) M[e] = p[e];
+    for (int e = 0; e < n * n; ++e) M[e] = sgv(sg, j, f + e);
 }
 template <int n>
-__device__ __forceinline__ void st_blk(double* p, const double* M) {
+__device__ __forceinline__ void st_node(double* sg, int j, int f, const double* M) {
 PG_UNROLL
-    for (int e = 0; e < n * n; ++e) p[e] = M[e];
+    for (int e = 0; e < n * n; ++e) sgv(sg, j, f + e) = M[e];
 }
 
 // Node j's diagonal block, right coupling and rhs from its separator state
 // and the two adjacent segments.
 template <int n, bool RHS>
-__device__ __forceinline__ void cr_assemble(const BlockSrc& M, int64_t off, int N, int nseg, int j, double* sg, TS ts) {
+__device__ __forceinline__ void cr_assemble(const BlockSrc& M, int N, int nseg, int j, double* sg, TS ts) {
     using G = SegLayout<n>;
     const int m = nseg - 1;
-    const int s = sep_state(N, nseg, j);
-    double* gj = sg + (int64_t)j * G::STRIDE;
-    const double* gn = sg + (int64_t)(j + 1) * G::STRIDE;
+    const uint32_t q = sep_pos(N, nseg, j);
     PG_MAT(A, ts);
-    src_D<n>(M, off + s, A);
+    src_D<n>(M, toff<n * n>(q), A);
 PG_UNROLL
-    for (int e = 0; e < n * n; ++e) A[e] += gj[G::DR + e] + gn[G::DL + e];
-    st_blk<n>(gj + G::NA, A);
+    for (int e = 0; e < n * n; ++e) A[e] += sgv(sg, j, G::DR + e) + sgv(sg, j + 1, G::DL + e);
+    st_node<n>(sg, j, G::NA, A);
     if (j + 1 < m) {
 PG_UNROLL
-        for (int e = 0; e < n * n; ++e) gj[G::NC + e] = gn[G::CLR + e];
+        for (int e = 0; e < n * n; ++e) sgv(sg, j, G::NC + e) = sgv(sg, j + 1, G::CLR + e);
     }
     if (RHS) {
         PG_VEC(r, ts);
-        src_r<n>(M, off + s, r);
+        src_r<n>(M, toff<n>(q), r);
 PG_UNROLL
-        for (int e = 0; e < n; ++e) gj[G::NR + e] = r[e] + gj[G::RR + e] + gn[G::RL + e];
+        for (int e = 0; e < n; ++e) sgv(sg, j, G::NR + e) = r[e] + sgv(sg, j, G::RR + e) + sgv(sg, j + 1, G::RL + e);
     }
 }
 
@@ -323,7 +402,6 @@ __device__ __forceinline__ bool cr_forward(int m, int j, double* sg, double* log
     const int levels = cr_levels(m);
     const bool own = j < m;
     const int lv = own ? __builtin_ctz(j + 1) : -1;
-    double* gj = sg + (int64_t)(own ? j : 0) * G::STRIDE;
     bool ok = true;
     for (int l = 0; l < levels; ++l) {
         const int h = 1 << l;
@@ -333,27 +411,27 @@ __device__ __forceinline__ bool cr_forward(int m, int j, double* sg, double* log
             PG_MAT(P, lt);
             PG_MAT(C, lt);
             PG_MAT(T, lt);
-            ld_blk<n>(gj + G::NA, A);
+            ld_node<n>(sg, j, G::NA, A);
             ok = spd_inverse<n>(A, P, RHS ? nullptr : logdet, lt) && ok;
-            st_blk<n>(gj + G::NP, P);
+            st_node<n>(sg, j, G::NP, P);
             if (j - h >= 0) {
-                ld_blk<n>(sg + (int64_t)(j - h) * G::STRIDE + G::NC, C);  // M(L, k)
+                ld_node<n>(sg, j - h, G::NC, C);  // M(L, k)
                 mmul_nt<n>(P, C, T);
-                st_blk<n>(gj + G::NGL, T);
+                st_node<n>(sg, j, G::NGL, T);
             }
             if (j + h < m) {
-                ld_blk<n>(gj + G::NC, C);  // M(k, R)
+                ld_node<n>(sg, j, G::NC, C);  // M(k, R)
                 mmul<n>(P, C, T);
-                st_blk<n>(gj + G::NGR, T);
+                st_node<n>(sg, j, G::NGR, T);
             }
             if (RHS) {
                 PG_VEC(r, lt);
                 PG_VEC(z, lt);
 PG_UNROLL
-                for (int e = 0; e < n; ++e) r[e] = gj[G::NR + e];
+                for (int e = 0; e < n; ++e) r[e] = sgv(sg, j, G::NR + e);
                 mvec<n>(P, r, z);
 PG_UNROLL
-                for (int e = 0; e < n; ++e) gj[G::NZ + e] = z[e];
+                for (int e = 0; e < n; ++e) sgv(sg, j, G::NZ + e) = z[e];
             }
         }
         __syncthreads();
@@ -364,47 +442,47 @@ PG_UNROLL
             PG_MAT(Gk, lt);
             PG_VEC(r, lt);
             PG_VEC(z, lt);
-            ld_blk<n>(gj + G::NA, A);
+            ld_node<n>(sg, j, G::NA, A);
             if (RHS) {
 PG_UNROLL
-                for (int e = 0; e < n; ++e) r[e] = gj[G::NR + e];
+                for (int e = 0; e < n; ++e) r[e] = sgv(sg, j, G::NR + e);
             }
             if (j + h < m) {
                 // right neighbour k = j + h: A -= M(j,k) G_L(k), r -= M(j,k) z_k,
                 // new coupling to k + h: -M(j,k) G_R(k)
-                const double* gk = sg + (int64_t)(j + h) * G::STRIDE;
-                ld_blk<n>(gj + G::NC, C);
-                ld_blk<n>(gk + G::NGL, Gk);
+                const int k = j + h;
+                ld_node<n>(sg, j, G::NC, C);
+                ld_node<n>(sg, k, G::NGL, Gk);
                 msub<n>(C, Gk, A);
                 if (RHS) {
 PG_UNROLL
-                    for (int e = 0; e < n; ++e) z[e] = gk[G::NZ + e];
+                    for (int e = 0; e < n; ++e) z[e] = sgv(sg, k, G::NZ + e);
                     mvec_sub<n>(C, z, r);
                 }
                 if (j + 2 * h < m) {
                     PG_MAT(T, lt);
-                    ld_blk<n>(gk + G::NGR, Gk);
+                    ld_node<n>(sg, k, G::NGR, Gk);
                     mmul<n>(C, Gk, T);
 PG_UNROLL
-                    for (int e = 0; e < n * n; ++e) gj[G::NC + e] = -T[e];
+                    for (int e = 0; e < n * n; ++e) sgv(sg, j, G::NC + e) = -T[e];
                 }
             }
             if (j - h >= 0) {
                 // left neighbour k = j - h: A -= M(k,j)^T G_R(k), r -= M(k,j)^T z_k
-                const double* gk = sg + (int64_t)(j - h) * G::STRIDE;
-                ld_blk<n>(gk + G::NC, C);
-                ld_blk<n>(gk + G::NGR, Gk);
+                const int k = j - h;
+                ld_node<n>(sg, k, G::NC, C);
+                ld_node<n>(sg, k, G::NGR, Gk);
                 msub_tn<n>(C, Gk, A);
                 if (RHS) {
 PG_UNROLL
-                    for (int e = 0; e < n; ++e) z[e] = gk[G::NZ + e];
+                    for (int e = 0; e < n; ++e) z[e] = sgv(sg, k, G::NZ + e);
                     mvec_tn_sub<n>(C, z, r);
                 }
             }
-            st_blk<n>(gj + G::NA, A);
+            st_node<n>(sg, j, G::NA, A);
             if (RHS) {
 PG_UNROLL
-                for (int e = 0; e < n; ++e) gj[G::NR + e] = r[e];
+                for (int e = 0; e < n; ++e) sgv(sg, j, G::NR + e) = r[e];
             }
         }
         __syncthreads();
@@ -419,20 +497,18 @@ PG_UNROLL
 // Writes S_kk (node and SDo) and the cross-covariances of the two new
 // adjacent pairs (L, k) and (k, R).  run = false keeps the barriers only.
 template <int n>
-__device__ __forceinline__ void cr_backward_cov(int m, int j, bool run, int64_t off, int N, int nseg, double* sg,
-                                                double* SDo, int64_t S, TS ts) {
+__device__ __forceinline__ void cr_backward_cov(int m, int j, bool run, int N, int nseg, double* sg, double* SDo,
+                                                TS ts) {
     using G = SegLayout<n>;
     const int levels = cr_levels(m);
     const bool own = run && j < m;
     const int lv = own ? __builtin_ctz(j + 1) : -1;
-    double* gj = sg + (int64_t)(own ? j : 0) * G::STRIDE;
     for (int l = levels - 1; l >= 0; --l) {
         const int h = 1 << l;
         if (own && lv == l) {
             TS lt = ts;
             const bool hasL = j - h >= 0, hasR = j + h < m;
-            double* gl = sg + (int64_t)(hasL ? j - h : j) * G::STRIDE;
-            const double* gr = sg + (int64_t)(hasR ? j + h : j) * G::STRIDE;
+            const int L = j - h, R = j + h;
             PG_MAT(Sk, lt);
             PG_MAT(GL, lt);
             PG_MAT(GR, lt);
@@ -440,12 +516,12 @@ __device__ __forceinline__ void cr_backward_cov(int m, int j, bool run, int64_t 
             PG_MAT(CR, lt);
             PG_MAT(X, lt);
             PG_MAT(T, lt);
-            ld_blk<n>(gj + G::NP, Sk);
-            if (hasL) ld_blk<n>(gj + G::NGL, GL);
-            if (hasR) ld_blk<n>(gj + G::NGR, GR);
-            if (hasL && hasR) ld_blk<n>(gl + G::NX, X);  // Cov(L, R)
+            ld_node<n>(sg, j, G::NP, Sk);
+            if (hasL) ld_node<n>(sg, j, G::NGL, GL);
+            if (hasR) ld_node<n>(sg, j, G::NGR, GR);
+            if (hasL && hasR) ld_node<n>(sg, L, G::NX, X);  // Cov(L, R)
             if (hasL) {
-                ld_blk<n>(gl + G::NA, T);  // S_LL
+                ld_node<n>(sg, L, G::NA, T);  // S_LL
                 mmul<n>(GL, T, CL);
                 if (hasR) {
                     // + G_R S_RL, S_RL = X^T
@@ -459,7 +535,7 @@ PG_UNROLL
                 msub_nt<n>(CL, GL, Sk);
             }
             if (hasR) {
-                ld_blk<n>(gr + G::NA, T);  // S_RR
+                ld_node<n>(sg, R, G::NA, T);  // S_RR
                 mmul<n>(GR, T, CR);
                 if (hasL) {
                     PG_MAT(U, lt);
@@ -471,15 +547,15 @@ PG_UNROLL
                 for (int e = 0; e < n * n; ++e) CR[e] = -CR[e];
                 msub_nt<n>(CR, GR, Sk);
             }
-            st_blk<n>(gj + G::NA, Sk);
-            st_soa_sym<n>(SDo, S, off + sep_state(N, nseg, j), Sk);
+            st_node<n>(sg, j, G::NA, Sk);
+            stt_sym<n>(SDo, toff<n * n>(sep_pos(N, nseg, j)), Sk);
             if (hasL) {
 PG_UNROLL
                 for (int r = 0; r < n; ++r)
 PG_UNROLL
-                    for (int c = 0; c < n; ++c) gl[G::NX + r * n + c] = CL[c * n + r];  // Cov(L, k)
+                    for (int c = 0; c < n; ++c) sgv(sg, L, G::NX + r * n + c) = CL[c * n + r];  // Cov(L, k)
             }
-            if (hasR) st_blk<n>(gj + G::NX, CR);  // Cov(k, R)
+            if (hasR) st_node<n>(sg, j, G::NX, CR);  // Cov(k, R)
         }
         __syncthreads();
     }
@@ -487,13 +563,12 @@ PG_UNROLL
 
 // Backward substitution: x_k = z_k - G_L x_L - G_R x_R, top level first.
 template <int n>
-__device__ __forceinline__ void cr_backward_rhs(int m, int j, bool run, int64_t off, int N, int nseg, double* sg,
-                                                double* xo, int64_t S, TS ts) {
+__device__ __forceinline__ void cr_backward_rhs(int m, int j, bool run, int N, int nseg, double* sg, double* xo,
+                                                TS ts) {
     using G = SegLayout<n>;
     const int levels = cr_levels(m);
     const bool own = run && j < m;
     const int lv = own ? __builtin_ctz(j + 1) : -1;
-    double* gj = sg + (int64_t)(own ? j : 0) * G::STRIDE;
     for (int l = levels - 1; l >= 0; --l) {
         const int h = 1 << l;
         if (own && lv == l) {
@@ -502,54 +577,62 @@ __device__ __forceinline__ void cr_backward_rhs(int m, int j, bool run, int64_t 
             PG_VEC(y, lt);
             PG_MAT(Gk, lt);
 PG_UNROLL
-            for (int e = 0; e < n; ++e) x[e] = gj[G::NZ + e];
+            for (int e = 0; e < n; ++e) x[e] = sgv(sg, j, G::NZ + e);
             if (j - h >= 0) {
-                const double* gl = sg + (int64_t)(j - h) * G::STRIDE;
-                ld_blk<n>(gj + G::NGL, Gk);
+                ld_node<n>(sg, j, G::NGL, Gk);
 PG_UNROLL
-                for (int e = 0; e < n; ++e) y[e] = gl[G::XS + e];
+                for (int e = 0; e < n; ++e) y[e] = sgv(sg, j - h, G::XS + e);
                 mvec_sub<n>(Gk, y, x);
             }
             if (j + h < m) {
-                const double* gr = sg + (int64_t)(j + h) * G::STRIDE;
-                ld_blk<n>(gj + G::NGR, Gk);
+                ld_node<n>(sg, j, G::NGR, Gk);
 PG_UNROLL
-                for (int e = 0; e < n; ++e) y[e] = gr[G::XS + e];
+                for (int e = 0; e < n; ++e) y[e] = sgv(sg, j + h, G::XS + e);
                 mvec_sub<n>(Gk, y, x);
             }
 PG_UNROLL
-            for (int e = 0; e < n; ++e) gj[G::XS + e] = x[e];
-            st_vec<n>(xo, S, off + sep_state(N, nseg, j), x);
+            for (int e = 0; e < n; ++e) sgv(sg, j, G::XS + e) = x[e];
+            stt<n, n>(xo, toff<n>(sep_pos(N, nseg, j)), x);
         }
         __syncthreads();
     }
 }
 
-// Backward recovery of segment j's interior marginals.
+// Backward recovery of segment j's interior marginals, top state first.
+// With x_i = P_i^-1 y_i - GU_i x_next - HX_i x_L:
+//   Cov(i, next) = -(GU S_nn + HX S_Ln),  Cov(i, L) = -(GU S_nL + HX S_LL),
+//   Sigma_ii = P_i^-1 - Cov(i, next) GU^T - Cov(i, L) HX^T.
+// Branch-free: the forward sweep stored zero GU after the chain's last state
+// and zero HX where there is no left separator; missing separator
+// covariances are zero blocks.
 template <int n>
-__device__ __forceinline__ void seg_backward_cov(int64_t off, int N, int nseg, int j, const double* ws, int wsst,
-                                 const double* sg, double* SDo, double* SUo, int64_t S, TS ts) {
-    using W = WsLayout<n>;
+__device__ __forceinline__ void seg_backward_cov(int N, int nseg, int j, const Ws& ws, double* sg, double* SDo,
+                                                 double* SUo, TS ts) {
     using G = SegLayout<n>;
+    constexpr int NN = n * n;
     int a, b;
     bool hasL, hasR;
     seg_bounds(N, nseg, j, a, b, hasL, hasR);
+    const SegPos ps = seg_pos(N, nseg, j);
+    const uint32_t qL = hasL ? sep_pos(N, nseg, j - 1) : ps.at(a);
+    const uint32_t qR = hasR ? ps.at(b + 1) : ps.at(b);
     PG_MAT(SLL, ts);
     PG_MAT(Snn, ts);
     PG_MAT(SnL, ts);
-    if (hasL) ld_soa<n>(SDo, S, off + a - 1, SLL);
-    if (hasR) {
-        ld_soa<n>(SDo, S, off + b + 1, Snn);
-        if (hasL) {
-            const double* cr = sg + (int64_t)(j - 1) * G::STRIDE + G::NX;  // Cov(L, R)
+    ldt<n, NN>(SDo, toff<NN>(qL), SLL);
+    ldt<n, NN>(SDo, toff<NN>(qR), Snn);
 PG_UNROLL
-            for (int r = 0; r < n; ++r)
-PG_UNROLL
-                for (int c = 0; c < n; ++c) SnL[r * n + c] = cr[c * n + r];
-        }
+    for (int e = 0; e < n * n; ++e) {
+        SLL[e] = hasL ? SLL[e] : 0.0;
+        Snn[e] = hasR ? Snn[e] : 0.0;
     }
-    // blocks of the forward sweep for the current state (c) and, loaded one
-    // step ahead, for the next state down the segment (n)
+    // Cov(R, L) = Cov(L, R)^T, Cov(L, R) = Cov(sep j-1, sep j)
+PG_UNROLL
+    for (int r = 0; r < n; ++r)
+PG_UNROLL
+        for (int c = 0; c < n; ++c) SnL[r * n + c] = (hasL && hasR) ? sgv(sg, j - 1, G::NX + c * n + r) : 0.0;
+    // forward-sweep blocks of the current state (c) and, loaded one step
+    // ahead, of the state below it (n)
     PG_MAT(Pc, ts);
     PG_MAT(Gc, ts);
     PG_MAT(Hc, ts);
@@ -557,75 +640,38 @@ PG_UNROLL
     PG_MAT(Gn, ts);
     PG_MAT(Hn, ts);
     {
-        const double* w = ws + (off + b) * (int64_t)wsst;
-PG_UNROLL
-        for (int e = 0; e < n * n; ++e) Pc[e] = w[W::PINV + e];
-        if (hasR) {
-PG_UNROLL
-            for (int e = 0; e < n * n; ++e) Gc[e] = w[W::GU + e];
-        }
-        if (hasL) {
-PG_UNROLL
-            for (int e = 0; e < n * n; ++e) Hc[e] = w[W::HX + e];
-        }
+        const uint32_t ob = toff<NN>(ps.at(b));
+        ldt<n, NN>(ws.P, ob, Pc);
+        ldt<n, NN>(ws.G, ob, Gc);
+        ldt<n, NN>(ws.H, ob, Hc);
     }
     for (int i = b; i >= a; --i) {
         TS lt = ts;
-        const bool hasNext = (i < b) || hasR;
-        if (i > a) {
-            const double* w = ws + (off + i - 1) * (int64_t)wsst;
-PG_UNROLL
-            for (int e = 0; e < n * n; ++e) Pn[e] = w[W::PINV + e];
-PG_UNROLL
-            for (int e = 0; e < n * n; ++e) Gn[e] = w[W::GU + e];
-            if (hasL) {
-PG_UNROLL
-                for (int e = 0; e < n * n; ++e) Hn[e] = w[W::HX + e];
-            }
-        }
-        // Pc becomes Sigma_ii in place
-        PG_MAT(SiL, lt);
+        const uint32_t oB = toff<NN>(ps.at(i)), oBp = toff<NN>(ps.at(i > a ? i - 1 : a));
+        ldt<n, NN>(ws.P, oBp, Pn);
+        ldt<n, NN>(ws.G, oBp, Gn);
+        ldt<n, NN>(ws.H, oBp, Hn);
         PG_MAT(Sin, lt);
+        PG_MAT(SiL, lt);
         PG_MAT(T, lt);
-        if (hasNext) {
-            // Cov(i, next) = -GU Snn - HX SnL^T
-            mmul<n>(Gc, Snn, Sin);
-            if (hasL) {
-                mmul_nt<n>(Hc, SnL, T);
+        // Sin = -(GU S_nn + HX S_nL^T), SiL = -(GU S_nL + HX S_LL)
+        mmul<n>(Gc, Snn, Sin);
+        mmul_nt<n>(Hc, SnL, T);
+        mmul<n>(Gc, SnL, SiL);
 PG_UNROLL
-                for (int e = 0; e < n * n; ++e) Sin[e] += T[e];
-                // Cov(i, L) = -GU SnL - HX SLL
-                mmul<n>(Gc, SnL, SiL);
-                mmul<n>(Hc, SLL, T);
+        for (int e = 0; e < n * n; ++e) Sin[e] = -(Sin[e] + T[e]);
+        mmul<n>(Hc, SLL, T);
 PG_UNROLL
-                for (int e = 0; e < n * n; ++e) SiL[e] = -(SiL[e] + T[e]);
-                // Sigma_ii = Pinv + G Sin^T + Hh SiL^T with G = -GU, Hh = -HX
-                mmul_nt<n>(Hc, SiL, T);
-PG_UNROLL
-                for (int e = 0; e < n * n; ++e) Pc[e] -= T[e];
-            }
-PG_UNROLL
-            for (int e = 0; e < n * n; ++e) Sin[e] = -Sin[e];
-            mmul_nt<n>(Gc, Sin, T);
-PG_UNROLL
-            for (int e = 0; e < n * n; ++e) Pc[e] -= T[e];
-            st_soa<n>(SUo, S, off + i, Sin);
-        } else if (hasL) {
-            mmul<n>(Hc, SLL, SiL);
-PG_UNROLL
-            for (int e = 0; e < n * n; ++e) SiL[e] = -SiL[e];
-            mmul_nt<n>(Hc, SiL, T);
-PG_UNROLL
-            for (int e = 0; e < n * n; ++e) Pc[e] -= T[e];
-        }
-        st_soa_sym<n>(SDo, S, off + i, Pc);
+        for (int e = 0; e < n * n; ++e) SiL[e] = -(SiL[e] + T[e]);
+        msub_nt<n>(Sin, Gc, Pc);
+        msub_nt<n>(SiL, Hc, Pc);
+        stt<n, NN>(SUo, oB, Sin);
+        stt_sym<n>(SDo, oB, Pc);
         mcopy<n>(Pc, Snn);
-        if (hasL) mcopy<n>(SiL, SnL);
-        if (i > a) {
-            mcopy<n>(Pn, Pc);
-            mcopy<n>(Gn, Gc);
-            if (hasL) mcopy<n>(Hn, Hc);
-        }
+        mcopy<n>(SiL, SnL);
+        mcopy<n>(Pn, Pc);
+        mcopy<n>(Gn, Gc);
+        mcopy<n>(Hn, Hc);
     }
     if (hasL) {
         // Cov(L, a) = Cov(a, L)^T
@@ -634,72 +680,70 @@ PG_UNROLL
         for (int r = 0; r < n; ++r)
 PG_UNROLL
             for (int c = 0; c < n; ++c) T[r * n + c] = SnL[c * n + r];
-        st_soa<n>(SUo, S, off + a - 1, T);
+        stt<n, NN>(SUo, toff<NN>(qL), T);
     }
 }
 
+// Backward substitution of segment j: x_i = P_i^-1 y_i - GU_i x_next - HX_i x_L.
 template <int n>
-__device__ __forceinline__ void seg_backward_rhs(int64_t off, int N, int nseg, int j, const double* ws, int wsst,
-                                 const double* sg, double* xo, int64_t S, TS ts) {
-    using W = WsLayout<n>;
+__device__ __forceinline__ void seg_backward_rhs(int N, int nseg, int j, const Ws& ws, double* sg, double* xo,
+                                                 TS ts) {
     using G = SegLayout<n>;
+    constexpr int NN = n * n;
     int a, b;
     bool hasL, hasR;
     seg_bounds(N, nseg, j, a, b, hasL, hasR);
+    const SegPos ps = seg_pos(N, nseg, j);
     PG_VEC(xL, ts); PG_VEC(xn, ts);
-    if (hasL) {
-        const double* p = sg + (int64_t)(j - 1) * G::STRIDE + G::XS;
 PG_UNROLL
-        for (int e = 0; e < n; ++e) xL[e] = p[e];
+    for (int e = 0; e < n; ++e) {
+        xL[e] = hasL ? sgv(sg, j - 1, G::XS + e) : 0.0;
+        xn[e] = hasR ? sgv(sg, j, G::XS + e) : 0.0;
     }
-    if (hasR) {
-        const double* p = sg + (int64_t)j * G::STRIDE + G::XS;
-PG_UNROLL
-        for (int e = 0; e < n; ++e) xn[e] = p[e];
-    }
+    PG_MAT(Gc, ts);
+    PG_MAT(Hc, ts);
+    PG_VEC(yc, ts);
+    PG_MAT(Gn, ts);
+    PG_MAT(Hn, ts);
+    PG_VEC(yn, ts);
+    ldt<n, NN>(ws.G, toff<NN>(ps.at(b)), Gc);
+    ldt<n, NN>(ws.H, toff<NN>(ps.at(b)), Hc);
+    ldt<n, n>(ws.Y, toff<n>(ps.at(b)), yc);
     for (int i = b; i >= a; --i) {
         TS lt = ts;
-        const double* w = ws + (off + i) * (int64_t)wsst;
-        const bool hasNext = (i < b) || hasR;
+        const uint32_t q = ps.at(i), qp = ps.at(i > a ? i - 1 : a);
+        const uint32_t oBp = toff<NN>(qp), oVp = toff<n>(qp);
+        ldt<n, NN>(ws.G, oBp, Gn);
+        ldt<n, NN>(ws.H, oBp, Hn);
+        ldt<n, n>(ws.Y, oVp, yn);
         PG_VEC(x, lt);
-        PG_VEC(t, lt);
 PG_UNROLL
-        for (int e = 0; e < n; ++e) x[e] = w[W::YV + e];
-        if (hasNext) {
-            PG_MAT(GUi, lt);
-PG_UNROLL
-            for (int e = 0; e < n * n; ++e) GUi[e] = w[W::GU + e];
-            mvec<n>(GUi, xn, t);
-PG_UNROLL
-            for (int e = 0; e < n; ++e) x[e] -= t[e];
-        }
-        if (hasL) {
-            PG_MAT(HXi, lt);
-PG_UNROLL
-            for (int e = 0; e < n * n; ++e) HXi[e] = w[W::HX + e];
-            mvec<n>(HXi, xL, t);
-PG_UNROLL
-            for (int e = 0; e < n; ++e) x[e] -= t[e];
-        }
-        st_vec<n>(xo, S, off + i, x);
+        for (int e = 0; e < n; ++e) x[e] = yc[e];
+        mvec_sub<n>(Gc, xn, x);
+        mvec_sub<n>(Hc, xL, x);
+        stt<n, n>(xo, toff<n>(q), x);
 PG_UNROLL
         for (int e = 0; e < n; ++e) xn[e] = x[e];
+        mcopy<n>(Gn, Gc);
+        mcopy<n>(Hn, Hc);
+PG_UNROLL
+        for (int e = 0; e < n; ++e) yc[e] = yn[e];
     }
 }
 
-// Workgroup-wide GBP: marginals of (D, U) from src into (SDo, SUo).  Called
-// by every lane of the half (tid = lane); sh_ld / sh_ok hold
-// kChainThreads + 1 entries.
+// Workgroup-wide GBP of the matrix in M into (SDo, SUo), log det
+// and PD flag; all arrays offset to the plan's chain range.  Called by every
+// lane of the half (tid = lane); sh_ld / sh_ok hold kChainThreads + 1 entries.
 template <int n>
-__device__ __forceinline__ bool wg_gbp(const BlockSrc& M, const DevState& st, double* ws, int tid, int64_t off,
-                                       int64_t So, int N, int nseg, double* sg, double* SDo, double* SUo,
-                                       double* logdet_out, double* sh_ld, int* sh_ok, TS ts) {
+__device__ __forceinline__ bool wg_gbp(const BlockSrc& M, const Ws& ws, int tid, int N, int nseg, double* sg,
+                                       double* SDo, double* SUo, double* logdet_out, double* sh_ld, int* sh_ok,
+                                       TS ts) {
     const int m = nseg - 1;
     double ld = 0.0;
     bool ok = true;
-    if (tid < nseg) ok = seg_forward<n, false>(M, off, N, nseg, tid, ws, st.ws_stride, sg, &ld, ts);
+    if (tid < nseg) ok = seg_forward<n, false>(M, N, nseg, tid, ws, sg, &ld, ts);
     __syncthreads();
-    if (tid < m) cr_assemble<n, false>(M, off, N, nseg, tid, sg, ts);
+    if (tid < m) cr_assemble<n, false>(M, N, nseg, tid, sg, ts);
     __syncthreads();
     ok = cr_forward<n, false>(m, tid, sg, &ld, ts) && ok;
     sh_ld[tid] = ld;
@@ -718,22 +762,22 @@ __device__ __forceinline__ bool wg_gbp(const BlockSrc& M, const DevState& st, do
     __syncthreads();
     const bool okall = sh_ok[kChainThreads] != 0;
     *logdet_out = sh_ld[kChainThreads];
-    cr_backward_cov<n>(m, tid, okall, off, N, nseg, sg, SDo, So, ts);
-    if (okall && tid < nseg) seg_backward_cov<n>(off, N, nseg, tid, ws, st.ws_stride, sg, SDo, SUo, So, ts);
+    cr_backward_cov<n>(m, tid, okall, N, nseg, sg, SDo, ts);
+    if (okall && tid < nseg) seg_backward_cov<n>(N, nseg, tid, ws, sg, SDo, SUo, ts);
     __syncthreads();
     return okall;
 }
 
 // Workgroup-wide solve of (D, U) x = r into xo (same barriers as wg_gbp).
 template <int n>
-__device__ __forceinline__ bool wg_solve(const BlockSrc& M, const DevState& st, double* ws, int tid, int64_t off,
-                                         int64_t So, int N, int nseg, double* sg, double* xo, int* sh_ok, TS ts) {
+__device__ __forceinline__ bool wg_solve(const BlockSrc& M, const Ws& ws, int tid, int N, int nseg, double* sg,
+                                         double* xo, int* sh_ok, TS ts) {
     const int m = nseg - 1;
     double ld = 0.0;
     bool ok = true;
-    if (tid < nseg) ok = seg_forward<n, true>(M, off, N, nseg, tid, ws, st.ws_stride, sg, &ld, ts);
+    if (tid < nseg) ok = seg_forward<n, true>(M, N, nseg, tid, ws, sg, &ld, ts);
     __syncthreads();
-    if (tid < m) cr_assemble<n, true>(M, off, N, nseg, tid, sg, ts);
+    if (tid < m) cr_assemble<n, true>(M, N, nseg, tid, sg, ts);
     __syncthreads();
     ok = cr_forward<n, true>(m, tid, sg, &ld, ts) && ok;
     sh_ok[tid] = ok ? 1 : 0;
@@ -745,8 +789,8 @@ __device__ __forceinline__ bool wg_solve(const BlockSrc& M, const DevState& st, 
     }
     __syncthreads();
     const bool okall = sh_ok[kChainThreads] != 0;
-    cr_backward_rhs<n>(m, tid, okall, off, N, nseg, sg, xo, So, ts);
-    if (okall && tid < nseg) seg_backward_rhs<n>(off, N, nseg, tid, ws, st.ws_stride, sg, xo, So, ts);
+    cr_backward_rhs<n>(m, tid, okall, N, nseg, sg, xo, ts);
+    if (okall && tid < nseg) seg_backward_rhs<n>(N, nseg, tid, ws, sg, xo, ts);
     __syncthreads();
     return okall;
 }
@@ -854,7 +898,6 @@ __device__ __forceinline__ double wg_sum(double v, double* sh) {
     __syncthreads();
     return r;
 }
-
 // Scratch of (plan, trial slot, half): half 0 serves the marginals, half 1
 // the mean solve of the same trial, which run side by side.
 template <int n>
@@ -865,54 +908,84 @@ template <int n>
 __device__ __forceinline__ TS thread_ws(const DevState& st, int pid, int t) {
     return TS{st.tws + (((int64_t)pid * st.W + t) * kTrialThreads + threadIdx.x) * st.tws_stride};
 }
-__device__ __forceinline__ double* state_ws(const DevState& st, int half) {
-    return st.ws + (int64_t)half * st.W * st.S * st.ws_stride;
+// Sweep temporaries of one half for the chain range starting at position c0
+// (trial slot included): four tiled arrays of W * Sc positions each.
+template <int n>
+__device__ __forceinline__ Ws sweep_ws(const DevState& st, int half, int64_t c0) {
+    const int64_t cap = (int64_t)st.W * st.Sc;
+    double* base = st.ws + (int64_t)half * (3 * n * n + n) * cap;
+    return Ws{base + c0 * n * n, base + cap * n * n + c0 * n * n, base + 2 * cap * n * n + c0 * n * n,
+              base + 3 * cap * n * n + c0 * n};
 }
 
 // Set-up and marginals of a plan (trial slot 0 of its scratch):
 // CHAIN_INIT: Lambda = K^-1, mean = solve(K^-1, eta), marginals, budget reset;
 // CHAIN_REINIT: Lambda = K^-1 (mean kept), marginals;
 // CHAIN_MARGINALS: marginals of the current Lambda.
+// The inputs are first copied into chain order, the results (trial slot 0)
+// are copied back in state order.
 template <int n>
 __global__ void __launch_bounds__(kChainThreads) chain_kernel(DevState st, int mode, int plan_lo) {
     __shared__ double sh_d[kChainThreads + 1];
     __shared__ int sh_i[kChainThreads + 1];
+    constexpr int NN = n * n;
     const int pid = plan_lo + blockIdx.x;
     PlanDev& p = st.plans[pid];
     if (!p.active) return;
     const int tid = threadIdx.x;
-    const int N = p.N;
-    const int64_t off = p.off;
-    const int64_t S = st.S;
-    const int nseg = p.nseg;
+    const int N = p.N, nseg = p.nseg;
+    const int64_t off = p.off, S = st.S, coff = p.coff;
     double* sg = seg_scratch<n>(st, pid, 0, 0);
-    double* ws = state_ws(st, 0);
+    const Ws ws = sweep_ws<n>(st, 0, coff);
     TS ts = thread_ws<n>(st, pid, 0);
-    const int n2 = n * n;
-    if (mode == CHAIN_INIT || mode == CHAIN_REINIT) {
-        for (int i = tid; i < N; i += kChainThreads) {
-            for (int e = 0; e < n2; ++e) {
-                st.LD[e * S + off + i] = st.KD[e * S + off + i];
-                st.LU[e * S + off + i] = st.KU[e * S + off + i];
+    const bool prior = mode == CHAIN_INIT || mode == CHAIN_REINIT;
+    // precision to factor (K^-1 or the current Lambda) in chain order
+    double* cD = prior ? st.cKD : st.cLD;
+    double* cU = prior ? st.cKU : st.cLU;
+    for (int i = tid; i < N; i += kChainThreads) {
+        const int64_t s = off + i, q = coff + chain_pos(N, nseg, i);
+        for (int e = 0; e < NN; ++e) {
+            const double d = prior ? st.KD[e * S + s] : st.LD[e * S + s];
+            cD[tidx<NN>(q, e)] = d;
+            if (prior) st.LD[e * S + s] = d;
+            if (i < N - 1) {
+                const double u = prior ? st.KU[e * S + s] : st.LU[e * S + s];
+                cU[tidx<NN>(q, e)] = u;
+                if (prior) st.LU[e * S + s] = u;
             }
         }
-        __syncthreads();
-        if (mode == CHAIN_INIT) {
-            BlockSrc M{st.KD, nullptr, st.KU, nullptr, st.eta, nullptr, 1.0, 0.0, S, 0};
-            wg_solve<n>(M, st, ws, tid, off, S, N, nseg, sg, st.mu, sh_i, ts);
-            if (tid == 0) {
-                p.iters_left = p.n_iters;
-                p.iters_done = 0;
-                p.trials_total = 0;
-            }
+        if (mode == CHAIN_INIT)
+            for (int e = 0; e < n; ++e) st.crb[tidx<n>(q, e)] = st.eta[e * S + s];
+    }
+    __syncthreads();
+    if (mode == CHAIN_INIT) {
+        const double *kd = st.cKD + coff * NN, *ku = st.cKU + coff * NN, *r = st.crb + coff * n;
+        BlockSrc M{kd, kd, ku, ku, r, r, 1.0, 0.0};
+        wg_solve<n>(M, ws, tid, N, nseg, sg, st.Tmu + coff * n, sh_i, ts);
+        if (tid == 0) {
+            p.iters_left = p.n_iters;
+            p.iters_done = 0;
+            p.trials_total = 0;
         }
     }
-    BlockSrc M{st.LD, nullptr, st.LU, nullptr, nullptr, nullptr, 1.0, 0.0, S, 0};
+    const double *d = cD + coff * NN, *u = cU + coff * NN;
+    BlockSrc M{d, d, u, u, d, d, 1.0, 0.0};
     double ld = 0.0;
-    const bool ok = wg_gbp<n>(M, st, ws, tid, off, S, N, nseg, sg, st.SD, st.SU, &ld, sh_d, sh_i, ts);
+    const bool ok = wg_gbp<n>(M, ws, tid, N, nseg, sg, st.TSD + coff * NN, st.TSU + coff * NN, &ld, sh_d, sh_i, ts);
     if (tid == 0) {
         p.logdet = ok ? ld : NAN;
         p.status = ok ? 0 : PGVIMP_ENOTPD;
+    }
+    for (int i = tid; i < N; i += kChainThreads) {
+        const int64_t s = off + i, q = coff + chain_pos(N, nseg, i);
+        if (ok) {
+            for (int e = 0; e < NN; ++e) {
+                st.SD[e * S + s] = st.TSD[tidx<NN>(q, e)];
+                if (i < N - 1) st.SU[e * S + s] = st.TSU[tidx<NN>(q, e)];
+            }
+        }
+        if (mode == CHAIN_INIT)
+            for (int e = 0; e < n; ++e) st.mu[e * S + s] = st.Tmu[tidx<n>(q, e)];
     }
 }
 
@@ -920,13 +993,15 @@ __global__ void __launch_bounds__(kChainThreads) chain_kernel(DevState st, int m
 __device__ __forceinline__ double block_sum(double v, double* sh) { return wg_sum(v, sh); }
 
 // One proximal iteration (Alg. 1), part 1: per-state quantities shared by all
-// trial step sizes -- KH = K^-1 + H (collision Hessians on the diagonal
-// blocks), rb = eta - g, Lmu = Lambda_k mu_k -- and the expected costs
-// (per-block partial sums; the select kernel adds them in block order).
+// trial step sizes, written in chain order -- KH = K^-1 + H (collision
+// Hessians on the diagonal blocks), rb = eta - g, Lmu = Lambda_k mu_k, and
+// copies of K^-1, Lambda_k and mu_k -- and the expected costs (per-block
+// partial sums; the select kernel adds them in block order).
 // Grid (plans, iter_blocks), kIterThreads threads, grid-stride over states.
 template <int n>
 __global__ void __launch_bounds__(kIterThreads) prep_kernel(DevState st) {
     __shared__ double sh_d[kIterThreads + 1];
+    constexpr int NN = n * n;
     const int pid = blockIdx.x, y = blockIdx.y, nb = gridDim.y;
     PlanDev& p = st.plans[pid];
     if (!p.active) return;
@@ -935,16 +1010,25 @@ __global__ void __launch_bounds__(kIterThreads) prep_kernel(DevState st) {
         if (y == 0 && tid == 0) p.phase = 1;
         return;
     }
-    const int N = p.N, d = p.d;
-    const int64_t off = p.off, S = st.S;
-    const int n2 = n * n;
+    const int N = p.N, d = p.d, nseg = p.nseg;
+    const int64_t off = p.off, S = st.S, coff = p.coff;
     TS ts = thread_ws<n>(st, pid, y);
     double ecol = 0.0, epri = 0.0;
     for (int i = y * kIterThreads + tid; i < N; i += nb * kIterThreads) {
         TS lt = ts;
-        const int64_t s = off + i;
+        const int64_t s = off + i, q = coff + chain_pos(N, nseg, i);
         const bool act = coll_active<n>(p, i);
-        for (int e = 0; e < n2; ++e) st.KH[e * S + s] = st.KD[e * S + s];
+        for (int e = 0; e < NN; ++e) {
+            const int64_t qe = tidx<NN>(q, e);
+            const double kd = st.KD[e * S + s];
+            st.cKD[qe] = kd;
+            st.cKH[qe] = kd;
+            st.cLD[qe] = st.LD[e * S + s];
+            if (i < N - 1) {
+                st.cKU[qe] = st.KU[e * S + s];
+                st.cLU[qe] = st.LU[e * S + s];
+            }
+        }
         PG_VEC(r, lt);
         ld_vec<n>(st.eta, S, s, r);
         if (act) {
@@ -953,17 +1037,18 @@ __global__ void __launch_bounds__(kIterThreads) prep_kernel(DevState st) {
                 r[p.coll_index[a]] -= st.gcol[a * S + s];
                 for (int b2 = 0; b2 < d; ++b2) {
                     const int e = p.coll_index[a] * n + p.coll_index[b2];
-                    st.KH[e * S + s] = st.KD[e * S + s] + st.Hcol[(a * d + b2) * S + s];
+                    st.cKH[tidx<NN>(q, e)] = st.KD[e * S + s] + st.Hcol[(a * d + b2) * S + s];
                 }
             }
         }
-        st_vec<n>(st.rb, S, s, r);
+        for (int e = 0; e < n; ++e) st.crb[tidx<n>(q, e)] = r[e];
         PG_MAT(Dm, lt);
         PG_VEC(m, lt);
         PG_VEC(t, lt);
         PG_VEC(acc, lt);
         ld_soa<n>(st.LD, S, s, Dm);
         ld_vec<n>(st.mu, S, s, m);
+        for (int e = 0; e < n; ++e) st.cmu[tidx<n>(q, e)] = m[e];
         mvec<n>(Dm, m, acc);
         if (i < N - 1) {
             ld_soa<n>(st.LU, S, s, Dm);
@@ -981,7 +1066,7 @@ PG_UNROLL
 PG_UNROLL
             for (int e = 0; e < n; ++e) acc[e] -= t[e];
         }
-        st_vec<n>(st.Lmu, S, s, acc);
+        for (int e = 0; e < n; ++e) st.cLmu[tidx<n>(q, e)] = acc[e];
         epri += prior_cost_state<n>(st, p, i, nullptr, nullptr, nullptr, lt);
     }
     ecol = block_sum(ecol, sh_d);
@@ -999,12 +1084,14 @@ PG_UNROLL
 //   KL(q' || q_k) = 1/2 [beta (T dim - tr((K^-1 + H) Sigma')) + dmu^T Lambda_k dmu
 //                        + log det Lambda' - log det Lambda_k]
 // (the trace term uses Lambda_k = (beta T + 1) Lambda' - beta (K^-1 + H) and
-// tr(Lambda' Sigma') = dim).  Results go to the trial slot and st.tres.
+// tr(Lambda' Sigma') = dim).  Results go to the trial slot (chain order) and
+// st.tres.
 template <int n>
 __global__ void __launch_bounds__(kTrialThreads) trial_kernel(DevState st, int round) {
     __shared__ double sh_d[kTrialThreads + 1];
     __shared__ int sh_i[kChainThreads + 1];
     __shared__ int sh_j[kChainThreads + 1];
+    constexpr int NN = n * n;
     const int pid = blockIdx.x, t = blockIdx.y;
     const PlanDev& p = st.plans[pid];
     if (!p.active || p.phase != 0) return;
@@ -1013,28 +1100,32 @@ __global__ void __launch_bounds__(kTrialThreads) trial_kernel(DevState st, int r
     const int tid = threadIdx.x;
     const int half = tid / kChainThreads, lane = tid % kChainThreads;
     const int N = p.N, nseg = p.nseg;
-    const int64_t S = st.S, off = p.off;
-    const int64_t SW = S * st.W, offt = (int64_t)t * S + off, shift = -(int64_t)t * S;
+    const int64_t coff = p.coff, c0 = (int64_t)t * st.Sc + coff;
     double* sg = seg_scratch<n>(st, pid, t, half);
-    double* ws = state_ws(st, half);
+    const Ws ws = sweep_ws<n>(st, half, c0);
     TS ts = thread_ws<n>(st, pid, t);
     double* res = st.tres + ((int64_t)pid * st.W + t) * 4;
     const double beta = ldexp(p.beta_max, -tt);
     const double T = p.temperature;
     const double c = 1.0 / fma(beta, T, 1.0);
+    // views of the plan's inputs and of this trial slot's outputs
+    const double *kh = st.cKH + coff * NN, *kd = st.cKD + coff * NN, *lD = st.cLD + coff * NN;
+    const double *ku = st.cKU + coff * NN, *lU = st.cLU + coff * NN;
+    const double *rb = st.crb + coff * n, *lmu = st.cLmu + coff * n, *cmu = st.cmu + coff * n;
+    double *tsd = st.TSD + c0 * NN, *tsu = st.TSU + c0 * NN, *tmu = st.Tmu + c0 * n;
     // wave 0: marginals and PD test of the trial precision; wave 1: trial mean.
-    // Both helpers pass the same three workgroup barriers.
-    double ldt = 0.0;
+    // Both helpers pass the same workgroup barriers.
+    double ld_trial = 0.0;
     if (half == 0) {
-        BlockSrc MT{st.KH, st.LD, st.KU, st.LU, nullptr, nullptr, c * beta, c, S, shift};
-        wg_gbp<n>(MT, st, ws, lane, offt, SW, N, nseg, sg, st.TSD, st.TSU, &ldt, sh_d, sh_i, ts);
+        BlockSrc MT{kh, lD, ku, lU, kh, lD, c * beta, c};
+        wg_gbp<n>(MT, ws, lane, N, nseg, sg, tsd, tsu, &ld_trial, sh_d, sh_i, ts);
     } else {
-        BlockSrc MM{st.KD, st.LD, st.KU, st.LU, st.rb, st.Lmu, 1.0, 1.0 / beta, S, shift};
-        wg_solve<n>(MM, st, ws, lane, offt, SW, N, nseg, sg, st.Tmu, sh_j, ts);
+        BlockSrc MM{kd, lD, ku, lU, rb, lmu, 1.0, 1.0 / beta};
+        wg_solve<n>(MM, ws, lane, N, nseg, sg, tmu, sh_j, ts);
     }
     __syncthreads();
     const bool pd = sh_i[kChainThreads] != 0;
-    ldt = sh_d[kChainThreads];
+    ld_trial = sh_d[kChainThreads];
     __syncthreads();
     if (!pd) {
         if (tid == 0) {
@@ -1045,30 +1136,45 @@ __global__ void __launch_bounds__(kTrialThreads) trial_kernel(DevState st, int r
         }
         return;
     }
+    // trace and quadratic terms over the chain range (consecutive positions
+    // per thread), pairs (i, i+1) through the successor's position
     double trKH = 0.0, quad = 0.0;
-    const int n2 = n * n;
-    for (int i = tid; i < N; i += kTrialThreads) {
+    const int clen = chain_len(N, nseg);
+    for (int ql = tid; ql < clen; ql += kTrialThreads) {
+        const int j = ql % nseg, il = ql / nseg;
+        const int i0 = seg_start(N, nseg, j), len = seg_start(N, nseg, j + 1) - i0;
+        if (il >= len) continue;
+        const int i = i0 + il;
         TS lt = ts;
-        const int64_t s = off + i, q = offt + i;
+        const uint32_t oB = toff<NN>(ql), oV = toff<n>(ql);
         PG_MAT(Sg, lt);
         PG_MAT(Dm, lt);
         PG_VEC(dm, lt);
         PG_VEC(tv, lt);
-        ld_soa<n>(st.TSD, SW, q, Sg);
+        ldt<n, NN>(tsd, oB, Sg);
+PG_UNROLL
         for (int r = 0; r < n; ++r)
-            for (int k = 0; k < n; ++k) trKH = fma(st.KH[(r * n + k) * S + s], Sg[k * n + r], trKH);
-        for (int e = 0; e < n; ++e) dm[e] = st.Tmu[e * SW + q] - st.mu[e * S + s];
-        ld_soa<n>(st.LD, S, s, Dm);
+PG_UNROLL
+            for (int k = 0; k < n; ++k) trKH = fma(ldo(kh, oB, r * n + k), Sg[k * n + r], trKH);
+PG_UNROLL
+        for (int e = 0; e < n; ++e) dm[e] = ldo(tmu, oV, e) - ldo(cmu, oV, e);
+        ldt<n, NN>(lD, oB, Dm);
         mvec<n>(Dm, dm, tv);
+PG_UNROLL
         for (int e = 0; e < n; ++e) quad = fma(dm[e], tv[e], quad);
         if (i < N - 1) {
+            const int qln = il + 1 < len ? ql + nseg : j + 1;  // successor (next segment starts at il = 0)
+            const uint32_t oVn = toff<n>(qln);
             PG_MAT(Su, lt);
             PG_VEC(dn, lt);
-            ld_soa<n>(st.TSU, SW, q, Su);
-            for (int e = 0; e < n2; ++e) trKH = fma(2.0 * st.KU[e * S + s], Su[e], trKH);
-            for (int e = 0; e < n; ++e) dn[e] = st.Tmu[e * SW + q + 1] - st.mu[e * S + s + 1];
-            ld_soa<n>(st.LU, S, s, Dm);
+            ldt<n, NN>(tsu, oB, Su);
+PG_UNROLL
+            for (int e = 0; e < NN; ++e) trKH = fma(2.0 * ldo(ku, oB, e), Su[e], trKH);
+PG_UNROLL
+            for (int e = 0; e < n; ++e) dn[e] = ldo(tmu, oVn, e) - ldo(cmu, oVn, e);
+            ldt<n, NN>(lU, oB, Dm);
             mvec<n>(Dm, dn, tv);
+PG_UNROLL
             for (int e = 0; e < n; ++e) quad = fma(2.0 * dm[e], tv[e], quad);
         }
     }
@@ -1076,21 +1182,22 @@ __global__ void __launch_bounds__(kTrialThreads) trial_kernel(DevState st, int r
     quad = wg_sum(quad, sh_d);
     if (tid == 0) {
         res[0] = 1.0;
-        res[1] = 0.5 * (beta * (T * (double)N * n - trKH) + quad + ldt - p.logdet);
-        res[2] = ldt;
+        res[1] = 0.5 * (beta * (T * (double)N * n - trKH) + quad + ld_trial - p.logdet);
+        res[2] = ld_trial;
         res[3] = beta;
     }
 }
 
 // Part 3: take the first passing trial of this window (in step-size order)
-// and write it back as the new iterate; finish the iteration of plans whose
-// step sizes are exhausted (state unchanged, ENOCONV).  Grid (plans,
-// iter_blocks): every block finds the same pick from the trial results and
-// copies its share of the states; block 0 does the bookkeeping and tags
-// the plan with phase 2 + round, which the other blocks of this launch still
-// read as pending.
+// and write it back, in state order, as the new iterate; finish the
+// iteration of plans whose step sizes are exhausted (state unchanged,
+// ENOCONV).  Grid (plans, iter_blocks): every block finds the same pick from
+// the trial results and copies its share of the states; block 0 does the
+// bookkeeping and tags the plan with phase 2 + round, which the other
+// blocks of this launch still read as pending.
 template <int n>
 __global__ void __launch_bounds__(kIterThreads) select_kernel(DevState st, int round) {
+    constexpr int NN = n * n;
     const int pid = blockIdx.x, y = blockIdx.y, nb = gridDim.y;
     PlanDev& p = st.plans[pid];
     if (!p.active) return;
@@ -1114,9 +1221,8 @@ __global__ void __launch_bounds__(kIterThreads) select_kernel(DevState st, int r
     }
     const bool exhausted = (round + 1) * W >= p.max_bisect;
     if (pick < 0 && !exhausted) return;  // next window
-    const int N = p.N;
-    const int64_t S = st.S, off = p.off, SW = S * W;
-    const int n2 = n * n;
+    const int N = p.N, nseg = p.nseg;
+    const int64_t S = st.S, off = p.off, coff = p.coff;
     double beta = 0.0, kl = last_kl, ld = 0.0;
     if (pick >= 0) {
         const double* res = st.tres + ((int64_t)pid * W + pick) * 4;
@@ -1125,18 +1231,17 @@ __global__ void __launch_bounds__(kIterThreads) select_kernel(DevState st, int r
         ld = res[2];
         const double c = 1.0 / fma(beta, p.temperature, 1.0);
         const double a0 = c * beta, a1 = c;
-        const int64_t tq = (int64_t)pick * S;
         for (int i = y * kIterThreads + tid; i < N; i += nb * kIterThreads) {
-            const int64_t s = off + i, q = tq + s;
-            for (int e = 0; e < n2; ++e) {
-                st.LD[e * S + s] = lin2(a0, st.KH[e * S + s], a1, st.LD[e * S + s]);
-                st.SD[e * S + s] = st.TSD[e * SW + q];
+            const int64_t s = off + i, qs = coff + chain_pos(N, nseg, i), q = (int64_t)pick * st.Sc + qs;
+            for (int e = 0; e < NN; ++e) {
+                st.LD[e * S + s] = lin2(a0, st.cKH[tidx<NN>(qs, e)], a1, st.LD[e * S + s]);
+                st.SD[e * S + s] = st.TSD[tidx<NN>(q, e)];
                 if (i < N - 1) {
                     st.LU[e * S + s] = lin2(a0, st.KU[e * S + s], a1, st.LU[e * S + s]);
-                    st.SU[e * S + s] = st.TSU[e * SW + q];
+                    st.SU[e * S + s] = st.TSU[tidx<NN>(q, e)];
                 }
             }
-            for (int e = 0; e < n; ++e) st.mu[e * S + s] = st.Tmu[e * SW + q];
+            for (int e = 0; e < n; ++e) st.mu[e * S + s] = st.Tmu[tidx<n>(q, e)];
         }
     }
     if (y == 0 && tid == 0) {

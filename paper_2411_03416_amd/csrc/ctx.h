@@ -31,8 +31,9 @@ struct PlanDev {
     int32_t d, gh_points, gx, gy;
     int32_t gz, n_spheres, coll_states, status;
     int32_t trials, m, n_iters, trials_total;
-    int32_t phase, pad0;  // 0 = step pending this iteration, 1 = no step this iteration,
-                          // 2 + r = step taken (or exhausted) in trial window r
+    int32_t phase;  // 0 = step pending this iteration, 1 = no step this iteration,
+                    // 2 + r = step taken (or exhausted) in trial window r
+    int32_t coff;   // start of the plan's chain-order range (capacity Sc)
     int32_t coll_index[PGVIMP_MAX_COLL_DIM];
     double temperature, beta_max, kl_bound, cell, dt;
     double inv_cell, hinge_eps, obs_weight, logdet;
@@ -67,9 +68,13 @@ struct DevState {
     // current iterate
     double *LD, *LU, *mu;  // precision blocks and mean
     double *SD, *SU;       // marginal covariances
-    // K^-1 + H (collision Hessians added on the diagonal blocks)
-    double* KH;
-    // trial iterates: W slots, slot t of state s at t * S + s (stride W * S)
+    // chain-order copies (capacity Sc) of one iteration's inputs: K^-1 + H
+    // (collision Hessians on the diagonal blocks), K^-1, Lambda_k, the mean-
+    // solve right-hand side parts rb = eta - g and Lmu = Lambda_k mu_k, mu_k
+    int64_t Sc;
+    double *cKH, *cKD, *cLD, *cKU, *cLU, *crb, *cLmu, *cmu;
+    // trial iterates in chain order: W slots, slot t of position q at t * Sc + q
+    // (stride W * Sc)
     double *Tmu, *TSD, *TSU;
     double* tres;  // per (plan, slot): passed, KL, log det, beta
     int32_t W;     // trial step sizes evaluated concurrently
@@ -77,11 +82,10 @@ struct DevState {
     double* psum;         // per (plan, prep block): partial E_coll, E_prior
     // collision expectations (d-dim, not embedded): E [S], g [d][S], H [d*d][S]
     double *Ecol, *gcol, *Hcol;
-    // mean-solve right-hand side parts: rb = eta - g, Lmu = Lambda_k mu_k
-    double *rb, *Lmu;
     // prior factor costs [S] (transition starting at state s) and end costs
     double* Epri;
-    // chain workspace: per state AoS (stride ws_stride), per segment AoS
+    // chain workspace: sweep temporaries [2][ws_stride][W * Sc] and segment
+    // scratch [P][W][2][seg_stride][kMaxSeg]
     double* ws;
     double* seg;
     int32_t ws_stride, seg_stride;
