@@ -88,7 +88,7 @@ typedef struct pgvimp_ctx pgvimp_ctx;
  *
  * Iteration: temperature T > 0 weights the entropy in E[psi] - T H(q);
  * the step size starts at beta_max > 0 and is halved at most max_bisect
- * times; kl_bound > 0 (may be +inf) bounds KL(q_{k+1} || q_k); n_iters is
+ * times (1 <= max_bisect <= 64); kl_bound > 0 (may be +inf) bounds KL(q_{k+1} || q_k); n_iters is
  * the plan's iteration budget consumed by pgvimp_prox_step.
  *
  * Collision cost of state x: psi = obs_weight * sum_s max(0, hinge_eps +
@@ -145,9 +145,14 @@ typedef struct pgvimp_problem {
  * to the plans present (re-captured when they change); use_graph = 2 sizes
  * the graph to the full capacity so plans can join and leave without a new
  * capture (serving).
- * trial_width (0 = 16, at most 64) is the number of step sizes of the
+ * trial_width (0 = 8, at most 64) is the number of step sizes of the
  * halving sequence evaluated concurrently per plan and iteration; it changes
  * speed and memory (the trial scratch scales with it), never results.
+ * trial_lookahead > 0 shortens each plan's first window of an iteration to
+ * min(trial_width, t + trial_lookahead) step sizes, t = the number of step
+ * sizes its previous iteration tried (later windows are trial_width wide);
+ * 0 = full first window.  Also a speed knob only: the accepted step is the
+ * first passing one in halving order whatever the windows.
  */
 typedef struct pgvimp_engine_cfg {
     int32_t device, n, precision, max_plans;
@@ -156,7 +161,7 @@ typedef struct pgvimp_engine_cfg {
     void *dev_arena;
     uint64_t arena_bytes;
     int32_t io_on_device, segments, lanes_per_factor, use_graph;
-    int32_t trial_width, reserved;
+    int32_t trial_width, trial_lookahead;
 } pgvimp_engine_cfg;
 
 /* Per-plan statistics of the last iteration run by pgvimp_prox_step. */

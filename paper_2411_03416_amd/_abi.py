@@ -54,7 +54,7 @@ class EngineCfg(C.Structure):
         ("max_states", C.c_int64), ("heap_bytes", C.c_int64),
         ("stream", C.c_void_p), ("dev_arena", C.c_void_p), ("arena_bytes", C.c_uint64),
         ("io_on_device", C.c_int32), ("segments", C.c_int32), ("lanes_per_factor", C.c_int32),
-        ("use_graph", C.c_int32), ("trial_width", C.c_int32), ("reserved", C.c_int32),
+        ("use_graph", C.c_int32), ("trial_width", C.c_int32), ("trial_lookahead", C.c_int32),
     ]
 
 

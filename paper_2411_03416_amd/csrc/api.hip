@@ -17,7 +17,7 @@ using namespace pg;
 namespace {
 
 constexpr int64_t kAlign = 256;
-constexpr int kDefaultTrialWidth = 16;
+constexpr int kDefaultTrialWidth = 8;
 constexpr int kMaxTrialWidth = 64;
 
 struct PlanHost {
@@ -267,7 +267,7 @@ int validate_problem(pgvimp_ctx* c, const pgvimp_problem* p) {
     if (!host_spd(p->Sig_start, n) || !host_spd(p->Sig_goal, n) || !host_spd(p->Qc, p->m))
         FAIL(c, PGVIMP_EINVAL, "start/goal covariance or Qc not symmetric positive definite");
     if (!(p->temperature > 0.0) || !(p->beta_max > 0.0) || !(p->kl_bound > 0.0) || p->max_bisect < 1 ||
-        p->n_iters < 0)
+        p->max_bisect > kMaxBisect || p->n_iters < 0)
         FAIL(c, PGVIMP_EINVAL, "bad iteration parameters");
     if (p->mu_init && !finite_all(p->mu_init, (int64_t)p->N * n)) FAIL(c, PGVIMP_EINVAL, "non-finite mu_init");
     if (p->coll_kind == PGVIMP_COLL_NONE) return PGVIMP_OK;
@@ -356,7 +356,7 @@ static int64_t carve(pgvimp_ctx* c, const pgvimp_engine_cfg* cfg, DevState& st, 
     take(&st.TSD, W * Sc * n * n * 8);
     take(&st.TSU, W * Sc * n * n * 8);
     take(&st.Tmu, W * Sc * n * 8);
-    take(&st.tres, P * W * 4 * 8);
+    take(&st.tres, P * kMaxBisect * 4 * 8);
     take(&st.psum, P * kIterBlocks * 2 * 8);
     take(&st.Ecol, S * 8);
     take(&st.gcol, S * dmax * 8);
@@ -384,6 +384,7 @@ static int64_t carve(pgvimp_ctx* c, const pgvimp_engine_cfg* cfg, DevState& st, 
     st.tws_stride = tws_stride;
     st.W = (int32_t)W;
     st.iter_blocks = (int32_t)std::min<int64_t>(kIterBlocks, W);
+    st.lookahead = std::max(0, cfg->trial_lookahead);
     return off;
 }
 
@@ -437,7 +438,7 @@ int pgvimp_create(const pgvimp_problem* probs, int32_t n_probs, const pgvimp_eng
     if (!cfg) FAIL((pgvimp_ctx*)nullptr, PGVIMP_EINVAL, "null config");
     if (!chain_supported(cfg->n)) FAIL((pgvimp_ctx*)nullptr, PGVIMP_EINVAL, "state dim %d not supported", cfg->n);
     if (cfg->max_plans < 1 || cfg->max_states < 1 || cfg->heap_bytes < 0 || n_probs < 0 || n_probs > cfg->max_plans ||
-        cfg->use_graph < 0 || cfg->use_graph > 2 || cfg->trial_width < 0 ||
+        cfg->use_graph < 0 || cfg->use_graph > 2 || cfg->trial_width < 0 || cfg->trial_lookahead < 0 ||
         (n_probs > 0 && !probs) || (cfg->precision != PGVIMP_FP64 && cfg->precision != PGVIMP_MIXED) ||
         cfg->segments < 0 || cfg->segments > kMaxSeg)
         FAIL((pgvimp_ctx*)nullptr, PGVIMP_EINVAL, "invalid engine configuration");
@@ -607,6 +608,7 @@ int pgvimp_add_plan(pgvimp_ctx* c, const pgvimp_problem* p, int32_t* plan_out) {
     pd.n_iters = p->n_iters;
     pd.dt = p->dt;
     pd.max_bisect = p->max_bisect;
+    pd.ltv = p->ltv ? 1 : 0;
     pd.coll_kind = p->coll_kind;
     pd.d = coll ? coll_dim_of(p->coll_kind) : 0;
     pd.gh_points = p->gh_points;
@@ -769,12 +771,15 @@ static int max_live_N(pgvimp_ctx* c) {
     return m;
 }
 
-// Windows of trial step sizes needed by the live plans.
+// Windows of trial step sizes needed by the live plans: a first window of
+// at least one step size (trial_width without lookahead), then windows of
+// trial_width.
 static int trial_rounds(pgvimp_ctx* c) {
     int mb = 1;
     for (auto& ph : c->plans)
         if (ph.active) mb = std::max(mb, ph.max_bisect);
-    return (mb + c->st.W - 1) / c->st.W;
+    const int W = c->st.W;
+    return c->st.lookahead > 0 ? 1 + (mb - 1 + W - 1) / W : (mb + W - 1) / W;
 }
 
 static int enqueue_iters(pgvimp_ctx* c, int n_iters, const std::vector<ClassKey>& cls, int64_t shw, int phw,
@@ -824,10 +829,10 @@ static int enqueue_iters(pgvimp_ctx* c, int n_iters, const std::vector<ClassKey>
             if ((rc = begin(PGVIMP_K_TRIAL))) return rc;
             HCK(c, launch_iteration(c->st, phw, 1, r, c->stream));
             if ((rc = end())) return rc;
-            if ((rc = begin(PGVIMP_K_SELECT))) return rc;
-            HCK(c, launch_iteration(c->st, phw, 2, r, c->stream));
-            if ((rc = end())) return rc;
         }
+        if ((rc = begin(PGVIMP_K_SELECT))) return rc;
+        HCK(c, launch_iteration(c->st, phw, 2, 0, c->stream));
+        if ((rc = end())) return rc;
     }
     return PGVIMP_OK;
 }

@@ -36,11 +36,11 @@
 //
 // Step-size selection.  Halving from beta_max accepts the first trial step
 // that passes (Alg. 1, App. C), so the trials are independent of each
-// other: one iteration evaluates a window of W consecutive trial step sizes
-// at once, one workgroup per (plan, trial), and a select kernel takes the
-// first passing trial of the window in order.  Plans still pending after a
-// window continue with the next W step sizes.  The chosen step and every
-// result are the same as trying the step sizes one after another.
+// other: one launch evaluates a window of consecutive trial step sizes at
+// once, one workgroup per (plan, trial).  A plan with a passing step in an
+// earlier window skips the later ones; after the last window a select
+// kernel takes the first passing step size in order.  The chosen step and
+// every result are the same as trying the step sizes one after another.
 #pragma once
 #include "blockmath.h"
 #include "ctx.h"
@@ -923,26 +923,30 @@ __device__ __forceinline__ Ws sweep_ws(const DevState& st, int half, int64_t c0)
 // CHAIN_REINIT: Lambda = K^-1 (mean kept), marginals;
 // CHAIN_MARGINALS: marginals of the current Lambda.
 // The inputs are first copied into chain order, the results (trial slot 0)
-// are copied back in state order.
+// are copied back in state order.  CHAIN_INIT runs with two wavefronts:
+// wave 0 computes the marginals while wave 1 solves for the mean; the other
+// modes run with one.
 template <int n>
-__global__ void __launch_bounds__(kChainThreads) chain_kernel(DevState st, int mode, int plan_lo) {
+__global__ void __launch_bounds__(kTrialThreads) chain_kernel(DevState st, int mode, int plan_lo) {
     __shared__ double sh_d[kChainThreads + 1];
     __shared__ int sh_i[kChainThreads + 1];
+    __shared__ int sh_j[kChainThreads + 1];
     constexpr int NN = n * n;
     const int pid = plan_lo + blockIdx.x;
     PlanDev& p = st.plans[pid];
     if (!p.active) return;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int half = tid / kChainThreads, lane = tid % kChainThreads;
     const int N = p.N, nseg = p.nseg;
     const int64_t off = p.off, S = st.S, coff = p.coff;
-    double* sg = seg_scratch<n>(st, pid, 0, 0);
-    const Ws ws = sweep_ws<n>(st, 0, coff);
+    double* sg = seg_scratch<n>(st, pid, 0, half);
+    const Ws ws = sweep_ws<n>(st, half, coff);
     TS ts = thread_ws<n>(st, pid, 0);
     const bool prior = mode == CHAIN_INIT || mode == CHAIN_REINIT;
     // precision to factor (K^-1 or the current Lambda) in chain order
     double* cD = prior ? st.cKD : st.cLD;
     double* cU = prior ? st.cKU : st.cLU;
-    for (int i = tid; i < N; i += kChainThreads) {
+    for (int i = tid; i < N; i += nt) {
         const int64_t s = off + i, q = coff + chain_pos(N, nseg, i);
         for (int e = 0; e < NN; ++e) {
             const double d = prior ? st.KD[e * S + s] : st.LD[e * S + s];
@@ -958,25 +962,28 @@ __global__ void __launch_bounds__(kChainThreads) chain_kernel(DevState st, int m
             for (int e = 0; e < n; ++e) st.crb[tidx<n>(q, e)] = st.eta[e * S + s];
     }
     __syncthreads();
-    if (mode == CHAIN_INIT) {
+    if (half == 0) {
+        const double *d = cD + coff * NN, *u = cU + coff * NN;
+        BlockSrc M{d, d, u, u, d, d, 1.0, 0.0};
+        double ld = 0.0;
+        wg_gbp<n>(M, ws, lane, N, nseg, sg, st.TSD + coff * NN, st.TSU + coff * NN, &ld, sh_d, sh_i, ts);
+    } else {
         const double *kd = st.cKD + coff * NN, *ku = st.cKU + coff * NN, *r = st.crb + coff * n;
         BlockSrc M{kd, kd, ku, ku, r, r, 1.0, 0.0};
-        wg_solve<n>(M, ws, tid, N, nseg, sg, st.Tmu + coff * n, sh_i, ts);
-        if (tid == 0) {
+        wg_solve<n>(M, ws, lane, N, nseg, sg, st.Tmu + coff * n, sh_j, ts);
+    }
+    __syncthreads();
+    const bool ok = sh_i[kChainThreads] != 0;
+    if (tid == 0) {
+        p.logdet = ok ? sh_d[kChainThreads] : NAN;
+        p.status = ok ? 0 : PGVIMP_ENOTPD;
+        if (mode == CHAIN_INIT) {
             p.iters_left = p.n_iters;
             p.iters_done = 0;
             p.trials_total = 0;
         }
     }
-    const double *d = cD + coff * NN, *u = cU + coff * NN;
-    BlockSrc M{d, d, u, u, d, d, 1.0, 0.0};
-    double ld = 0.0;
-    const bool ok = wg_gbp<n>(M, ws, tid, N, nseg, sg, st.TSD + coff * NN, st.TSU + coff * NN, &ld, sh_d, sh_i, ts);
-    if (tid == 0) {
-        p.logdet = ok ? ld : NAN;
-        p.status = ok ? 0 : PGVIMP_ENOTPD;
-    }
-    for (int i = tid; i < N; i += kChainThreads) {
+    for (int i = tid; i < N; i += nt) {
         const int64_t s = off + i, q = coff + chain_pos(N, nseg, i);
         if (ok) {
             for (int e = 0; e < NN; ++e) {
@@ -1074,11 +1081,28 @@ PG_UNROLL
     if (tid == 0) {
         st.psum[((int64_t)pid * nb + y) * 2 + 0] = ecol;
         st.psum[((int64_t)pid * nb + y) * 2 + 1] = epri;
-        if (y == 0) p.phase = 0;
+        if (y == 0) {
+            // first window: all W step sizes, or (lookahead) a few more than
+            // the previous iteration needed
+            const int W = st.W;
+            int w1 = W;
+            if (st.lookahead > 0 && p.iters_done > 0) w1 = min(W, max(1, p.trials + st.lookahead));
+            p.w1 = min(w1, p.max_bisect);
+            p.phase = 0;
+        }
     }
 }
 
-// Part 2: trial step size number round * W + blockIdx.y for plan blockIdx.x:
+// Window r of an iteration's step sizes: [start, start + width) of the
+// halving sequence, clipped to max_bisect.  Window 0 has the plan's width
+// w1 (set by prep), later windows the full W.
+__device__ __forceinline__ void trial_window(const PlanDev& p, int W, int r, int& start, int& width) {
+    start = r == 0 ? 0 : p.w1 + (r - 1) * W;
+    width = r == 0 ? p.w1 : W;
+    width = max(0, min(width, p.max_bisect - start));
+}
+
+// Part 2: trial step size number start + blockIdx.y of window `round` for plan blockIdx.x:
 //   Lambda' = (beta (K^-1 + H) + Lambda_k) / (beta T + 1)  -> marginals, log det, PD
 //   (K^-1 + Lambda_k / beta) mu' = eta - g + Lambda_k mu_k / beta
 //   KL(q' || q_k) = 1/2 [beta (T dim - tr((K^-1 + H) Sigma')) + dmu^T Lambda_k dmu
@@ -1095,8 +1119,13 @@ __global__ void __launch_bounds__(kTrialThreads) trial_kernel(DevState st, int r
     const int pid = blockIdx.x, t = blockIdx.y;
     const PlanDev& p = st.plans[pid];
     if (!p.active || p.phase != 0) return;
-    const int tt = round * st.W + t;
-    if (tt >= p.max_bisect) return;
+    int wstart, wwidth;
+    trial_window(p, st.W, round, wstart, wwidth);
+    if (t >= wwidth) return;
+    const int tt = wstart + t;
+    const double* tr = st.tres + (int64_t)pid * kMaxBisect * 4;
+    for (int k = 0; k < wstart; ++k)  // an earlier window already has a passing step
+        if (tr[4 * k] != 0.0 && tr[4 * k + 1] <= p.kl_bound) return;
     const int tid = threadIdx.x;
     const int half = tid / kChainThreads, lane = tid % kChainThreads;
     const int N = p.N, nseg = p.nseg;
@@ -1104,7 +1133,7 @@ __global__ void __launch_bounds__(kTrialThreads) trial_kernel(DevState st, int r
     double* sg = seg_scratch<n>(st, pid, t, half);
     const Ws ws = sweep_ws<n>(st, half, c0);
     TS ts = thread_ws<n>(st, pid, t);
-    double* res = st.tres + ((int64_t)pid * st.W + t) * 4;
+    double* res = st.tres + ((int64_t)pid * kMaxBisect + tt) * 4;
     const double beta = ldexp(p.beta_max, -tt);
     const double T = p.temperature;
     const double c = 1.0 / fma(beta, T, 1.0);
@@ -1188,51 +1217,44 @@ PG_UNROLL
     }
 }
 
-// Part 3: take the first passing trial of this window (in step-size order)
-// and write it back, in state order, as the new iterate; finish the
-// iteration of plans whose step sizes are exhausted (state unchanged,
-// ENOCONV).  Grid (plans, iter_blocks): every block finds the same pick from
-// the trial results and copies its share of the states; block 0 does the
-// bookkeeping and tags the plan with phase 2 + round, which the other
-// blocks of this launch still read as pending.
+// Part 3 (after the last window): take the first passing step size in
+// halving order and write its trial back, in state order, as the new
+// iterate; a plan with no passing step keeps its state (ENOCONV).  Every
+// step size before the first passing one was evaluated in this iteration,
+// so the scan reads only this iteration's results.  Grid (plans,
+// iter_blocks): every block finds the same pick and copies its share of the
+// states; block 0 does the bookkeeping.
 template <int n>
-__global__ void __launch_bounds__(kIterThreads) select_kernel(DevState st, int round) {
+__global__ void __launch_bounds__(kIterThreads) select_kernel(DevState st, int /*unused*/) {
     constexpr int NN = n * n;
     const int pid = blockIdx.x, y = blockIdx.y, nb = gridDim.y;
     PlanDev& p = st.plans[pid];
-    if (!p.active) return;
-    const int ph = p.phase;
-    if (ph != 0 && ph != 2 + round) return;
+    if (!p.active || p.phase != 0) return;
     const int tid = threadIdx.x;
     const int W = st.W;
+    const double* tr = st.tres + (int64_t)pid * kMaxBisect * 4;
     int pick = -1;
-    int tried = 0;
-    double last_kl = NAN;
-    for (int t = 0; t < W; ++t) {
-        const int tt = round * W + t;
-        if (tt >= p.max_bisect) break;
-        const double* res = st.tres + ((int64_t)pid * W + t) * 4;
-        tried = tt + 1;
-        last_kl = res[1];
-        if (res[0] != 0.0 && res[1] <= p.kl_bound) {
-            pick = t;
+    for (int k = 0; k < p.max_bisect; ++k)
+        if (tr[4 * k] != 0.0 && tr[4 * k + 1] <= p.kl_bound) {
+            pick = k;
             break;
         }
-    }
-    const bool exhausted = (round + 1) * W >= p.max_bisect;
-    if (pick < 0 && !exhausted) return;  // next window
+    const double last_kl = tr[4 * (p.max_bisect - 1) + 1];
+    // trial slot of step size number pick: its position in its window
+    int slot = pick;
+    if (pick >= p.w1) slot = (pick - p.w1) % W;
     const int N = p.N, nseg = p.nseg;
     const int64_t S = st.S, off = p.off, coff = p.coff;
     double beta = 0.0, kl = last_kl, ld = 0.0;
     if (pick >= 0) {
-        const double* res = st.tres + ((int64_t)pid * W + pick) * 4;
+        const double* res = tr + 4 * pick;
         beta = res[3];
         kl = res[1];
         ld = res[2];
         const double c = 1.0 / fma(beta, p.temperature, 1.0);
         const double a0 = c * beta, a1 = c;
         for (int i = y * kIterThreads + tid; i < N; i += nb * kIterThreads) {
-            const int64_t s = off + i, qs = coff + chain_pos(N, nseg, i), q = (int64_t)pick * st.Sc + qs;
+            const int64_t s = off + i, qs = coff + chain_pos(N, nseg, i), q = (int64_t)slot * st.Sc + qs;
             for (int e = 0; e < NN; ++e) {
                 st.LD[e * S + s] = lin2(a0, st.cKH[tidx<NN>(qs, e)], a1, st.LD[e * S + s]);
                 st.SD[e * S + s] = st.TSD[tidx<NN>(q, e)];
@@ -1252,7 +1274,7 @@ __global__ void __launch_bounds__(kIterThreads) select_kernel(DevState st, int r
         }
         p.E_coll = ecol;
         p.E_prior = epri;
-        p.trials = pick >= 0 ? round * W + pick + 1 : tried;
+        p.trials = pick >= 0 ? pick + 1 : p.max_bisect;
         p.trials_total += p.trials;
         p.kl = kl;
         if (pick >= 0) {
@@ -1266,7 +1288,6 @@ __global__ void __launch_bounds__(kIterThreads) select_kernel(DevState st, int r
         p.entropy = 0.5 * (double)N * n * (1.0 + 1.8378770664093453) - 0.5 * p.logdet;
         p.iters_left -= 1;
         p.iters_done += 1;
-        p.phase = 2 + round;
     }
 }
 
@@ -1287,7 +1308,8 @@ __global__ void __launch_bounds__(kChainThreads) prior_cost_kernel(DevState st, 
 template <int n>
 hipError_t launch_chain_n(const DevState& st, int mode, int lo, int hi, hipStream_t s) {
     if (hi <= lo) return hipSuccess;
-    hipLaunchKernelGGL(chain_kernel<n>, dim3(hi - lo), dim3(kChainThreads), 0, s, st, mode, lo);
+    const int threads = mode == CHAIN_INIT ? kTrialThreads : kChainThreads;
+    hipLaunchKernelGGL(chain_kernel<n>, dim3(hi - lo), dim3(threads), 0, s, st, mode, lo);
     return hipGetLastError();
 }
 

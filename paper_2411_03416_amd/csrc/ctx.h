@@ -16,6 +16,7 @@ constexpr int kChainThreads = 64; // one wavefront per plan in the chain kernel
 constexpr int kTrialThreads = 128; // trial kernel: marginals and mean solve side by side
 constexpr int kIterThreads = 128;  // prep/select kernels (uses the trial kernel's per-thread slots)
 constexpr int kIterBlocks = 8;     // prep/select blocks per plan (at most W)
+constexpr int kMaxBisect = 64;     // step sizes of the halving sequence per iteration (upper bound)
 constexpr int kMaxGH = 10;        // Gauss-Hermite points per dimension
 // n x n temporaries a chain-kernel thread may hold at once.  Deepest call
 // paths: kernel loop body 1 + prior cost 8 = 9; segment elimination 9 +
@@ -31,8 +32,9 @@ struct PlanDev {
     int32_t d, gh_points, gx, gy;
     int32_t gz, n_spheres, coll_states, status;
     int32_t trials, m, n_iters, trials_total;
-    int32_t phase;  // 0 = step pending this iteration, 1 = no step this iteration,
-                    // 2 + r = step taken (or exhausted) in trial window r
+    int32_t w1;   // width of this iteration's first window of step sizes
+    int32_t ltv;  // 0: every interval has the same dynamics (A, a, B)
+    int32_t phase;  // 0 = iteration pending, 1 = no iteration (budget spent)
     int32_t coff;   // start of the plan's chain-order range (capacity Sc)
     int32_t coll_index[PGVIMP_MAX_COLL_DIM];
     double temperature, beta_max, kl_bound, cell, dt;
@@ -76,9 +78,10 @@ struct DevState {
     // trial iterates in chain order: W slots, slot t of position q at t * Sc + q
     // (stride W * Sc)
     double *Tmu, *TSD, *TSU;
-    double* tres;  // per (plan, slot): passed, KL, log det, beta
+    double* tres;  // per (plan, step size number < kMaxBisect): passed, KL, log det, beta
     int32_t W;     // trial step sizes evaluated concurrently
     int32_t iter_blocks;  // blocks per plan of the prep and select kernels
+    int32_t lookahead;    // first-window lookahead (0 = full first window)
     double* psum;         // per (plan, prep block): partial E_coll, E_prior
     // collision expectations (d-dim, not embedded): E [S], g [d][S], H [d*d][S]
     double *Ecol, *gcol, *Hcol;

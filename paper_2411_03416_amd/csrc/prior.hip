@@ -104,7 +104,9 @@ __device__ bool spd_inv_serial(const double* A, double* Ainv, double* L, int n) 
 }
 
 // Plan plan_lo + blockIdx.y; blockIdx.x < N-1: interval; == N-1: start/goal
-// inverses; beyond: nothing.
+// inverses; beyond: nothing.  With time-invariant dynamics every interval
+// has the same transition, offset and Grammian: only interval 0 computes
+// them and the assembly kernel shares them with the other intervals.
 __global__ void __launch_bounds__(kPriorThreads) prior_build_kernel(DevState st, int plan_lo) {
     __shared__ double M[kMaxAug * kMaxAug], E[kMaxAug * kMaxAug], T1[kMaxAug * kMaxAug], T2[kMaxAug * kMaxAug];
     PlanDev& p = st.plans[plan_lo + blockIdx.y];
@@ -114,6 +116,7 @@ __global__ void __launch_bounds__(kPriorThreads) prior_build_kernel(DevState st,
     if (i >= p.N) return;
     const double dt = p.dt;
     const int64_t S = st.S;
+    if (!p.ltv && i > 0 && i < p.N - 1) return;
     if (i == p.N - 1) {
         if (threadIdx.x == 0) {
             spd_inv_serial(p.Sig_start, p.Wstart, M, n);
@@ -191,6 +194,17 @@ __global__ void prior_assemble_kernel(DevState st, int plan_lo) {
     const int N = p.N;
     if (i >= N) return;
     const int64_t S = st.S, s = p.off + i;
+    // interval blocks of this interval (sI) and of the previous one (sP):
+    // interval 0's for time-invariant dynamics, copied to this interval for
+    // the later per-state readers
+    const int64_t sI = p.ltv ? s : p.off, sP = p.ltv ? s - 1 : p.off;
+    if (!p.ltv && i > 0 && i < N - 1) {
+        for (int e = 0; e < n * n; ++e) {
+            st.Phi[e * S + s] = st.Phi[e * S + sI];
+            st.Qinv[e * S + s] = st.Qinv[e * S + sI];
+        }
+        for (int e = 0; e < n; ++e) st.abar[e * S + s] = st.abar[e * S + sI];
+    }
     for (int r = 0; r < n; ++r) {
         for (int c = 0; c < n; ++c) {
             double v = 0.0;
@@ -199,14 +213,14 @@ __global__ void prior_assemble_kernel(DevState st, int plan_lo) {
             if (i < N - 1) {  // Phi^T Qinv Phi
                 for (int k = 0; k < n; ++k) {
                     double t = 0.0;
-                    for (int l = 0; l < n; ++l) t += st.Qinv[(k * n + l) * S + s] * st.Phi[(l * n + c) * S + s];
-                    v += st.Phi[(k * n + r) * S + s] * t;
+                    for (int l = 0; l < n; ++l) t += st.Qinv[(k * n + l) * S + sI] * st.Phi[(l * n + c) * S + sI];
+                    v += st.Phi[(k * n + r) * S + sI] * t;
                 }
                 double u = 0.0;  // -Phi^T Qinv
-                for (int k = 0; k < n; ++k) u -= st.Phi[(k * n + r) * S + s] * st.Qinv[(k * n + c) * S + s];
+                for (int k = 0; k < n; ++k) u -= st.Phi[(k * n + r) * S + sI] * st.Qinv[(k * n + c) * S + sI];
                 st.KU[(r * n + c) * S + s] = u;
             }
-            if (i > 0) v += st.Qinv[(r * n + c) * S + s - 1];
+            if (i > 0) v += st.Qinv[(r * n + c) * S + sP];
             st.KD[(r * n + c) * S + s] = v;
         }
         double e = 0.0;
@@ -217,12 +231,12 @@ __global__ void prior_assemble_kernel(DevState st, int plan_lo) {
         if (i < N - 1) {  // -Phi^T Qinv abar
             for (int k = 0; k < n; ++k) {
                 double t = 0.0;
-                for (int l = 0; l < n; ++l) t += st.Qinv[(k * n + l) * S + s] * st.abar[l * S + s];
-                e -= st.Phi[(k * n + r) * S + s] * t;
+                for (int l = 0; l < n; ++l) t += st.Qinv[(k * n + l) * S + sI] * st.abar[l * S + sI];
+                e -= st.Phi[(k * n + r) * S + sI] * t;
             }
         }
         if (i > 0) {
-            for (int l = 0; l < n; ++l) e += st.Qinv[(r * n + l) * S + s - 1] * st.abar[l * S + s - 1];
+            for (int l = 0; l < n; ++l) e += st.Qinv[(r * n + l) * S + sP] * st.abar[l * S + sP];
         }
         st.eta[r * S + s] = e;
     }
@@ -437,6 +451,7 @@ __global__ void __launch_bounds__(kSlrThreads) slr_kernel(DevState st, int plan,
         for (int e = 0; e < n * n; ++e) A_out[(int64_t)i * n * n + e] = A[e];
     if (a_out)
         for (int e = 0; e < n; ++e) a_out[(int64_t)i * n + e] = av[e];
+    if (write_model && i == 0 && lane == 0) p.ltv = 1;  // the intervals now differ
     if (write_model && i < p.N - 1) {
         for (int e = 0; e < n * n; ++e) p.A[(int64_t)i * n * n + e] = A[e];
         for (int e = 0; e < n; ++e) p.a[(int64_t)i * n + e] = av[e];
