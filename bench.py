@@ -93,6 +93,14 @@ def timed_solve(pg, probs, precision, steps, warmup, iters, segments=0, lanes=0,
     (launched directly, since events inside a graph cannot be timed) to get
     each kernel's mean duration."""
     import torch
+    if segments or lanes:
+        # explicit shapes override the tuned per-plan ones
+        probs = [dict(p) for p in probs]
+        for p in probs:
+            if segments:
+                p["segments"] = segments
+            if lanes:
+                p["lanes_per_factor"] = lanes
     ctx = pg.pgvimp_create(probs, precision=precision, use_graph=True, segments=segments, lanes=lanes,
                            trial_width=trial_width, trial_lookahead=trial_lookahead)
     for _ in range(warmup):

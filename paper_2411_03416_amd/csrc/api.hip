@@ -332,7 +332,7 @@ static int64_t carve(pgvimp_ctx* c, const pgvimp_engine_cfg* cfg, DevState& st, 
     const int64_t S = cfg->max_states, P = cfg->max_plans;
     const int dmax = std::min(n, PGVIMP_MAX_COLL_DIM);
     const int ws_stride = 3 * n * n + n;
-    const int seg_stride = 7 * n * n + 5 * n;  // SegLayout<n>::STRIDE
+    const int seg_stride = 6 * n * n + 3 * n;  // SegLayout<n>::STRIDE
     int64_t off = 0;
     auto take = [&](auto** ptr, int64_t bytes) {
         if (base) *ptr = (std::remove_reference_t<decltype(**ptr)>*)(base + off);

@@ -1,7 +1,8 @@
 // Chain kernels: marginal covariances of the block-tridiagonal precision
 // (Gaussian belief propagation on the chain, Sec. 5.1), the block-
 // tridiagonal mean solve of Theorem 1, and the fused step-size loop of
-// Alg. 1 / App. C.  One wavefront (64 lanes) factors one matrix of one plan.
+// Alg. 1 / App. C.  One wavefront (64 lanes, one per segment) factors one
+// matrix of one plan.
 //
 // Parallel form.  GBP on a chain is exact and equals the block-tridiagonal
 // selected inverse (Sigma_ii, Sigma_{i,i+1}).  Instead of one sequential
@@ -48,27 +49,35 @@
 namespace pg {
 
 // Entry offsets in the per-segment scratch, stored field-major:
-// sg[f * kMaxSeg + j] is field f of slot j.  Slot j holds segment j's
-// contributions to its separators and, for the reduced chain, the data of
-// separator j (node j).
+// sg[f * kMaxSeg + j] is field f of slot j.  Slot j holds the data of
+// separator j (node j) of the reduced chain; before the nodes are
+// assembled, the first fields hold segment j's contributions to its two
+// separators (they are read into registers before the node fields are
+// written).  For small blocks the scratch lives in LDS.
 template <int n>
 struct SegLayout {
-    static constexpr int DL = 0;              // Schur contribution to left separator
-    static constexpr int DR = n * n;          // ... to right separator
-    static constexpr int CLR = 2 * n * n;     // coupling block (left sep, right sep)
-    // node j; NGL/NGR reuse DL/DR, which are consumed when the nodes are assembled
-    static constexpr int NGL = 0;             // pivot^-1 M(j, left neighbour)
-    static constexpr int NGR = n * n;         // pivot^-1 M(j, right neighbour)
-    static constexpr int NA = 3 * n * n;      // current diagonal block; Sigma_jj after the backward pass
-    static constexpr int NC = 4 * n * n;      // coupling M(j, right neighbour at the current level)
-    static constexpr int NP = 5 * n * n;      // pivot inverse at elimination
-    static constexpr int NX = 6 * n * n;      // Cov(j, right neighbour at j's level); Cov(j, j+1) at the end
-    static constexpr int RL = 7 * n * n;      // rhs contribution to left separator
-    static constexpr int RR = 7 * n * n + n;  // ... to right separator
-    static constexpr int NR = 7 * n * n + 2 * n;  // current rhs of node j
-    static constexpr int NZ = 7 * n * n + 3 * n;  // pivot^-1 rhs at elimination
-    static constexpr int XS = 7 * n * n + 4 * n;  // solution at separator j
-    static constexpr int STRIDE = 7 * n * n + 5 * n;
+    static constexpr int NA = 0;              // current diagonal block; Sigma_jj after the backward pass
+    static constexpr int NC = n * n;          // coupling M(j, right neighbour at the current level)
+    static constexpr int NP = 2 * n * n;      // pivot inverse at elimination
+    static constexpr int NGL = 3 * n * n;     // pivot^-1 M(j, left neighbour)
+    static constexpr int NGR = 4 * n * n;     // pivot^-1 M(j, right neighbour)
+    static constexpr int NX = 5 * n * n;      // Cov(j, right neighbour at j's level); Cov(j, j+1) at the end
+    static constexpr int NR = 6 * n * n;      // current rhs of node j
+    static constexpr int NZ = 6 * n * n + n;  // pivot^-1 rhs at elimination
+    static constexpr int XS = 6 * n * n + 2 * n;  // solution at separator j
+    static constexpr int STRIDE = 6 * n * n + 3 * n;
+    // segment j's contributions before assembly (aliases)
+    static constexpr int DL = NA;    // Schur contribution to the left separator
+    static constexpr int DR = NC;    // ... to the right separator
+    static constexpr int CLR = NP;   // coupling block (left sep, right sep)
+    static constexpr int RL = NR;    // rhs contribution to the left separator
+    static constexpr int RR = NZ;    // ... to the right separator
+};
+// Node scratch in LDS (both halves of a workgroup) for small blocks.
+template <int n>
+struct NodeLds {
+    static constexpr bool value = RegBlocks<n>::value;
+    static constexpr int size = value ? 2 * kMaxSeg * SegLayout<n>::STRIDE : 1;
 };
 
 // Field f of slot j of the segment scratch.
@@ -369,26 +378,35 @@ PG_UNROLL
 }
 
 // Node j's diagonal block, right coupling and rhs from its separator state
-// and the two adjacent segments.
+// and the two adjacent segments: read into registers (A, C, r) ...
 template <int n, bool RHS>
-__device__ __forceinline__ void cr_assemble(const BlockSrc& M, int N, int nseg, int j, double* sg, TS ts) {
+__device__ __forceinline__ void cr_assemble_read(const BlockSrc& M, int N, int nseg, int j, double* sg, double* A,
+                                                 double* C, double* r) {
     using G = SegLayout<n>;
     const int m = nseg - 1;
     const uint32_t q = sep_pos(N, nseg, j);
-    PG_MAT(A, ts);
     src_D<n>(M, toff<n * n>(q), A);
 PG_UNROLL
-    for (int e = 0; e < n * n; ++e) A[e] += sgv(sg, j, G::DR + e) + sgv(sg, j + 1, G::DL + e);
-    st_node<n>(sg, j, G::NA, A);
-    if (j + 1 < m) {
-PG_UNROLL
-        for (int e = 0; e < n * n; ++e) sgv(sg, j, G::NC + e) = sgv(sg, j + 1, G::CLR + e);
+    for (int e = 0; e < n * n; ++e) {
+        A[e] += sgv(sg, j, G::DR + e) + sgv(sg, j + 1, G::DL + e);
+        C[e] = j + 1 < m ? sgv(sg, j + 1, G::CLR + e) : 0.0;
     }
     if (RHS) {
-        PG_VEC(r, ts);
         src_r<n>(M, toff<n>(q), r);
 PG_UNROLL
-        for (int e = 0; e < n; ++e) sgv(sg, j, G::NR + e) = r[e] + sgv(sg, j, G::RR + e) + sgv(sg, j + 1, G::RL + e);
+        for (int e = 0; e < n; ++e) r[e] += sgv(sg, j, G::RR + e) + sgv(sg, j + 1, G::RL + e);
+    }
+}
+// ... and, after a barrier, written as the node's fields.
+template <int n, bool RHS>
+__device__ __forceinline__ void cr_assemble_write(int j, double* sg, const double* A, const double* C,
+                                                  const double* r) {
+    using G = SegLayout<n>;
+    st_node<n>(sg, j, G::NA, A);
+    st_node<n>(sg, j, G::NC, C);
+    if (RHS) {
+PG_UNROLL
+        for (int e = 0; e < n; ++e) sgv(sg, j, G::NR + e) = r[e];
     }
 }
 
@@ -743,7 +761,14 @@ __device__ __forceinline__ bool wg_gbp(const BlockSrc& M, const Ws& ws, int tid,
     bool ok = true;
     if (tid < nseg) ok = seg_forward<n, false>(M, N, nseg, tid, ws, sg, &ld, ts);
     __syncthreads();
-    if (tid < m) cr_assemble<n, false>(M, N, nseg, tid, sg, ts);
+    {
+        PG_MAT(A, ts);
+        PG_MAT(C, ts);
+        PG_VEC(r, ts);
+        if (tid < m) cr_assemble_read<n, false>(M, N, nseg, tid, sg, A, C, r);
+        __syncthreads();
+        if (tid < m) cr_assemble_write<n, false>(tid, sg, A, C, r);
+    }
     __syncthreads();
     ok = cr_forward<n, false>(m, tid, sg, &ld, ts) && ok;
     sh_ld[tid] = ld;
@@ -777,7 +802,14 @@ __device__ __forceinline__ bool wg_solve(const BlockSrc& M, const Ws& ws, int ti
     bool ok = true;
     if (tid < nseg) ok = seg_forward<n, true>(M, N, nseg, tid, ws, sg, &ld, ts);
     __syncthreads();
-    if (tid < m) cr_assemble<n, true>(M, N, nseg, tid, sg, ts);
+    {
+        PG_MAT(A, ts);
+        PG_MAT(C, ts);
+        PG_VEC(r, ts);
+        if (tid < m) cr_assemble_read<n, true>(M, N, nseg, tid, sg, A, C, r);
+        __syncthreads();
+        if (tid < m) cr_assemble_write<n, true>(tid, sg, A, C, r);
+    }
     __syncthreads();
     ok = cr_forward<n, true>(m, tid, sg, &ld, ts) && ok;
     sh_ok[tid] = ok ? 1 : 0;
@@ -939,7 +971,8 @@ __global__ void __launch_bounds__(kTrialThreads) chain_kernel(DevState st, int m
     const int half = tid / kChainThreads, lane = tid % kChainThreads;
     const int N = p.N, nseg = p.nseg;
     const int64_t off = p.off, S = st.S, coff = p.coff;
-    double* sg = seg_scratch<n>(st, pid, 0, half);
+    __shared__ double sg_lds[NodeLds<n>::size];
+    double* sg = NodeLds<n>::value ? sg_lds + half * kMaxSeg * SegLayout<n>::STRIDE : seg_scratch<n>(st, pid, 0, half);
     const Ws ws = sweep_ws<n>(st, half, coff);
     TS ts = thread_ws<n>(st, pid, 0);
     const bool prior = mode == CHAIN_INIT || mode == CHAIN_REINIT;
@@ -1041,9 +1074,12 @@ __global__ void __launch_bounds__(kIterThreads) prep_kernel(DevState st) {
         if (act) {
             ecol += st.Ecol[s];
             for (int a = 0; a < d; ++a) {
-                r[p.coll_index[a]] -= st.gcol[a * S + s];
+                const double ga = st.gcol[a * S + s];
+                const int ca = p.coll_index[a];
+PG_UNROLL
+                for (int e = 0; e < n; ++e) r[e] -= e == ca ? ga : 0.0;  // static indexing keeps r in registers
                 for (int b2 = 0; b2 < d; ++b2) {
-                    const int e = p.coll_index[a] * n + p.coll_index[b2];
+                    const int e = ca * n + p.coll_index[b2];
                     st.cKH[tidx<NN>(q, e)] = st.KD[e * S + s] + st.Hcol[(a * d + b2) * S + s];
                 }
             }
@@ -1130,7 +1166,8 @@ __global__ void __launch_bounds__(kTrialThreads) trial_kernel(DevState st, int r
     const int half = tid / kChainThreads, lane = tid % kChainThreads;
     const int N = p.N, nseg = p.nseg;
     const int64_t coff = p.coff, c0 = (int64_t)t * st.Sc + coff;
-    double* sg = seg_scratch<n>(st, pid, t, half);
+    __shared__ double sg_lds[NodeLds<n>::size];
+    double* sg = NodeLds<n>::value ? sg_lds + half * kMaxSeg * SegLayout<n>::STRIDE : seg_scratch<n>(st, pid, t, half);
     const Ws ws = sweep_ws<n>(st, half, c0);
     TS ts = thread_ws<n>(st, pid, t);
     double* res = st.tres + ((int64_t)pid * kMaxBisect + tt) * 4;

@@ -12,7 +12,7 @@
 namespace pg {
 
 constexpr int kMaxSeg = 64;      // chain segments per plan (upper bound)
-constexpr int kChainThreads = 64; // one wavefront per plan in the chain kernel
+constexpr int kChainThreads = 64; // one wavefront per factorization, one lane per segment
 constexpr int kTrialThreads = 128; // trial kernel: marginals and mean solve side by side
 constexpr int kIterThreads = 128;  // prep/select kernels (uses the trial kernel's per-thread slots)
 constexpr int kIterBlocks = 8;     // prep/select blocks per plan (at most W)

@@ -62,7 +62,7 @@ def test_marginals_segment_counts_agree(pg):
     D, U = rand_chain(rng, N, n)
     Sr, Sor, ldr = gbp.gbp_marginals(D, U)
     prob = workloads.free_problem(n_dof=2, N=N)
-    for seg in (1, 2, 5, 16, 64):
+    for seg in (1, 2, 5, 16, 33, 64):
         ctx = pg.pgvimp_create([prob], segments=seg, use_graph=False)
         pg.pgvimp_set_state(ctx, 0, np.zeros((N, n)), D, U)
         S, So, ld = pg.pgvimp_marginals(ctx, 0)
