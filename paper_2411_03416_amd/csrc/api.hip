@@ -237,9 +237,12 @@ int upload_plan(pgvimp_ctx* c, int plan) {
 }
 
 int download_plans(pgvimp_ctx* c) {
+    int32_t flags[16] = {0};
     HCK(c, hipMemcpyAsync(c->pdev.data(), c->st.plans, sizeof(PlanDev) * c->pdev.size(), hipMemcpyDeviceToHost,
                           c->stream));
+    HCK(c, hipMemcpyAsync(flags, c->st.flags, sizeof(flags), hipMemcpyDeviceToHost, c->stream));
     HCK(c, hipStreamSynchronize(c->stream));
+    if (flags[0]) FAIL(c, PGVIMP_EDEVICE, "block workspace overflow in a chain kernel (library defect)");
     return PGVIMP_OK;
 }
 
@@ -364,8 +367,9 @@ static int64_t carve(pgvimp_ctx* c, const pgvimp_engine_cfg* cfg, DevState& st, 
     take(&st.Epri, (S + P) * 8);
     take(&st.ws, 2 * W * Sc * ws_stride * 8);
     take(&st.seg, P * W * 2 * kMaxSeg * (int64_t)seg_stride * 8);
-    const int64_t tws_stride = (int64_t)kTwsBlocks * n * n + (int64_t)kTwsVecs * n;
+    const int64_t tws_stride = n > 4 ? (int64_t)kTwsBlocks * n * n + (int64_t)kTwsVecs * n : 0;
     take(&st.tws, P * W * kTrialThreads * tws_stride * 8);
+    take(&st.flags, 16 * 4);
     take(&st.gh_x64, (kMaxGH + 1) * kMaxGH * 8);
     take(&st.gh_w64, (kMaxGH + 1) * kMaxGH * 8);
     take(&st.gh_x32, (kMaxGH + 1) * kMaxGH * 4);
@@ -423,6 +427,7 @@ static int ctx_alloc(pgvimp_ctx* c) {
     gh_tables(X, W);
     std::vector<float> Xf(X.begin(), X.end()), Wf(W.begin(), W.end());
     HCK(c, hipMemcpy((void*)st.gh_x64, X.data(), X.size() * 8, hipMemcpyHostToDevice));
+    HCK(c, hipMemset(st.flags, 0, 16 * 4));
     HCK(c, hipMemcpy((void*)st.gh_w64, W.data(), W.size() * 8, hipMemcpyHostToDevice));
     HCK(c, hipMemcpy((void*)st.gh_x32, Xf.data(), Xf.size() * 4, hipMemcpyHostToDevice));
     HCK(c, hipMemcpy((void*)st.gh_w32, Wf.data(), Wf.size() * 4, hipMemcpyHostToDevice));

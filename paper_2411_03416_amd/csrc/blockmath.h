@@ -15,11 +15,19 @@ struct RegBlocks {
     static constexpr bool value = (n <= 4);
 };
 
-// Bump allocator over a thread's workspace.  Passed by value: a callee's
-// allocations end when it returns.
+// Bump allocator over a thread's workspace [p, end).  Passed by value: a
+// callee's allocations end when it returns.  A request past the end sets
+// *flag (the host then fails the call) and reuses the last slots, so no
+// access leaves the thread's slice.
 struct TS {
     double* p;
+    double* end;
+    int* flag;
     __device__ __forceinline__ double* take(int cnt) {
+        if (p + cnt > end) {
+            *flag = 1;
+            return end - cnt;
+        }
         double* r = p;
         p += cnt;
         return r;

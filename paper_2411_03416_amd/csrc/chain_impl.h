@@ -265,7 +265,8 @@ __device__ __forceinline__ bool seg_forward(const BlockSrc& M, int N, int nseg, 
     src_D<n>(M, toff<NN>(ps.at(a)), P);
     src_U<n>(M, toff<NN>(ps.at(a)), U);  // every segment has >= 2 states, so U_a exists
     {
-        PG_MAT(UL, ts);
+        TS ut = ts;
+        PG_MAT(UL, ut);
         src_U<n>(M, toff<NN>(hasL ? sep_pos(N, nseg, j - 1) : ps.at(a)), UL);
 PG_UNROLL
         for (int r = 0; r < n; ++r)
@@ -508,15 +509,49 @@ PG_UNROLL
     return ok;
 }
 
+// Contributions to the KL terms of a trial (Theorem 1 step, App. C), added
+// where the blocks they need are produced:
+//   trace: tr(KH_i Sigma'_ii) with Sigma'_ii symmetrised, and
+//          2 tr(KU_i^T Sigma'_{i,i+1});
+//   quad:  d_i^T LD_i d_i and 2 d_i^T LU_i d_{i+1}, d = mu' - mu_k.
+template <int n>
+__device__ __forceinline__ double tr_diag(const double* K, const double* Sg) {
+    double t = 0.0;
+PG_UNROLL
+    for (int r = 0; r < n; ++r)
+PG_UNROLL
+        for (int k = 0; k < n; ++k) t = fma(K[r * n + k], 0.5 * (Sg[k * n + r] + Sg[r * n + k]), t);
+    return t;
+}
+template <int n>
+__device__ __forceinline__ double tr_off(const double* K, const double* So) {
+    double t = 0.0;
+PG_UNROLL
+    for (int e = 0; e < n * n; ++e) t = fma(K[e], So[e], t);
+    return 2.0 * t;
+}
+template <int n>
+__device__ __forceinline__ double quad_form(const double* L, const double* u, const double* v) {
+    double t = 0.0;
+PG_UNROLL
+    for (int r = 0; r < n; ++r) {
+        double w = 0.0;
+PG_UNROLL
+        for (int c = 0; c < n; ++c) w = fma(L[r * n + c], v[c], w);
+        t = fma(u[r], w, t);
+    }
+    return t;
+}
+
 // Backward selected inversion, top level first: node k eliminated at level l
 // with neighbours L, R (whose covariances are known from higher levels):
 //   Cov(k, L) = -(G_L S_LL + G_R S_RL),  Cov(k, R) = -(G_L S_LR + G_R S_RR),
 //   S_kk = P - Cov(k, L) G_L^T - Cov(k, R) G_R^T.
 // Writes S_kk (node and SDo) and the cross-covariances of the two new
 // adjacent pairs (L, k) and (k, R).  run = false keeps the barriers only.
-template <int n>
+template <int n, bool TRACE>
 __device__ __forceinline__ void cr_backward_cov(int m, int j, bool run, int N, int nseg, double* sg, double* SDo,
-                                                TS ts) {
+                                                const double* KH, double* trace, TS ts) {
     using G = SegLayout<n>;
     const int levels = cr_levels(m);
     const bool own = run && j < m;
@@ -566,7 +601,12 @@ PG_UNROLL
                 msub_nt<n>(CR, GR, Sk);
             }
             st_node<n>(sg, j, G::NA, Sk);
-            stt_sym<n>(SDo, toff<n * n>(sep_pos(N, nseg, j)), Sk);
+            const uint32_t oS = toff<n * n>(sep_pos(N, nseg, j));
+            stt_sym<n>(SDo, oS, Sk);
+            if (TRACE) {
+                ldt<n, n * n>(KH, oS, T);
+                *trace += tr_diag<n>(T, Sk);
+            }
             if (hasL) {
 PG_UNROLL
                 for (int r = 0; r < n; ++r)
@@ -580,9 +620,9 @@ PG_UNROLL
 }
 
 // Backward substitution: x_k = z_k - G_L x_L - G_R x_R, top level first.
-template <int n>
+template <int n, bool QUAD>
 __device__ __forceinline__ void cr_backward_rhs(int m, int j, bool run, int N, int nseg, double* sg, double* xo,
-                                                TS ts) {
+                                                const double* LD, const double* mu0, double* quad, TS ts) {
     using G = SegLayout<n>;
     const int levels = cr_levels(m);
     const bool own = run && j < m;
@@ -610,7 +650,15 @@ PG_UNROLL
             }
 PG_UNROLL
             for (int e = 0; e < n; ++e) sgv(sg, j, G::XS + e) = x[e];
-            stt<n, n>(xo, toff<n>(sep_pos(N, nseg, j)), x);
+            const uint32_t q = sep_pos(N, nseg, j);
+            stt<n, n>(xo, toff<n>(q), x);
+            if (QUAD) {
+                ldt<n, n * n>(LD, toff<n * n>(q), Gk);
+                ldt<n, n>(mu0, toff<n>(q), y);
+PG_UNROLL
+                for (int e = 0; e < n; ++e) y[e] = x[e] - y[e];
+                *quad += quad_form<n>(Gk, y, y);
+            }
         }
         __syncthreads();
     }
@@ -623,9 +671,10 @@ PG_UNROLL
 // Branch-free: the forward sweep stored zero GU after the chain's last state
 // and zero HX where there is no left separator; missing separator
 // covariances are zero blocks.
-template <int n>
+template <int n, bool TRACE>
 __device__ __forceinline__ void seg_backward_cov(int N, int nseg, int j, const Ws& ws, double* sg, double* SDo,
-                                                 double* SUo, TS ts) {
+                                                 double* SUo, const double* KH, const double* KU, double* trace,
+                                                 TS ts) {
     using G = SegLayout<n>;
     constexpr int NN = n * n;
     int a, b;
@@ -657,6 +706,8 @@ PG_UNROLL
     PG_MAT(Pn, ts);
     PG_MAT(Gn, ts);
     PG_MAT(Hn, ts);
+    PG_MAT(Kd, ts);  // trace blocks KH_i, KU_i (loaded at the top of step i, used at its end)
+    PG_MAT(Ku, ts);
     {
         const uint32_t ob = toff<NN>(ps.at(b));
         ldt<n, NN>(ws.P, ob, Pc);
@@ -666,9 +717,14 @@ PG_UNROLL
     for (int i = b; i >= a; --i) {
         TS lt = ts;
         const uint32_t oB = toff<NN>(ps.at(i)), oBp = toff<NN>(ps.at(i > a ? i - 1 : a));
+        const bool hasNext = i < b || hasR;
         ldt<n, NN>(ws.P, oBp, Pn);
         ldt<n, NN>(ws.G, oBp, Gn);
         ldt<n, NN>(ws.H, oBp, Hn);
+        if (TRACE) {
+            ldt<n, NN>(KH, oB, Kd);
+            ldt<n, NN>(KU, oB, Ku);
+        }
         PG_MAT(Sin, lt);
         PG_MAT(SiL, lt);
         PG_MAT(T, lt);
@@ -685,6 +741,10 @@ PG_UNROLL
         msub_nt<n>(SiL, Hc, Pc);
         stt<n, NN>(SUo, oB, Sin);
         stt_sym<n>(SDo, oB, Pc);
+        if (TRACE) {
+            const double to = tr_off<n>(Ku, Sin);
+            *trace += tr_diag<n>(Kd, Pc) + (hasNext ? to : 0.0);
+        }
         mcopy<n>(Pc, Snn);
         mcopy<n>(SiL, SnL);
         mcopy<n>(Pn, Pc);
@@ -693,18 +753,24 @@ PG_UNROLL
     }
     if (hasL) {
         // Cov(L, a) = Cov(a, L)^T
-        PG_MAT(T, ts);
+        TS lt = ts;
+        PG_MAT(T, lt);
 PG_UNROLL
         for (int r = 0; r < n; ++r)
 PG_UNROLL
             for (int c = 0; c < n; ++c) T[r * n + c] = SnL[c * n + r];
         stt<n, NN>(SUo, toff<NN>(qL), T);
+        if (TRACE) {
+            ldt<n, NN>(KU, toff<NN>(qL), Ku);
+            *trace += tr_off<n>(Ku, T);
+        }
     }
 }
 
 // Backward substitution of segment j: x_i = P_i^-1 y_i - GU_i x_next - HX_i x_L.
-template <int n>
+template <int n, bool QUAD>
 __device__ __forceinline__ void seg_backward_rhs(int N, int nseg, int j, const Ws& ws, double* sg, double* xo,
+                                                 const double* LD, const double* LU, const double* mu0, double* quad,
                                                  TS ts) {
     using G = SegLayout<n>;
     constexpr int NN = n * n;
@@ -727,19 +793,44 @@ PG_UNROLL
     ldt<n, NN>(ws.G, toff<NN>(ps.at(b)), Gc);
     ldt<n, NN>(ws.H, toff<NN>(ps.at(b)), Hc);
     ldt<n, n>(ws.Y, toff<n>(ps.at(b)), yc);
+    // d of the state after the current one (the right separator first)
+    PG_VEC(dn, ts);
+    if (QUAD) {
+        ldt<n, n>(mu0, toff<n>(hasR ? ps.at(b + 1) : ps.at(b)), dn);
+PG_UNROLL
+        for (int e = 0; e < n; ++e) dn[e] = hasR ? xn[e] - dn[e] : 0.0;
+    }
+    PG_MAT(Ld, ts);  // quadratic-term blocks (loaded at the top of step i, used at its end)
+    PG_MAT(Lu, ts);
+    PG_VEC(m0, ts);
     for (int i = b; i >= a; --i) {
         TS lt = ts;
         const uint32_t q = ps.at(i), qp = ps.at(i > a ? i - 1 : a);
         const uint32_t oBp = toff<NN>(qp), oVp = toff<n>(qp);
+        const bool hasNext = i < b || hasR;
         ldt<n, NN>(ws.G, oBp, Gn);
         ldt<n, NN>(ws.H, oBp, Hn);
         ldt<n, n>(ws.Y, oVp, yn);
+        if (QUAD) {
+            ldt<n, NN>(LD, toff<NN>(q), Ld);
+            ldt<n, NN>(LU, toff<NN>(q), Lu);
+            ldt<n, n>(mu0, toff<n>(q), m0);
+        }
         PG_VEC(x, lt);
 PG_UNROLL
         for (int e = 0; e < n; ++e) x[e] = yc[e];
         mvec_sub<n>(Gc, xn, x);
         mvec_sub<n>(Hc, xL, x);
         stt<n, n>(xo, toff<n>(q), x);
+        if (QUAD) {
+            PG_VEC(d, lt);
+PG_UNROLL
+            for (int e = 0; e < n; ++e) d[e] = x[e] - m0[e];
+            const double cross = 2.0 * quad_form<n>(Lu, d, dn);
+            *quad += quad_form<n>(Ld, d, d) + (hasNext ? cross : 0.0);
+PG_UNROLL
+            for (int e = 0; e < n; ++e) dn[e] = d[e];
+        }
 PG_UNROLL
         for (int e = 0; e < n; ++e) xn[e] = x[e];
         mcopy<n>(Gn, Gc);
@@ -747,24 +838,36 @@ PG_UNROLL
 PG_UNROLL
         for (int e = 0; e < n; ++e) yc[e] = yn[e];
     }
+    if (QUAD && hasL) {
+        // 2 d_L^T LU_L d_a, L = left separator, a = first state (d_a in dn)
+        const uint32_t qL = sep_pos(N, nseg, j - 1);
+        TS lt = ts;
+        PG_VEC(dL, lt);
+        ldt<n, NN>(LU, toff<NN>(qL), Lu);
+        ldt<n, n>(mu0, toff<n>(qL), dL);
+PG_UNROLL
+        for (int e = 0; e < n; ++e) dL[e] = xL[e] - dL[e];
+        *quad += 2.0 * quad_form<n>(Lu, dL, dn);
+    }
 }
 
 // Workgroup-wide GBP of the matrix in M into (SDo, SUo), log det
 // and PD flag; all arrays offset to the plan's chain range.  Called by every
 // lane of the half (tid = lane); sh_ld / sh_ok hold kChainThreads + 1 entries.
-template <int n>
+template <int n, bool TRACE>
 __device__ __forceinline__ bool wg_gbp(const BlockSrc& M, const Ws& ws, int tid, int N, int nseg, double* sg,
                                        double* SDo, double* SUo, double* logdet_out, double* sh_ld, int* sh_ok,
-                                       TS ts) {
+                                       double* trace, TS ts) {
     const int m = nseg - 1;
     double ld = 0.0;
     bool ok = true;
     if (tid < nseg) ok = seg_forward<n, false>(M, N, nseg, tid, ws, sg, &ld, ts);
     __syncthreads();
     {
-        PG_MAT(A, ts);
-        PG_MAT(C, ts);
-        PG_VEC(r, ts);
+        TS at = ts;
+        PG_MAT(A, at);
+        PG_MAT(C, at);
+        PG_VEC(r, at);
         if (tid < m) cr_assemble_read<n, false>(M, N, nseg, tid, sg, A, C, r);
         __syncthreads();
         if (tid < m) cr_assemble_write<n, false>(tid, sg, A, C, r);
@@ -787,25 +890,26 @@ __device__ __forceinline__ bool wg_gbp(const BlockSrc& M, const Ws& ws, int tid,
     __syncthreads();
     const bool okall = sh_ok[kChainThreads] != 0;
     *logdet_out = sh_ld[kChainThreads];
-    cr_backward_cov<n>(m, tid, okall, N, nseg, sg, SDo, ts);
-    if (okall && tid < nseg) seg_backward_cov<n>(N, nseg, tid, ws, sg, SDo, SUo, ts);
+    cr_backward_cov<n, TRACE>(m, tid, okall, N, nseg, sg, SDo, M.D0, trace, ts);
+    if (okall && tid < nseg) seg_backward_cov<n, TRACE>(N, nseg, tid, ws, sg, SDo, SUo, M.D0, M.U0, trace, ts);
     __syncthreads();
     return okall;
 }
 
 // Workgroup-wide solve of (D, U) x = r into xo (same barriers as wg_gbp).
-template <int n>
+template <int n, bool QUAD>
 __device__ __forceinline__ bool wg_solve(const BlockSrc& M, const Ws& ws, int tid, int N, int nseg, double* sg,
-                                         double* xo, int* sh_ok, TS ts) {
+                                         double* xo, int* sh_ok, const double* mu0, double* quad, TS ts) {
     const int m = nseg - 1;
     double ld = 0.0;
     bool ok = true;
     if (tid < nseg) ok = seg_forward<n, true>(M, N, nseg, tid, ws, sg, &ld, ts);
     __syncthreads();
     {
-        PG_MAT(A, ts);
-        PG_MAT(C, ts);
-        PG_VEC(r, ts);
+        TS at = ts;
+        PG_MAT(A, at);
+        PG_MAT(C, at);
+        PG_VEC(r, at);
         if (tid < m) cr_assemble_read<n, true>(M, N, nseg, tid, sg, A, C, r);
         __syncthreads();
         if (tid < m) cr_assemble_write<n, true>(tid, sg, A, C, r);
@@ -821,8 +925,8 @@ __device__ __forceinline__ bool wg_solve(const BlockSrc& M, const Ws& ws, int ti
     }
     __syncthreads();
     const bool okall = sh_ok[kChainThreads] != 0;
-    cr_backward_rhs<n>(m, tid, okall, N, nseg, sg, xo, ts);
-    if (okall && tid < nseg) seg_backward_rhs<n>(N, nseg, tid, ws, sg, xo, ts);
+    cr_backward_rhs<n, QUAD>(m, tid, okall, N, nseg, sg, xo, M.D1, mu0, quad, ts);
+    if (okall && tid < nseg) seg_backward_rhs<n, QUAD>(N, nseg, tid, ws, sg, xo, M.D1, M.U1, mu0, quad, ts);
     __syncthreads();
     return okall;
 }
@@ -938,7 +1042,8 @@ __device__ __forceinline__ double* seg_scratch(const DevState& st, int pid, int 
 }
 template <int n>
 __device__ __forceinline__ TS thread_ws(const DevState& st, int pid, int t) {
-    return TS{st.tws + (((int64_t)pid * st.W + t) * kTrialThreads + threadIdx.x) * st.tws_stride};
+    double* base = st.tws + (((int64_t)pid * st.W + t) * kTrialThreads + threadIdx.x) * st.tws_stride;
+    return TS{base, base + st.tws_stride, st.flags};
 }
 // Sweep temporaries of one half for the chain range starting at position c0
 // (trial slot included): four tiled arrays of W * Sc positions each.
@@ -999,11 +1104,12 @@ __global__ void __launch_bounds__(kTrialThreads) chain_kernel(DevState st, int m
         const double *d = cD + coff * NN, *u = cU + coff * NN;
         BlockSrc M{d, d, u, u, d, d, 1.0, 0.0};
         double ld = 0.0;
-        wg_gbp<n>(M, ws, lane, N, nseg, sg, st.TSD + coff * NN, st.TSU + coff * NN, &ld, sh_d, sh_i, ts);
+        wg_gbp<n, false>(M, ws, lane, N, nseg, sg, st.TSD + coff * NN, st.TSU + coff * NN, &ld, sh_d, sh_i, nullptr,
+                         ts);
     } else {
         const double *kd = st.cKD + coff * NN, *ku = st.cKU + coff * NN, *r = st.crb + coff * n;
         BlockSrc M{kd, kd, ku, ku, r, r, 1.0, 0.0};
-        wg_solve<n>(M, ws, lane, N, nseg, sg, st.Tmu + coff * n, sh_j, ts);
+        wg_solve<n, false>(M, ws, lane, N, nseg, sg, st.Tmu + coff * n, sh_j, nullptr, nullptr, ts);
     }
     __syncthreads();
     const bool ok = sh_i[kChainThreads] != 0;
@@ -1179,78 +1285,38 @@ __global__ void __launch_bounds__(kTrialThreads) trial_kernel(DevState st, int r
     const double *ku = st.cKU + coff * NN, *lU = st.cLU + coff * NN;
     const double *rb = st.crb + coff * n, *lmu = st.cLmu + coff * n, *cmu = st.cmu + coff * n;
     double *tsd = st.TSD + c0 * NN, *tsu = st.TSU + c0 * NN, *tmu = st.Tmu + c0 * n;
-    // wave 0: marginals and PD test of the trial precision; wave 1: trial mean.
-    // Both helpers pass the same workgroup barriers.
-    double ld_trial = 0.0;
+    // wave 0: marginals and PD test of the trial precision, with the trace
+    // term; wave 1: trial mean, with the quadratic term.  Both helpers pass
+    // the same workgroup barriers.
+    __shared__ double sh_t[kTrialThreads];
+    double part = 0.0, ld_trial = 0.0;
     if (half == 0) {
         BlockSrc MT{kh, lD, ku, lU, kh, lD, c * beta, c};
-        wg_gbp<n>(MT, ws, lane, N, nseg, sg, tsd, tsu, &ld_trial, sh_d, sh_i, ts);
+        wg_gbp<n, true>(MT, ws, lane, N, nseg, sg, tsd, tsu, &ld_trial, sh_d, sh_i, &part, ts);
     } else {
         BlockSrc MM{kd, lD, ku, lU, rb, lmu, 1.0, 1.0 / beta};
-        wg_solve<n>(MM, ws, lane, N, nseg, sg, tmu, sh_j, ts);
+        wg_solve<n, true>(MM, ws, lane, N, nseg, sg, tmu, sh_j, cmu, &part, ts);
     }
+    sh_t[tid] = part;
     __syncthreads();
-    const bool pd = sh_i[kChainThreads] != 0;
-    ld_trial = sh_d[kChainThreads];
-    __syncthreads();
-    if (!pd) {
-        if (tid == 0) {
+    if (tid == 0) {
+        const bool pd = sh_i[kChainThreads] != 0;
+        ld_trial = sh_d[kChainThreads];
+        if (!pd) {
             res[0] = 0.0;
             res[1] = NAN;
             res[2] = NAN;
             res[3] = beta;
+        } else {
+            // partial sums in lane order: trace from wave 0, quadratic from wave 1
+            double trKH = 0.0, quad = 0.0;
+            for (int k = 0; k < kChainThreads; ++k) trKH += sh_t[k];
+            for (int k = 0; k < kChainThreads; ++k) quad += sh_t[kChainThreads + k];
+            res[0] = 1.0;
+            res[1] = 0.5 * (beta * (T * (double)N * n - trKH) + quad + ld_trial - p.logdet);
+            res[2] = ld_trial;
+            res[3] = beta;
         }
-        return;
-    }
-    // trace and quadratic terms over the chain range (consecutive positions
-    // per thread), pairs (i, i+1) through the successor's position
-    double trKH = 0.0, quad = 0.0;
-    const int clen = chain_len(N, nseg);
-    for (int ql = tid; ql < clen; ql += kTrialThreads) {
-        const int j = ql % nseg, il = ql / nseg;
-        const int i0 = seg_start(N, nseg, j), len = seg_start(N, nseg, j + 1) - i0;
-        if (il >= len) continue;
-        const int i = i0 + il;
-        TS lt = ts;
-        const uint32_t oB = toff<NN>(ql), oV = toff<n>(ql);
-        PG_MAT(Sg, lt);
-        PG_MAT(Dm, lt);
-        PG_VEC(dm, lt);
-        PG_VEC(tv, lt);
-        ldt<n, NN>(tsd, oB, Sg);
-PG_UNROLL
-        for (int r = 0; r < n; ++r)
-PG_UNROLL
-            for (int k = 0; k < n; ++k) trKH = fma(ldo(kh, oB, r * n + k), Sg[k * n + r], trKH);
-PG_UNROLL
-        for (int e = 0; e < n; ++e) dm[e] = ldo(tmu, oV, e) - ldo(cmu, oV, e);
-        ldt<n, NN>(lD, oB, Dm);
-        mvec<n>(Dm, dm, tv);
-PG_UNROLL
-        for (int e = 0; e < n; ++e) quad = fma(dm[e], tv[e], quad);
-        if (i < N - 1) {
-            const int qln = il + 1 < len ? ql + nseg : j + 1;  // successor (next segment starts at il = 0)
-            const uint32_t oVn = toff<n>(qln);
-            PG_MAT(Su, lt);
-            PG_VEC(dn, lt);
-            ldt<n, NN>(tsu, oB, Su);
-PG_UNROLL
-            for (int e = 0; e < NN; ++e) trKH = fma(2.0 * ldo(ku, oB, e), Su[e], trKH);
-PG_UNROLL
-            for (int e = 0; e < n; ++e) dn[e] = ldo(tmu, oVn, e) - ldo(cmu, oVn, e);
-            ldt<n, NN>(lU, oB, Dm);
-            mvec<n>(Dm, dn, tv);
-PG_UNROLL
-            for (int e = 0; e < n; ++e) quad = fma(2.0 * dm[e], tv[e], quad);
-        }
-    }
-    trKH = wg_sum(trKH, sh_d);
-    quad = wg_sum(quad, sh_d);
-    if (tid == 0) {
-        res[0] = 1.0;
-        res[1] = 0.5 * (beta * (T * (double)N * n - trKH) + quad + ld_trial - p.logdet);
-        res[2] = ld_trial;
-        res[3] = beta;
     }
 }
 

@@ -18,11 +18,12 @@ constexpr int kIterThreads = 128;  // prep/select kernels (uses the trial kernel
 constexpr int kIterBlocks = 8;     // prep/select blocks per plan (at most W)
 constexpr int kMaxBisect = 64;     // step sizes of the halving sequence per iteration (upper bound)
 constexpr int kMaxGH = 10;        // Gauss-Hermite points per dimension
-// n x n temporaries a chain-kernel thread may hold at once.  Deepest call
-// paths: kernel loop body 1 + prior cost 8 = 9; segment elimination 9 +
-// Cholesky inverse 2 = 11; segment backward sweep 9 + 3 = 12.
-constexpr int kTwsBlocks = 14;
-constexpr int kTwsVecs = 16;  // n-vector temporaries (deepest path: 8)
+// n x n temporaries a chain-kernel thread may hold at once (n > 4; smaller
+// blocks live in registers).  Deepest call paths: segment elimination 15
+// live blocks + the first coupling 1 + Cholesky inverse 2 = 18 (8 vectors);
+// segment backward sweep 16 blocks; mean-solve backward sweep 10 vectors.
+constexpr int kTwsBlocks = 20;
+constexpr int kTwsVecs = 16;
 
 // Per-plan parameters and statistics, read by every kernel.  One entry per
 // plan slot; an empty slot has active = 0.
@@ -97,6 +98,7 @@ struct DevState {
     // n-vectors each)
     double* tws;
     int64_t tws_stride;
+    int* flags;  // [0]: a block workspace request overflowed
     // Gauss-Hermite 1-D tables [kMaxGH+1][kMaxGH] (row p), FP64 and FP32
     const double* gh_x64;
     const double* gh_w64;
