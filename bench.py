@@ -116,12 +116,14 @@ def timed_solve(pg, probs, precision, steps, warmup, iters, segments=0, lanes=0,
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     kt = None
+    evals = 0
     if profile:
         pg.pgvimp_profile(ctx, True)
         pg.pgvimp_kernel_times(ctx, reset=True)
         t1 = time.perf_counter()
         for _ in range(steps):
-            pg.pgvimp_solve(ctx, iters)
+            sp = pg.pgvimp_solve(ctx, iters)
+            evals += sum(v["evals_total"] for v in sp.values())
         kt = pg.pgvimp_kernel_times(ctx, reset=True)
         kt["eager_ms_per_step"] = 1e3 * (time.perf_counter() - t1) / steps
         pg.pgvimp_profile(ctx, False)
@@ -129,7 +131,30 @@ def timed_solve(pg, probs, precision, steps, warmup, iters, segments=0, lanes=0,
     seg, lanes_used = pg.pgvimp_launch_shape(ctx, probs[0]["N"])
     pg.pgvimp_destroy(ctx)
     return {"wall_s": wall, "step_ms": step_ms, "trials": trials, "kt": kt, "status": status,
-            "segments": seg, "lanes": lanes_used}
+            "segments": seg, "lanes": lanes_used, "evals": evals}
+
+
+def counter_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (profiles/<kernel>_config1_counters.txt: FETCH_SIZE and WRITE_SIZE
+    per launch, each scaled by the factor a 512 MiB copy kernel reads), or
+    None when the summary is missing or was taken on other kernel sources."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_config1_counters.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    src = os.path.join(ROOT, "paper_2411_03416_amd", "csrc", "chain_impl.h")
+    if kv.get("source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def pct(xs, q):
@@ -216,19 +241,22 @@ def main():
         exp_ms = kt["expect"][0]
         exp_bytes = 88.0 * B * N
         exp_gbs = exp_bytes / (exp_ms * 1e-3) / 1e9
-        # trial kernel: FP64 flops of the plain block-tridiagonal algorithm per
-        # state and step size the halving sequence tries (~10 n^3 for the
-        # marginals, ~5 n^3 for the mean solve); speculative trials beyond the
-        # accepted one are not counted
+        # trial kernel, per (evaluated step size, state): the GBP sweep of the
+        # trial precision reads D_i, U_i and writes Sigma_ii, Sigma_{i,i+1} with
+        # messages (48 n^2 B) and the update + mean solve moves (6 n^2 + 4 n)
+        # doubles: 1664 B for n = 4 (HBM bound at batch); FP64 ~18 n^3 flops
         trial_ms, trial_launches = kt["trial"]
-        alg_flops = 15.0 * n ** 3 * N * mixed["trials"]  # over the timed steps
-        flops_per_launch = alg_flops / trial_launches
-        trial_tf = flops_per_launch / (trial_ms * 1e-3) / 1e12
+        unit_bytes = 48.0 * n * n + 8.0 * (6 * n * n + 4 * n)
+        units_per_launch = mixed["evals"] * N / trial_launches
+        bytes_per_launch = unit_bytes * units_per_launch
+        trial_gbs = bytes_per_launch / (trial_ms * 1e-3) / 1e9
         totals = {k: v[0] * v[1] for k, v in kt.items() if isinstance(v, tuple)}
         tot = sum(totals.values())
-        rtrial = {"kernel": "trial_kernel<4>", "bound": "alu", "achieved": trial_tf, "peak": FP64_PEAK_TFLOPS,
-                  "unit": "TFLOP/s", "frac": trial_tf / FP64_PEAK_TFLOPS, "traffic": None,
-                  "avg_ms": trial_ms, "flops_per_launch": flops_per_launch}
+        rtrial = {"kernel": "trial_kernel<4>", "bound": "hbm", "achieved": trial_gbs, "peak": HBM_PEAK_GBS,
+                  "unit": "GB/s", "frac": trial_gbs / HBM_PEAK_GBS, "traffic": counter_traffic("trial_kernel"),
+                  "avg_ms": trial_ms, "bytes_per_launch": bytes_per_launch, "unit_bytes": unit_bytes,
+                  "units_per_launch": units_per_launch,
+                  "fp64_tflops": 18.0 * n ** 3 * units_per_launch / (trial_ms * 1e-3) / 1e12}
         rexp = {"kernel": "expect_kernel<float,2,5,32,point2d>", "bound": "hbm", "achieved": exp_gbs,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": exp_gbs / HBM_PEAK_GBS, "traffic": None,
                 "avg_ms": exp_ms, "bytes_per_launch": exp_bytes}

@@ -176,6 +176,8 @@ typedef struct pgvimp_stats {
     int32_t trials; /* step sizes tried in the last iteration               */
     int32_t iters_done, iters_left;
     int32_t trials_total; /* step sizes tried since the plan was (re)started  */
+    int32_t evals_total;  /* step sizes evaluated since then, counting the
+                             speculative ones of each window (>= trials_total) */
 } pgvimp_stats;
 
 /*

@@ -63,7 +63,7 @@ class Stats(C.Structure):
         ("beta", C.c_double), ("kl", C.c_double), ("E_coll", C.c_double), ("E_prior", C.c_double),
         ("logdet", C.c_double), ("entropy", C.c_double),
         ("status", C.c_int32), ("trials", C.c_int32), ("iters_done", C.c_int32), ("iters_left", C.c_int32),
-        ("trials_total", C.c_int32),
+        ("trials_total", C.c_int32), ("evals_total", C.c_int32),
     ]
 
     def as_dict(self):

@@ -926,6 +926,7 @@ static int run_iters(pgvimp_ctx* c, int32_t n_iters, pgvimp_stats* per_plan, boo
             s.iters_done = p.iters_done;
             s.iters_left = p.iters_left;
             s.trials_total = p.trials_total;
+            s.evals_total = p.evals_total;
         }
     }
     return PGVIMP_OK;

@@ -1120,6 +1120,7 @@ __global__ void __launch_bounds__(kTrialThreads) chain_kernel(DevState st, int m
             p.iters_left = p.n_iters;
             p.iters_done = 0;
             p.trials_total = 0;
+            p.evals_total = 0;
         }
     }
     for (int i = tid; i < N; i += nt) {
@@ -1379,6 +1380,10 @@ __global__ void __launch_bounds__(kIterThreads) select_kernel(DevState st, int /
         p.E_prior = epri;
         p.trials = pick >= 0 ? pick + 1 : p.max_bisect;
         p.trials_total += p.trials;
+        // step sizes evaluated: every window up to the one holding the pick
+        int evals = p.max_bisect;
+        if (pick >= 0) evals = pick < p.w1 ? p.w1 : min(p.max_bisect, p.w1 + ((pick - p.w1) / W + 1) * W);
+        p.evals_total += evals;
         p.kl = kl;
         if (pick >= 0) {
             p.logdet = ld;

@@ -34,6 +34,7 @@ struct PlanDev {
     int32_t gz, n_spheres, coll_states, status;
     int32_t trials, m, n_iters, trials_total;
     int32_t w1;   // width of this iteration's first window of step sizes
+    int32_t evals_total;  // step sizes evaluated since the (re)start, speculative ones included
     int32_t ltv;  // 0: every interval has the same dynamics (A, a, B)
     int32_t phase;  // 0 = iteration pending, 1 = no iteration (budget spent)
     int32_t coff;   // start of the plan's chain-order range (capacity Sc)
