@@ -48,6 +48,9 @@ def parse():
                     help="run the serving mix (Poisson arrivals of configs 0-3) instead of the batch solve")
     ap.add_argument("--qps", type=float, default=20.0)
     ap.add_argument("--requests", type=int, default=60)
+    ap.add_argument("--sweep-plans", type=int, nargs="*", default=None, help="plan counts of --expect-sweep")
+    ap.add_argument("--expect-sweep", action="store_true",
+                    help="time the expectation kernel alone over a batch sweep (32 plans, growing N)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a 512 MiB copy kernel once (known traffic, to scale memory counters)")
     return ap.parse_args()
@@ -72,6 +75,51 @@ def serve(args, pg):
         out[name] = m
     out["value"] = out["mixed"]["plans_per_s"]
     out["dtype"] = "fp32 quadrature + fp64"
+    print(json.dumps(out), flush=True)
+
+
+def expect_sweep(args, pg):
+    """Expectation kernel alone (config 1 shape: point robot, 500x500 maps,
+    p = 5, N = 750) over a batch sweep of the number of plans (the 32 seeded
+    maps repeated), mixed and FP64.  (Longer chains at dt = 0.1 make the
+    prior numerically singular, so the batch grows in plans.)
+    Achieved HBM rate = 88 B per factor (mean 2 + covariance 3 doubles in,
+    E + g 2 + H 3 doubles out) / mean launch time; the SDF gathers (4 cells x
+    4 B per node, 25 nodes) and FP32 node flops (~1.1 kFLOP) are reported
+    beside it."""
+    import torch
+    import workloads
+    rows = []
+    base = [workloads.config1_problem(seed=k) for k in range(32)]
+    N = 750
+    for n_plans in ((32, 128, 512, 2048, 8192) if not args.sweep_plans else tuple(args.sweep_plans)):
+        probs = []
+        for k in range(n_plans):
+            q = dict(base[k % 32])
+            q["n_iters"] = 1
+            if args.lanes:
+                q["lanes_per_factor"] = args.lanes
+            probs.append(q)
+        for name, prec in (("mixed", pg.MIXED), ("fp64", pg.FP64)):
+            ctx = pg.pgvimp_create(probs, precision=prec, use_graph=False, trial_width=1)
+            pg.pgvimp_expect_all(ctx, 3)
+            pg.pgvimp_profile(ctx, True)
+            pg.pgvimp_kernel_times(ctx, reset=True)
+            pg.pgvimp_expect_all(ctx, 20)
+            kt = pg.pgvimp_kernel_times(ctx, reset=True)
+            pg.pgvimp_destroy(ctx)
+            torch.cuda.synchronize()
+            ms = kt["expect"][0]
+            f = n_plans * N
+            rows.append({"factors": f, "precision": name, "lanes": args.lanes or "tuned", "ms": ms,
+                         "factors_per_s": f / (ms * 1e-3),
+                         "hbm_GBs": 88.0 * f / (ms * 1e-3) / 1e9, "hbm_frac": 88.0 * f / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                         "gather_GBs": 400.0 * f / (ms * 1e-3) / 1e9,
+                         "fp32_tflops": 1100.0 * f / (ms * 1e-3) / 1e12})
+            print(json.dumps(rows[-1]), flush=True)
+    out = {"metric": "expectation kernel alone, batch sweep", "unit": "factor-expectations/s", "n_gpus": 1,
+           "data": "synthetic", "config": {"workload": "point robot, 500x500 maps, GH p=5, N=750, plans swept"},
+           "rows": rows}
     print(json.dumps(out), flush=True)
 
 
@@ -211,6 +259,9 @@ def main():
         del src, dst
     if args.serve:
         serve(args, pg)
+        return
+    if args.expect_sweep:
+        expect_sweep(args, pg)
         return
 
     probs = make_batch(args.plans, args.N, args.iters)

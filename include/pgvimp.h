@@ -222,6 +222,16 @@ int pgvimp_marginals(pgvimp_ctx *ctx, int32_t plan, double *cov_diag, double *co
  * expected prior factor costs 1/2 E[r^T W r] ordered (start, transitions
  * 0..N-2, goal).  Any output pointer may be NULL.
  */
+/*
+ * Evaluate the collision-factor expectations (Sec. 4.1 eq. gradients_psid,
+ * Sec. 4.3) of every live plan at its current mean and marginals, reps >= 1
+ * times, leaving them on the device (no readback; the results are the ones
+ * the next iteration would use).  With pgvimp_profile enabled each launch is
+ * timed (kind PGVIMP_K_EXPECT of pgvimp_kernel_times).  Meant for measuring
+ * the expectation stage alone.  Errors: EINVAL (bad reps), EDEVICE.
+ */
+int pgvimp_expect_all(pgvimp_ctx *ctx, int32_t reps);
+
 int pgvimp_factor_expectations(pgvimp_ctx *ctx, int32_t plan, double *E_coll, double *grad,
                                double *hess, double *E_prior);
 

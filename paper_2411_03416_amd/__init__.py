@@ -21,7 +21,7 @@ __all__ = [
     "pgvimp_marginals", "pgvimp_factor_expectations", "pgvimp_prox_step", "pgvimp_solve", "pgvimp_slr_linearize",
     "pgvimp_get_state", "pgvimp_set_state", "pgvimp_set_budget", "pgvimp_kernel_times", "pgvimp_profile",
     "pgvimp_launch_shape", "pgvimp_arena_bytes", "problem_struct", "library_path", "ipgvimp_begin",
-    "ipgvimp_next_round",
+    "ipgvimp_next_round", "pgvimp_expect_all",
 ]
 
 _KIND = {"none": COLL_NONE, "point2d": COLL_POINT2D, "point3d": COLL_POINT3D, "arm3d": COLL_ARM3D}
@@ -250,6 +250,12 @@ def pgvimp_marginals(ctx, plan):
     _check(_abi.load().pgvimp_marginals(ctx.handle, plan, S.ctypes.data, So.ctypes.data if So.size else None,
                                         C.byref(ld)), ctx.handle)
     return S, So, ld.value
+
+
+def pgvimp_expect_all(ctx, reps=1):
+    """Collision expectations of every live plan at its current state, reps
+    times, left on the device (see pgvimp_expect_all in include/pgvimp.h)."""
+    _check(_abi.load().pgvimp_expect_all(ctx.handle, int(reps)), ctx.handle)
 
 
 def pgvimp_factor_expectations(ctx, plan):

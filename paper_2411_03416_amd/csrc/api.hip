@@ -65,6 +65,7 @@ struct pgvimp_ctx {
     int64_t g_hw = -1;
     bool g_restart = false;
     int g_rounds = -1;
+    int g_maxN = 0;
     std::vector<ClassKey> g_classes;
     bool g_profiled = false;
     // profiling
@@ -366,7 +367,8 @@ static int64_t carve(pgvimp_ctx* c, const pgvimp_engine_cfg* cfg, DevState& st, 
     take(&st.Hcol, S * dmax * dmax * 8);
     take(&st.Epri, (S + P) * 8);
     take(&st.ws, 2 * W * Sc * ws_stride * 8);
-    take(&st.seg, P * W * 2 * kMaxSeg * (int64_t)seg_stride * 8);
+    // reduced-chain node scratch: in LDS for n <= 4, in the arena otherwise
+    take(&st.seg, n > 4 ? P * W * 2 * kMaxSeg * (int64_t)seg_stride * 8 : 0);
     const int64_t tws_stride = n > 4 ? (int64_t)kTwsBlocks * n * n + (int64_t)kTwsVecs * n : 0;
     take(&st.tws, P * W * kTrialThreads * tws_stride * 8);
     take(&st.flags, 16 * 4);
@@ -738,7 +740,7 @@ int pgvimp_factor_expectations(pgvimp_ctx* c, int32_t plan, double* E_coll, doub
     const PlanHost& ph = c->plans[plan];
     const int N = ph.N, n = c->n;
     if (ph.coll_kind != PGVIMP_COLL_NONE)
-        HCK(c, launch_expect(c->st, ph.coll_kind, ph.d, ph.p, c->cfg.precision, ph.lanes, ph.off, ph.off + N, 0,
+        HCK(c, launch_expect(c->st, ph.coll_kind, ph.d, ph.p, c->cfg.precision, ph.lanes, plan, plan + 1, N, 0,
                              c->stream));
     HCK(c, launch_prior_costs(c->st, plan, N, c->stream));
     int rc;
@@ -768,7 +770,6 @@ static int plan_high_water(pgvimp_ctx* c) {
     return hw;
 }
 
-// Enqueue n_iters iterations; with timing, bracket each launch by events.
 static int max_live_N(pgvimp_ctx* c) {
     int m = 0;
     for (auto& ph : c->plans)
@@ -787,8 +788,11 @@ static int trial_rounds(pgvimp_ctx* c) {
     return c->st.lookahead > 0 ? 1 + (mb - 1 + W - 1) / W : (mb + W - 1) / W;
 }
 
+// Enqueue n_iters iterations; with timing, bracket each launch by events.
+// phw: plan slots covered; maxN: bound on the live plans' lengths that
+// sizes the grids (kernels stride over longer plans).
 static int enqueue_iters(pgvimp_ctx* c, int n_iters, const std::vector<ClassKey>& cls, int64_t shw, int phw,
-                         bool timed, bool restart) {
+                         int maxN, bool timed, bool restart) {
     const int rounds = trial_rounds(c);
     c->ev_used = 0;
     // record an event pair around each launch when timing (kind = PGVIMP_K_*)
@@ -814,7 +818,6 @@ static int enqueue_iters(pgvimp_ctx* c, int n_iters, const std::vector<ClassKey>
     if (restart) {
         // every live plan: prior from its stored dynamics, mu_0 = prior mean,
         // Lambda_0 = K^-1, marginals, budget reset (Alg. 1 set-up)
-        const int maxN = max_live_N(c);
         if ((rc = begin(PGVIMP_K_RESTART))) return rc;
         HCK(c, launch_prior_build(c->st, 0, phw, maxN, c->stream));
         HCK(c, launch_prior_assemble(c->st, 0, phw, maxN, c->stream));
@@ -824,7 +827,7 @@ static int enqueue_iters(pgvimp_ctx* c, int n_iters, const std::vector<ClassKey>
     for (int it = 0; it < n_iters; ++it) {
         for (auto& k : cls) {
             if ((rc = begin(PGVIMP_K_EXPECT))) return rc;
-            HCK(c, launch_expect(c->st, k.kind, k.d, k.p, c->cfg.precision, k.lanes, 0, shw, 1, c->stream));
+            HCK(c, launch_expect(c->st, k.kind, k.d, k.p, c->cfg.precision, k.lanes, 0, phw, maxN, 1, c->stream));
             if ((rc = end())) return rc;
         }
         if ((rc = begin(PGVIMP_K_PREP))) return rc;
@@ -855,6 +858,36 @@ static int collect_times(pgvimp_ctx* c) {
 
 static int run_iters(pgvimp_ctx* c, int32_t n_iters, pgvimp_stats* per_plan, bool restart);
 
+int pgvimp_expect_all(pgvimp_ctx* c, int32_t reps) {
+    if (!c || reps < 1) return PGVIMP_EINVAL;
+    HCK(c, hipSetDevice(c->cfg.device));
+    const std::vector<ClassKey> cls = live_classes(c);
+    const int64_t shw = c->states.high_water();
+    c->ev_used = 0;
+    for (int r = 0; r < reps; ++r)
+        for (auto& k : cls) {
+            if (c->profile) {
+                while (c->ev.size() < c->ev_used + 2) {
+                    hipEvent_t e;
+                    HCK(c, hipEventCreate(&e));
+                    c->ev.push_back(e);
+                    c->ev_kind.push_back(0);
+                }
+                c->ev_kind[c->ev_used] = PGVIMP_K_EXPECT;
+                HCK(c, hipEventRecord(c->ev[c->ev_used], c->stream));
+            }
+            HCK(c, launch_expect(c->st, k.kind, k.d, k.p, c->cfg.precision, k.lanes, 0, (int)c->plans.size(),
+                                 max_live_N(c), 1, c->stream));
+            if (c->profile) {
+                HCK(c, hipEventRecord(c->ev[c->ev_used + 1], c->stream));
+                c->ev_used += 2;
+            }
+        }
+    HCK(c, hipStreamSynchronize(c->stream));
+    if (c->profile) return collect_times(c);
+    return PGVIMP_OK;
+}
+
 int pgvimp_prox_step(pgvimp_ctx* c, int32_t n_iters, pgvimp_stats* per_plan) {
     return run_iters(c, n_iters, per_plan, false);
 }
@@ -875,11 +908,16 @@ static int run_iters(pgvimp_ctx* c, int32_t n_iters, pgvimp_stats* per_plan, boo
         // Timed runs launch eagerly: events recorded during graph capture
         // cannot be queried for elapsed time.
         if (c->cfg.use_graph && !timed) {
+            // grid-size bound, rounded up so that a captured graph serves
+            // plans of growing length without re-capture
+            int gN = 64;
+            while (gN < max_live_N(c)) gN *= 2;
             if (!c->gexec || c->g_iters != n_iters || c->g_hw != shw || !(c->g_classes == cls) ||
-                c->g_profiled != timed || c->g_restart != restart || c->g_rounds != trial_rounds(c)) {
+                c->g_profiled != timed || c->g_restart != restart || c->g_rounds != trial_rounds(c) ||
+                c->g_maxN < max_live_N(c)) {
                 drop_graph(c);
                 HCK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-                rc = enqueue_iters(c, n_iters, cls, shw, (int)c->plans.size(), timed, restart);
+                rc = enqueue_iters(c, n_iters, cls, shw, (int)c->plans.size(), gN, timed, restart);
                 hipGraph_t g = nullptr;
                 hipError_t e2 = hipStreamEndCapture(c->stream, &g);
                 if (rc) {
@@ -893,12 +931,13 @@ static int run_iters(pgvimp_ctx* c, int32_t n_iters, pgvimp_stats* per_plan, boo
                 c->g_hw = shw;
                 c->g_restart = restart;
                 c->g_rounds = trial_rounds(c);
+                c->g_maxN = gN;
                 c->g_classes = cls;
                 c->g_profiled = timed;
             }
             HCK(c, hipGraphLaunch(c->gexec, c->stream));
         } else {
-            rc = enqueue_iters(c, n_iters, cls, shw, phw, timed, restart);
+            rc = enqueue_iters(c, n_iters, cls, shw, phw, max_live_N(c), timed, restart);
             if (rc) return rc;
         }
     }

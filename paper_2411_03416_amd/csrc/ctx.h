@@ -172,8 +172,9 @@ hipError_t launch_chain(const DevState& st, int mode, int plan_lo, int plan_hi, 
 // parts of one proximal iteration for plans [0, phw): 0 = prep, 1 = trial
 // window `round`, 2 = select for window `round`
 hipError_t launch_iteration(const DevState& st, int phw, int part, int round, hipStream_t s);
-hipError_t launch_expect(const DevState& st, int coll_kind, int d, int p, int precision, int lanes,
-                         int64_t s_lo, int64_t s_hi, int respect_budget, hipStream_t s);
+// collision expectations of plans [plan_lo, plan_hi) of up to maxN states each
+hipError_t launch_expect(const DevState& st, int coll_kind, int d, int p, int precision, int lanes, int plan_lo,
+                         int plan_hi, int maxN, int respect_budget, hipStream_t s);
 hipError_t launch_prior_costs(const DevState& st, int plan, int N, hipStream_t s);
 hipError_t launch_gather(const DevState& st, int what, int plan, int N, double* out, hipStream_t s);
 hipError_t launch_scatter(const DevState& st, int what, int plan, int N, const double* in, hipStream_t s);

@@ -22,9 +22,11 @@
 // is centred by psi(mu) before the FP32 sums (the rule integrates constants
 // and the first two moments exactly, so only E[psi] needs it added back).
 //
-// Blocks are remapped so that each of the 8 XCDs (one L2 each) receives a
-// contiguous range of states: neighbouring states of one plan share SDF
-// cache lines, and one XCD's L2 then holds only a few plans' maps.
+// Each block serves one plan, and plan q always runs on XCD q mod 8 (one L2
+// per XCD): neighbouring states of a plan share SDF cache lines, and an
+// XCD's L2 holds only its own plans' maps.
+#include <algorithm>
+
 #include "ctx.h"
 
 namespace pg {
@@ -249,24 +251,14 @@ __device__ __forceinline__ bool chol_d(const double* A, double* L) {
     return ok;
 }
 
+// One factor: state s (index i within its plan), evaluated by the G lanes
+// that share it.
 template <typename R, int D, int P, int G, int KIND>
-__global__ void __launch_bounds__(kExpectThreads) expect_kernel(DevState st, int64_t s_lo, int64_t s_hi,
-                                                                int respect_budget, int blocks_per_xcd) {
+__device__ __forceinline__ void expect_factor(const DevState& st, const PlanDev& p, const Cost<R, D, KIND>& cost,
+                                              int64_t s, int lane) {
     constexpr int NODES = ipow(P, D);
-    constexpr int FPB = kExpectThreads / G;  // factors per block
     constexpr int NS2 = D * (D + 1) / 2;
-    const int b = blockIdx.x;
-    const int tile = (b % kNumXcd) * blocks_per_xcd + b / kNumXcd;
-    const int lane = threadIdx.x % G;
-    const int64_t s = s_lo + (int64_t)tile * FPB + threadIdx.x / G;
-    if (s >= s_hi) return;
-    const int pid = st.state_plan[s];
-    if (pid < 0) return;
-    const PlanDev& p = st.plans[pid];
-    if (!p.active || p.coll_kind != KIND || p.gh_points != P) return;
-    if (respect_budget && p.iters_left <= 0) return;
-    const int i = (int)(s - p.off);
-    if (p.coll_states == 1 && (i == 0 || i == p.N - 1)) return;
+    constexpr int STEPS = (NODES + G - 1) / G;  // nodes per lane, rounded up
     const int64_t S = st.S;
     const int n = st.n;
 
@@ -280,8 +272,6 @@ __global__ void __launch_bounds__(kExpectThreads) expect_kernel(DevState st, int
         for (int c = 0; c < D; ++c) Sg[a * D + c] = st.SD[(int64_t)(p.coll_index[a] * n + p.coll_index[c]) * S + s];
     const bool ok = chol_d<D>(Sg, L);
 
-    Cost<R, D, KIND> cost;
-    cost.init(p);
     R muR[D], LR[D * D];
 #pragma unroll
     for (int a = 0; a < D; ++a) muR[a] = (R)mu[a];
@@ -296,16 +286,20 @@ __global__ void __launch_bounds__(kExpectThreads) expect_kernel(DevState st, int
     for (int a = 0; a < D; ++a) s1[a] = R(0);
 #pragma unroll
     for (int a = 0; a < NS2; ++a) S2[a] = R(0);
-    for (int j = lane; j < NODES; j += G) {
+    // a fixed trip count lets the compiler overlap several nodes' SDF gathers
+#pragma unroll 4
+    for (int k = 0; k < STEPS; ++k) {
+        const int j = lane + k * G;
+        if (NODES % G != 0 && j >= NODES) break;
         R xi[D], x[D];
         R W = R(1);
         int r = j;
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-            const int k = r % P;
+            const int q = r % P;
             r /= P;
-            xi[a] = xi1[k];
-            W *= w1[k];
+            xi[a] = xi1[q];
+            W *= w1[q];
         }
 #pragma unroll
         for (int a = 0; a < D; ++a) {
@@ -401,51 +395,90 @@ __global__ void __launch_bounds__(kExpectThreads) expect_kernel(DevState st, int
         }
 }
 
+// Grid: per XCD, `slots` plan slots of `tiles` blocks each.  Block b runs on
+// XCD b mod 8 and serves plan plan_lo + 8*slot + (b mod 8), so the plan and
+// its fields are wave-uniform (scalar loads) and each XCD's L2 caches the
+// maps of its own plans only.  A block strides over its plan's states in
+// steps of `tiles` tiles, so any plan length is covered whatever the grid.
 template <typename R, int D, int P, int G, int KIND>
-static hipError_t launch_one(const DevState& st, int64_t lo, int64_t hi, int respect, hipStream_t s) {
+__global__ void __launch_bounds__(kExpectThreads) expect_kernel(DevState st, int plan_lo, int plan_hi, int tiles,
+                                                                int respect_budget) {
+    constexpr int FPB = kExpectThreads / G;  // factors per block
+    const int b = blockIdx.x;
+    const int k = b / kNumXcd;
+    const int pid = plan_lo + (k / tiles) * kNumXcd + b % kNumXcd;
+    if (pid >= plan_hi) return;
+    const PlanDev& p = st.plans[pid];
+    if (!p.active || p.coll_kind != KIND || p.gh_points != P) return;
+    if (respect_budget && p.iters_left <= 0) return;
+    const int lane = threadIdx.x % G;
+    const int N = p.N;
+    const int lo = p.coll_states == 1 ? 1 : 0;
+    const int hi = p.coll_states == 1 ? N - 1 : N;
+    Cost<R, D, KIND> cost;
+    cost.init(p);
+    for (int i0 = (k % tiles) * FPB; i0 < N; i0 += tiles * FPB) {
+        const int i = i0 + (int)threadIdx.x / G;
+        if (i < lo || i >= hi) continue;  // all G lanes of a factor agree
+        expect_factor<R, D, P, G, KIND>(st, p, cost, p.off + i, lane);
+    }
+}
+
+template <typename R, int D, int P, int G, int KIND>
+static hipError_t launch_one(const DevState& st, int plo, int phi, int maxN, int respect, hipStream_t s) {
     constexpr int FPB = kExpectThreads / G;
-    const int64_t tiles = (hi - lo + FPB - 1) / FPB;
-    const int64_t per_xcd = (tiles + kNumXcd - 1) / kNumXcd;
-    const int64_t blocks = per_xcd * kNumXcd;
-    if (tiles <= 0) return hipSuccess;
+    const int tiles = std::max(1, (maxN + FPB - 1) / FPB);
+    const int64_t slots = (phi - plo + kNumXcd - 1) / kNumXcd;
+    const int64_t blocks = slots * tiles * kNumXcd;
+    if (blocks <= 0) return hipSuccess;
+    if (blocks > INT32_MAX) return hipErrorInvalidValue;
     hipLaunchKernelGGL((expect_kernel<R, D, P, G, KIND>), dim3((unsigned)blocks), dim3(kExpectThreads), 0, s, st,
-                       lo, hi, respect, (int)per_xcd);
+                       plo, phi, tiles, respect);
     return hipGetLastError();
 }
 
-// Instantiated shapes: (kind, d, p) x lanes per factor.
+// Instantiated shapes: (kind, d, p) x lanes per factor (1, 2 and 4 lanes
+// for the point robots only).
+#define PG_LANES_SMALL(R, D, P, KIND)                                            \
+    switch (lanes) {                                                             \
+        case 1: return launch_one<R, D, P, 1, KIND>(st, plo, phi, maxN, respect, s);     \
+        case 2: return launch_one<R, D, P, 2, KIND>(st, plo, phi, maxN, respect, s);     \
+        case 4: return launch_one<R, D, P, 4, KIND>(st, plo, phi, maxN, respect, s);     \
+        default: break;                                                          \
+    }                                                                            \
+    PG_LANES(R, D, P, KIND)
 #define PG_LANES(R, D, P, KIND)                                                  \
     switch (lanes) {                                                             \
-        case 8: return launch_one<R, D, P, 8, KIND>(st, lo, hi, respect, s);     \
-        case 16: return launch_one<R, D, P, 16, KIND>(st, lo, hi, respect, s);   \
-        case 32: return launch_one<R, D, P, 32, KIND>(st, lo, hi, respect, s);   \
-        case 64: return launch_one<R, D, P, 64, KIND>(st, lo, hi, respect, s);   \
+        case 8: return launch_one<R, D, P, 8, KIND>(st, plo, phi, maxN, respect, s);     \
+        case 16: return launch_one<R, D, P, 16, KIND>(st, plo, phi, maxN, respect, s);   \
+        case 32: return launch_one<R, D, P, 32, KIND>(st, plo, phi, maxN, respect, s);   \
+        case 64: return launch_one<R, D, P, 64, KIND>(st, plo, phi, maxN, respect, s);   \
         default: return hipErrorInvalidValue;                                    \
     }
 
 template <typename R>
-static hipError_t dispatch(const DevState& st, int kind, int d, int p, int lanes, int64_t lo, int64_t hi,
+static hipError_t dispatch(const DevState& st, int kind, int d, int p, int lanes, int plo, int phi, int maxN,
                            int respect, hipStream_t s) {
     if (kind == PGVIMP_COLL_POINT2D && d == 2) {
         switch (p) {
-            case 1: PG_LANES(R, 2, 1, PGVIMP_COLL_POINT2D);
-            case 2: PG_LANES(R, 2, 2, PGVIMP_COLL_POINT2D);
-            case 3: PG_LANES(R, 2, 3, PGVIMP_COLL_POINT2D);
-            case 4: PG_LANES(R, 2, 4, PGVIMP_COLL_POINT2D);
-            case 5: PG_LANES(R, 2, 5, PGVIMP_COLL_POINT2D);
-            case 6: PG_LANES(R, 2, 6, PGVIMP_COLL_POINT2D);
-            case 7: PG_LANES(R, 2, 7, PGVIMP_COLL_POINT2D);
-            case 8: PG_LANES(R, 2, 8, PGVIMP_COLL_POINT2D);
-            case 10: PG_LANES(R, 2, 10, PGVIMP_COLL_POINT2D);
+            case 1: PG_LANES_SMALL(R, 2, 1, PGVIMP_COLL_POINT2D);
+            case 2: PG_LANES_SMALL(R, 2, 2, PGVIMP_COLL_POINT2D);
+            case 3: PG_LANES_SMALL(R, 2, 3, PGVIMP_COLL_POINT2D);
+            case 4: PG_LANES_SMALL(R, 2, 4, PGVIMP_COLL_POINT2D);
+            case 5: PG_LANES_SMALL(R, 2, 5, PGVIMP_COLL_POINT2D);
+            case 6: PG_LANES_SMALL(R, 2, 6, PGVIMP_COLL_POINT2D);
+            case 7: PG_LANES_SMALL(R, 2, 7, PGVIMP_COLL_POINT2D);
+            case 8: PG_LANES_SMALL(R, 2, 8, PGVIMP_COLL_POINT2D);
+            case 10: PG_LANES_SMALL(R, 2, 10, PGVIMP_COLL_POINT2D);
             default: return hipErrorInvalidValue;
         }
     }
     if (kind == PGVIMP_COLL_POINT3D && d == 3) {
         switch (p) {
-            case 2: PG_LANES(R, 3, 2, PGVIMP_COLL_POINT3D);
-            case 3: PG_LANES(R, 3, 3, PGVIMP_COLL_POINT3D);
-            case 4: PG_LANES(R, 3, 4, PGVIMP_COLL_POINT3D);
-            case 5: PG_LANES(R, 3, 5, PGVIMP_COLL_POINT3D);
+            case 2: PG_LANES_SMALL(R, 3, 2, PGVIMP_COLL_POINT3D);
+            case 3: PG_LANES_SMALL(R, 3, 3, PGVIMP_COLL_POINT3D);
+            case 4: PG_LANES_SMALL(R, 3, 4, PGVIMP_COLL_POINT3D);
+            case 5: PG_LANES_SMALL(R, 3, 5, PGVIMP_COLL_POINT3D);
             default: return hipErrorInvalidValue;
         }
     }
@@ -459,9 +492,12 @@ static hipError_t dispatch(const DevState& st, int kind, int d, int p, int lanes
     return hipErrorInvalidValue;
 }
 #undef PG_LANES
+#undef PG_LANES_SMALL
 
 bool expect_supported(int kind, int d, int p, int lanes) {
-    if (lanes != 8 && lanes != 16 && lanes != 32 && lanes != 64) return false;
+    const bool small = lanes == 1 || lanes == 2 || lanes == 4;
+    if (!small && lanes != 8 && lanes != 16 && lanes != 32 && lanes != 64) return false;
+    if (small && kind == PGVIMP_COLL_ARM3D) return false;
     if (kind == PGVIMP_COLL_POINT2D) return d == 2 && p >= 1 && p <= 10 && p != 9;
     if (kind == PGVIMP_COLL_POINT3D) return d == 3 && p >= 2 && p <= 5;
     if (kind == PGVIMP_COLL_ARM3D) return d == PGVIMP_ARM_DOF && (p == 2 || p == 3);
@@ -480,11 +516,11 @@ int default_lanes(int kind, int d, int p) {
     return 64;
 }
 
-hipError_t launch_expect(const DevState& st, int kind, int d, int p, int precision, int lanes, int64_t lo,
-                         int64_t hi, int respect, hipStream_t s) {
+hipError_t launch_expect(const DevState& st, int kind, int d, int p, int precision, int lanes, int plo, int phi,
+                         int maxN, int respect, hipStream_t s) {
     if (kind == PGVIMP_COLL_NONE) return hipSuccess;
-    if (precision == PGVIMP_MIXED) return dispatch<float>(st, kind, d, p, lanes, lo, hi, respect, s);
-    return dispatch<double>(st, kind, d, p, lanes, lo, hi, respect, s);
+    if (precision == PGVIMP_MIXED) return dispatch<float>(st, kind, d, p, lanes, plo, phi, maxN, respect, s);
+    return dispatch<double>(st, kind, d, p, lanes, plo, phi, maxN, respect, s);
 }
 
 }  // namespace pg
