@@ -42,6 +42,7 @@ def parse():
     ap.add_argument("--segments", type=int, default=0)
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--trial-width", type=int, default=0, help="trial step sizes per window (0 = library default)")
+    ap.add_argument("--trial-slots", type=int, default=0, help="widest trial window (0 = library default)")
     ap.add_argument("--trial-lookahead", type=int, default=0,
                     help="first window = previous trial count + this (0 = full first window)")
     ap.add_argument("--serve", action="store_true",
@@ -134,7 +135,7 @@ def make_batch(n_plans, N, iters):
 
 
 def timed_solve(pg, probs, precision, steps, warmup, iters, segments=0, lanes=0, profile=True, trial_width=0,
-                trial_lookahead=0):
+                trial_lookahead=0, trial_slots=0):
     """Create one context for the batch, warm up, then time `steps` solves,
     each one HIP graph replay.  With profile, the same number of solves is
     then run with HIP events around every kernel on the context's stream
@@ -150,7 +151,7 @@ def timed_solve(pg, probs, precision, steps, warmup, iters, segments=0, lanes=0,
             if lanes:
                 p["lanes_per_factor"] = lanes
     ctx = pg.pgvimp_create(probs, precision=precision, use_graph=True, segments=segments, lanes=lanes,
-                           trial_width=trial_width, trial_lookahead=trial_lookahead)
+                           trial_width=trial_width, trial_lookahead=trial_lookahead, trial_slots=trial_slots)
     for _ in range(warmup):
         pg.pgvimp_solve(ctx, iters)
     torch.cuda.synchronize()
@@ -268,7 +269,8 @@ def main():
     B, N, K = args.plans, args.N, args.iters
     n = probs[0]["n"]
     mixed = timed_solve(pg, probs, pg.MIXED, args.steps, args.warmup, K, args.segments, args.lanes,
-                        trial_width=args.trial_width, trial_lookahead=args.trial_lookahead)
+                        trial_width=args.trial_width, trial_lookahead=args.trial_lookahead,
+                        trial_slots=args.trial_slots)
     ms = 1e3 * mixed["wall_s"] / args.steps
     factors_per_step = B * N * K
     value = factors_per_step / (ms / 1e3)
@@ -319,7 +321,8 @@ def main():
         out["eager_ms_per_step"] = kt["eager_ms_per_step"]
     if not args.no_fp64:
         f64 = timed_solve(pg, probs, pg.FP64, max(2, args.steps // 2), 1, K, args.segments, args.lanes,
-                          profile=False, trial_width=args.trial_width, trial_lookahead=args.trial_lookahead)
+                          profile=False, trial_width=args.trial_width, trial_lookahead=args.trial_lookahead,
+                          trial_slots=args.trial_slots)
         ms64 = 1e3 * f64["wall_s"] / max(2, args.steps // 2)
         out["fp64"] = {"value": factors_per_step / (ms64 / 1e3), "ms_per_step": ms64,
                        "plans_per_s": B / (ms64 / 1e3),

@@ -145,14 +145,18 @@ typedef struct pgvimp_problem {
  * to the plans present (re-captured when they change); use_graph = 2 sizes
  * the graph to the full capacity so plans can join and leave without a new
  * capture (serving).
- * trial_width (0 = 8, at most 64) is the number of step sizes of the
- * halving sequence evaluated concurrently per plan and iteration; it changes
- * speed and memory (the trial scratch scales with it), never results.
- * trial_lookahead > 0 shortens each plan's first window of an iteration to
- * min(trial_width, t + trial_lookahead) step sizes, t = the number of step
- * sizes its previous iteration tried (later windows are trial_width wide);
- * 0 = full first window.  Also a speed knob only: the accepted step is the
- * first passing one in halving order whatever the windows.
+ * Step sizes of the halving sequence (Alg. 1) are evaluated concurrently
+ * in windows: each window of a plan continues where its previous one ended,
+ * until one holds a passing step.  A window's width is the number of
+ * compute units divided by the number of plans still searching, clamped to
+ * [trial_width, trial_slots]: trial_width (0 = 8, at most 64) is the
+ * narrowest window, trial_slots (0 = 2 * trial_width, at least
+ * trial_width, at most 64) the widest, and the trial scratch scales with
+ * trial_slots.  trial_lookahead > 0 cuts each plan's first window of an
+ * iteration to t + trial_lookahead step sizes (at least 1), t = the number
+ * its previous iteration tried; 0 = no cut.  All three change speed and
+ * memory, never results: the accepted step is the first passing one in
+ * halving order whatever the windows.
  */
 typedef struct pgvimp_engine_cfg {
     int32_t device, n, precision, max_plans;
@@ -161,7 +165,7 @@ typedef struct pgvimp_engine_cfg {
     void *dev_arena;
     uint64_t arena_bytes;
     int32_t io_on_device, segments, lanes_per_factor, use_graph;
-    int32_t trial_width, trial_lookahead;
+    int32_t trial_width, trial_lookahead, trial_slots;
 } pgvimp_engine_cfg;
 
 /* Per-plan statistics of the last iteration run by pgvimp_prox_step. */

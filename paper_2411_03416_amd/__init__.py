@@ -176,7 +176,7 @@ def _heap_need(probs):
 
 def pgvimp_create(problems, n=None, precision=FP64, max_plans=None, max_states=None, heap_bytes=None,
                   device=0, use_torch=True, stream=None, segments=0, lanes=0, use_graph=True, mu_init=None,
-                  trial_width=0, trial_lookahead=0):
+                  trial_width=0, trial_lookahead=0, trial_slots=0):
     """Create a context holding `problems` (list of dicts); see pgvimp_create
     in include/pgvimp.h.  With use_torch the device arena is a torch uint8
     tensor and the work runs on a torch stream."""
@@ -194,6 +194,7 @@ def pgvimp_create(problems, n=None, precision=FP64, max_plans=None, max_states=N
     cfg.use_graph = int(use_graph) if not isinstance(use_graph, bool) else (1 if use_graph else 0)
     cfg.trial_width = trial_width
     cfg.trial_lookahead = trial_lookahead
+    cfg.trial_slots = trial_slots
     arena = None
     tstream = None
     if use_torch:

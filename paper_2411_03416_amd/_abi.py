@@ -55,6 +55,7 @@ class EngineCfg(C.Structure):
         ("stream", C.c_void_p), ("dev_arena", C.c_void_p), ("arena_bytes", C.c_uint64),
         ("io_on_device", C.c_int32), ("segments", C.c_int32), ("lanes_per_factor", C.c_int32),
         ("use_graph", C.c_int32), ("trial_width", C.c_int32), ("trial_lookahead", C.c_int32),
+        ("trial_slots", C.c_int32),
     ]
 
 

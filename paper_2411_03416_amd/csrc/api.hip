@@ -318,9 +318,16 @@ int64_t pgvimp_device_bytes(const pgvimp_ctx* ctx) { return ctx ? (int64_t)ctx->
 
 static int64_t layout_bytes(const pgvimp_engine_cfg* cfg);
 
-// Trial step sizes evaluated concurrently per plan (1..kMaxTrialWidth).
+// Narrowest window of trial step sizes per plan (1..kMaxTrialWidth).
 static int64_t trial_width(const pgvimp_engine_cfg* cfg) {
     return cfg->trial_width > 0 ? std::min<int64_t>(cfg->trial_width, kMaxTrialWidth) : kDefaultTrialWidth;
+}
+// Trial slots per plan = the widest window (trial_width..kMaxTrialWidth,
+// default twice trial_width).
+static int64_t trial_slots(const pgvimp_engine_cfg* cfg) {
+    const int64_t w = trial_width(cfg);
+    const int64_t s = cfg->trial_slots > 0 ? cfg->trial_slots : 2 * w;
+    return std::min<int64_t>(kMaxTrialWidth, std::max(w, s));
 }
 
 int64_t pgvimp_arena_bytes(const pgvimp_engine_cfg* cfg) {
@@ -336,7 +343,7 @@ static int64_t carve(pgvimp_ctx* c, const pgvimp_engine_cfg* cfg, DevState& st, 
     const int64_t S = cfg->max_states, P = cfg->max_plans;
     const int dmax = std::min(n, PGVIMP_MAX_COLL_DIM);
     const int ws_stride = 3 * n * n + n;
-    const int seg_stride = 6 * n * n + 3 * n;  // SegLayout<n>::STRIDE
+    const int seg_stride = std::max(5 * n * n, 4 * n * n + 3 * n);  // larger scratch layout per slot
     int64_t off = 0;
     auto take = [&](auto** ptr, int64_t bytes) {
         if (base) *ptr = (std::remove_reference_t<decltype(**ptr)>*)(base + off);
@@ -344,7 +351,7 @@ static int64_t carve(pgvimp_ctx* c, const pgvimp_engine_cfg* cfg, DevState& st, 
     };
     take(&st.plans, P * (int64_t)sizeof(PlanDev));
     take(&st.state_plan, S * 4);
-    const int64_t W = trial_width(cfg);
+    const int64_t W = trial_slots(cfg);
     // chain-order capacity: each plan's range is rounded up to whole rows of
     // its segments and to whole tiles of 32 positions, and starts on a tile
     // (fewer than kMaxSeg + 2 * 32 extra positions per plan)
@@ -361,6 +368,7 @@ static int64_t carve(pgvimp_ctx* c, const pgvimp_engine_cfg* cfg, DevState& st, 
     take(&st.TSU, W * Sc * n * n * 8);
     take(&st.Tmu, W * Sc * n * 8);
     take(&st.tres, P * kMaxBisect * 4 * 8);
+    take(&st.wlist, (P * kMaxTrialWidth + 1) * 4);
     take(&st.psum, P * kIterBlocks * 2 * 8);
     take(&st.Ecol, S * 8);
     take(&st.gcol, S * dmax * 8);
@@ -389,6 +397,7 @@ static int64_t carve(pgvimp_ctx* c, const pgvimp_engine_cfg* cfg, DevState& st, 
     st.seg_stride = seg_stride;
     st.tws_stride = tws_stride;
     st.W = (int32_t)W;
+    st.Wmin = (int32_t)trial_width(cfg);
     st.iter_blocks = (int32_t)std::min<int64_t>(kIterBlocks, W);
     st.lookahead = std::max(0, cfg->trial_lookahead);
     return off;
@@ -419,6 +428,9 @@ static int ctx_alloc(pgvimp_ctx* c) {
     }
     c->arena_bytes = total;
     carve(c, &c->cfg, st, c->arena);
+    int cus = 0;
+    HCK(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->cfg.device));
+    st.wbudget = std::max(1, cus);
     c->states.reset(S);
     c->cstates.reset(c->st.Sc);
     c->heapalloc.reset(c->heap_bytes);
@@ -445,7 +457,7 @@ int pgvimp_create(const pgvimp_problem* probs, int32_t n_probs, const pgvimp_eng
     if (!cfg) FAIL((pgvimp_ctx*)nullptr, PGVIMP_EINVAL, "null config");
     if (!chain_supported(cfg->n)) FAIL((pgvimp_ctx*)nullptr, PGVIMP_EINVAL, "state dim %d not supported", cfg->n);
     if (cfg->max_plans < 1 || cfg->max_states < 1 || cfg->heap_bytes < 0 || n_probs < 0 || n_probs > cfg->max_plans ||
-        cfg->use_graph < 0 || cfg->use_graph > 2 || cfg->trial_width < 0 || cfg->trial_lookahead < 0 ||
+        cfg->use_graph < 0 || cfg->use_graph > 2 || cfg->trial_width < 0 || cfg->trial_lookahead < 0 || cfg->trial_slots < 0 ||
         (n_probs > 0 && !probs) || (cfg->precision != PGVIMP_FP64 && cfg->precision != PGVIMP_MIXED) ||
         cfg->segments < 0 || cfg->segments > kMaxSeg)
         FAIL((pgvimp_ctx*)nullptr, PGVIMP_EINVAL, "invalid engine configuration");
@@ -777,14 +789,14 @@ static int max_live_N(pgvimp_ctx* c) {
     return m;
 }
 
-// Windows of trial step sizes needed by the live plans: a first window of
-// at least one step size (trial_width without lookahead), then windows of
-// trial_width.
+// Windows of trial step sizes that cover max_bisect for every live plan
+// when every window is as narrow as allowed: a first window of at least one
+// step size (trial_width without lookahead), then windows of trial_width.
 static int trial_rounds(pgvimp_ctx* c) {
     int mb = 1;
     for (auto& ph : c->plans)
         if (ph.active) mb = std::max(mb, ph.max_bisect);
-    const int W = c->st.W;
+    const int W = c->st.Wmin;
     return c->st.lookahead > 0 ? 1 + (mb - 1 + W - 1) / W : (mb + W - 1) / W;
 }
 
@@ -834,6 +846,7 @@ static int enqueue_iters(pgvimp_ctx* c, int n_iters, const std::vector<ClassKey>
         HCK(c, launch_iteration(c->st, phw, 0, 0, c->stream));
         if ((rc = end())) return rc;
         for (int r = 0; r < rounds; ++r) {
+            HCK(c, launch_window(c->st, phw, r, c->stream));
             if ((rc = begin(PGVIMP_K_TRIAL))) return rc;
             HCK(c, launch_iteration(c->st, phw, 1, r, c->stream));
             if ((rc = end())) return rc;

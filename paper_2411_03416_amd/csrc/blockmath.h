@@ -181,28 +181,39 @@ PG_UNROLL
     }
 }
 
+// 1/sqrt(x) for a positive normal x: the hardware estimate refined by two
+// Newton steps for f(y) = y^-2 - x, y <- y (3 - x y^2) / 2 (quadratic
+// convergence, a few ulp at the end).
+__device__ __forceinline__ double rsqrt_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    y = y * fma(-h, y * y, 1.5);
+    y = y * fma(-h, y * y, 1.5);
+    return y;
+}
+
 // Inverse of an SPD matrix through its Cholesky factor A = L L^T:
-// Ainv = L^-T L^-1.  If logdet is not null, adds log det A (the log of the
-// product of the pivots, one logarithm per block).  Returns false (and
-// leaves Ainv unspecified) if a pivot is not positive or not finite.
+// Ainv = L^-T L^-1.  Reads only the lower triangle of A.  If det is not
+// null, stores det A (the product of the pivots) there.  Returns false (and
+// leaves Ainv unspecified) if a pivot is not positive, not finite or below
+// the smallest normal number.  One reciprocal square root per pivot; the
+// diagonal of L is kept as its reciprocal, which is what both triangular
+// steps use.
 template <int n>
-__device__ __forceinline__ bool spd_inverse(const double* A, double* Ainv, double* logdet, TS ts) {
-    PG_MAT(L, ts);
-PG_UNROLL
-    for (int e = 0; e < n * n; ++e) L[e] = 0.0;
-    double det = 1.0;
+__device__ __forceinline__ bool spd_inverse(const double* A, double* Ainv, double* det, TS ts) {
+    PG_MAT(L, ts);  // strictly lower part of L; diagonal: 1 / L_jj
+    double dt = 1.0;
     bool ok = true;
 PG_UNROLL
     for (int j = 0; j < n; ++j) {
         double d = A[j * n + j];
 PG_UNROLL
         for (int k = 0; k < j; ++k) d = fma(-L[j * n + k], L[j * n + k], d);
-        ok = ok && (d > 0.0) && (d < INFINITY);
+        ok = ok && (d >= 2.2250738585072014e-308) && (d < INFINITY);
         d = ok ? d : 1.0;
-        const double ljj = sqrt(d);
-        const double inv = 1.0 / ljj;
-        det *= d;
-        L[j * n + j] = ljj;
+        const double inv = rsqrt_nr(d);
+        dt *= d;
+        L[j * n + j] = inv;
 PG_UNROLL
         for (int i = j + 1; i < n; ++i) {
             double s = A[i * n + j];
@@ -214,10 +225,8 @@ PG_UNROLL
     // W = L^-1 (lower triangular), by forward substitution column by column
     PG_MAT(W, ts);
 PG_UNROLL
-    for (int e = 0; e < n * n; ++e) W[e] = 0.0;
-PG_UNROLL
     for (int i = 0; i < n; ++i) {
-        const double inv = 1.0 / L[i * n + i];
+        const double inv = L[i * n + i];
         W[i * n + i] = inv;
 PG_UNROLL
         for (int j = 0; j < i; ++j) {
@@ -238,8 +247,84 @@ PG_UNROLL
             Ainv[i * n + j] = s;
             Ainv[j * n + i] = s;
         }
-    if (logdet) *logdet += log(det);
+    if (det) *det = dt;
     return ok;
+}
+
+// Running product of block determinants kept as mantissa * 2^exponent, so
+// a sweep takes one logarithm at its end instead of one per block.
+struct DetAcc {
+    double m = 1.0;
+    int e = 0;
+    __device__ __forceinline__ void mul(double d) {
+        int k;
+        m = frexp(m * d, &k);
+        e += k;
+    }
+    __device__ __forceinline__ double log_value() const { return log(m) + e * 0.6931471805599453; }
+};
+
+// Lower-triangle (j <= i) variants for symmetric results; the upper
+// triangle of C is not touched.
+// C -= A^T B
+template <int n>
+__device__ __forceinline__ void msub_tn_lo(const double* A, const double* B, double* C) {
+PG_UNROLL
+    for (int i = 0; i < n; ++i)
+PG_UNROLL
+        for (int j = 0; j <= i; ++j) {
+            double s = C[i * n + j];
+PG_UNROLL
+            for (int k = 0; k < n; ++k) s = fma(-A[k * n + i], B[k * n + j], s);
+            C[i * n + j] = s;
+        }
+}
+// C -= A B^T
+template <int n>
+__device__ __forceinline__ void msub_nt_lo(const double* A, const double* B, double* C) {
+PG_UNROLL
+    for (int i = 0; i < n; ++i)
+PG_UNROLL
+        for (int j = 0; j <= i; ++j) {
+            double s = C[i * n + j];
+PG_UNROLL
+            for (int k = 0; k < n; ++k) s = fma(-A[i * n + k], B[j * n + k], s);
+            C[i * n + j] = s;
+        }
+}
+// upper triangle of C from its lower triangle
+template <int n>
+__device__ __forceinline__ void sym_from_lo(double* C) {
+PG_UNROLL
+    for (int i = 0; i < n; ++i)
+PG_UNROLL
+        for (int j = 0; j < i; ++j) C[j * n + i] = C[i * n + j];
+}
+// C = -(A^T B)
+template <int n>
+__device__ __forceinline__ void mmul_tn_neg(const double* A, const double* B, double* C) {
+PG_UNROLL
+    for (int i = 0; i < n; ++i)
+PG_UNROLL
+        for (int j = 0; j < n; ++j) {
+            double s = 0.0;
+PG_UNROLL
+            for (int k = 0; k < n; ++k) s = fma(-A[k * n + i], B[k * n + j], s);
+            C[i * n + j] = s;
+        }
+}
+// C = -(A B)
+template <int n>
+__device__ __forceinline__ void mmul_neg(const double* A, const double* B, double* C) {
+PG_UNROLL
+    for (int i = 0; i < n; ++i)
+PG_UNROLL
+        for (int j = 0; j < n; ++j) {
+            double s = 0.0;
+PG_UNROLL
+            for (int k = 0; k < n; ++k) s = fma(-A[i * n + k], B[k * n + j], s);
+            C[i * n + j] = s;
+        }
 }
 
 }  // namespace pg

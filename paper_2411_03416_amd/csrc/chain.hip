@@ -35,6 +35,79 @@ hipError_t launch_iteration(const DevState& st, int phw, int part, int round, hi
     }
 }
 
+// Windows of the step-size halving rule (Alg. 1): every plan evaluates its
+// step sizes window by window, each window continuing where the previous
+// one ended, until a window holds a passing step.  For window `round`, a
+// plan still searching (every plan with an iteration to run, in window 0)
+// takes the next clamp(wbudget / searching, Wmin, W) step sizes, never past
+// max_bisect: the compute units are shared by the plans that still need
+// them, and a few stragglers get wide windows.  With a lookahead, window 0
+// is cut to the previous iteration's count plus the lookahead.  The window's
+// trials are listed plan by plan in wlist.  Widths change speed, never the
+// accepted step.  One block; plans are taken in chunks of 256, thread tid
+// owning plan chunk + tid.
+constexpr int kWindowThreads = 256;
+__global__ void __launch_bounds__(kWindowThreads) window_kernel(DevState st, int phw, int round) {
+    __shared__ int sh[kWindowThreads];
+    __shared__ int total;
+    const int tid = threadIdx.x;
+    if (tid == 0) total = 0;
+    __syncthreads();
+    int mine = 0;
+    for (int pid = tid; pid < phw; pid += kWindowThreads) {
+        PlanDev& p = st.plans[pid];
+        int s = 0;
+        if (p.active && p.phase == 0) {
+            if (round == 0) {
+                p.wnext = 0;
+                p.firstpass = kNoPass;
+            }
+            s = p.firstpass == kNoPass && p.wnext < p.max_bisect;
+        }
+        p.wwidth = s;  // flag until the width is known
+        mine += s;
+    }
+    atomicAdd(&total, mine);
+    __syncthreads();
+    const int width = max(st.Wmin, min(st.W, st.wbudget / max(total, 1)));
+    int base = 0;  // items of the plans before this chunk
+    for (int c0 = 0; c0 < phw; c0 += kWindowThreads) {
+        const int pid = c0 + tid;
+        int w = 0;
+        if (pid < phw) {
+            PlanDev& p = st.plans[pid];
+            if (p.wwidth) {
+                w = width;
+                if (round == 0 && st.lookahead > 0 && p.iters_done > 0) w = min(w, max(1, p.trials + st.lookahead));
+                w = min(w, p.max_bisect - p.wnext);
+                p.wstart = p.wnext;
+                p.wnext += w;
+            }
+            p.wwidth = w;
+        }
+        // exclusive scan of the widths over the chunk (in plan order)
+        __syncthreads();
+        sh[tid] = w;
+        __syncthreads();
+        for (int o = 1; o < kWindowThreads; o <<= 1) {
+            const int v = tid >= o ? sh[tid - o] : 0;
+            __syncthreads();
+            sh[tid] += v;
+            __syncthreads();
+        }
+        const int first = base + sh[tid] - w;
+        for (int t = 0; t < w; ++t) st.wlist[1 + first + t] = pid * 64 + t;
+        base += sh[kWindowThreads - 1];
+    }
+    if (tid == 0) st.wlist[0] = base;
+}
+
+hipError_t launch_window(const DevState& st, int phw, int round, hipStream_t s) {
+    if (phw <= 0) return hipSuccess;
+    hipLaunchKernelGGL(window_kernel, dim3(1), dim3(kWindowThreads), 0, s, st, phw, round);
+    return hipGetLastError();
+}
+
 hipError_t launch_prior_costs(const DevState& st, int plan, int N, hipStream_t s) {
     switch (st.n) {
         case 2: return launch_prior_costs_n<2>(st, plan, N, s);

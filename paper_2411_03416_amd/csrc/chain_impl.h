@@ -53,56 +53,79 @@ namespace pg {
 // separator j (node j) of the reduced chain; before the nodes are
 // assembled, the first fields hold segment j's contributions to its two
 // separators (they are read into registers before the node fields are
-// written).  For small blocks the scratch lives in LDS.
+// written).  The covariance half (selected inversion, RHS = false) and the
+// mean half (solve, RHS = true) keep only the fields they use.  For small
+// blocks the scratch lives in LDS.
+template <int n, bool RHS>
+struct SegLayout;
 template <int n>
-struct SegLayout {
-    static constexpr int NA = 0;              // current diagonal block; Sigma_jj after the backward pass
-    static constexpr int NC = n * n;          // coupling M(j, right neighbour at the current level)
-    static constexpr int NP = 2 * n * n;      // pivot inverse at elimination
-    static constexpr int NGL = 3 * n * n;     // pivot^-1 M(j, left neighbour)
-    static constexpr int NGR = 4 * n * n;     // pivot^-1 M(j, right neighbour)
-    static constexpr int NX = 5 * n * n;      // Cov(j, right neighbour at j's level); Cov(j, j+1) at the end
-    static constexpr int NR = 6 * n * n;      // current rhs of node j
-    static constexpr int NZ = 6 * n * n + n;  // pivot^-1 rhs at elimination
-    static constexpr int XS = 6 * n * n + 2 * n;  // solution at separator j
-    static constexpr int STRIDE = 6 * n * n + 3 * n;
+struct SegLayout<n, false> {
+    static constexpr int NA = 0;          // current diagonal block; Sigma_jj after the backward pass
+    static constexpr int NC = n * n;      // coupling M(j, right neighbour at the current level)
+    static constexpr int NP = 2 * n * n;  // pivot inverse at elimination
+    static constexpr int NGL = 3 * n * n; // pivot^-1 M(j, left neighbour)
+    static constexpr int NGR = 4 * n * n; // pivot^-1 M(j, right neighbour)
+    // Cov(j, right neighbour at j's level), Cov(j, j+1) at the end.  It
+    // shares the coupling's entries: the backward pass reads no coupling.
+    static constexpr int NX = NC;
+    static constexpr int STRIDE = 5 * n * n;
     // segment j's contributions before assembly (aliases)
-    static constexpr int DL = NA;    // Schur contribution to the left separator
-    static constexpr int DR = NC;    // ... to the right separator
-    static constexpr int CLR = NP;   // coupling block (left sep, right sep)
-    static constexpr int RL = NR;    // rhs contribution to the left separator
-    static constexpr int RR = NZ;    // ... to the right separator
+    static constexpr int DL = NA;   // Schur contribution to the left separator
+    static constexpr int DR = NC;   // ... to the right separator
+    static constexpr int CLR = NP;  // coupling block (left sep, right sep)
 };
+template <int n>
+struct SegLayout<n, true> {
+    static constexpr int NA = 0;
+    static constexpr int NC = n * n;
+    static constexpr int NGL = 2 * n * n;
+    static constexpr int NGR = 3 * n * n;
+    static constexpr int NR = 4 * n * n;          // current rhs of node j
+    static constexpr int NZ = 4 * n * n + n;      // pivot^-1 rhs at elimination
+    static constexpr int XS = 4 * n * n + 2 * n;  // solution at separator j
+    static constexpr int STRIDE = 4 * n * n + 3 * n;
+    static constexpr int DL = NA;
+    static constexpr int DR = NC;
+    static constexpr int CLR = NGL;
+    static constexpr int RL = NR;  // rhs contribution to the left separator
+    static constexpr int RR = NZ;  // ... to the right separator
+};
+constexpr unsigned kTrialLdsPad = 4096;
 // Node scratch in LDS (both halves of a workgroup) for small blocks.
 template <int n>
 struct NodeLds {
     static constexpr bool value = RegBlocks<n>::value;
-    static constexpr int size = value ? 2 * kMaxSeg * SegLayout<n>::STRIDE : 1;
+    static constexpr int size = value ? kMaxSeg * (SegLayout<n, false>::STRIDE + SegLayout<n, true>::STRIDE) : 1;
 };
 
 // Field f of slot j of the segment scratch.
 __device__ __forceinline__ double& sgv(double* sg, int j, int f) { return sg[(uint32_t)(f * kMaxSeg + j)]; }
 
-// Chain-order arrays are tiled in groups of kTile positions: entry e of
-// position q (E entries per position) is element ((q >> 5) * E + e) * 32 +
-// (q & 31).  A wave reading entry e of consecutive positions reads 256
-// contiguous bytes, and all entries of one position share one per-lane byte
-// offset (entry e adds the constant e * 256).  Views (plan range, trial
-// slot) start at a multiple of kTile positions.
+// Chain-order arrays are tiled in groups of kTile positions, with entries
+// paired: entry e of position q (E entries per position, E even) is element
+// ((q >> 5) * E + (e & ~1)) * 32 + (q & 31) * 2 + (e & 1).  Entries 2k and
+// 2k + 1 of a position are adjacent, so a lane moves them with one 16-byte
+// access, and a wave doing so for 32 consecutive positions touches 512
+// contiguous bytes.  All entries of one position share one per-lane byte
+// offset (entry e adds the constant (e >> 1) * 512 + (e & 1) * 8).  Views
+// (plan range, trial slot) start at a multiple of kTile positions.
 constexpr int kTile = 32;
 template <int E>
 __device__ __forceinline__ uint32_t toff(uint32_t pl) {
-    return ((pl >> 5) * (uint32_t)(E * kTile) + (pl & 31u)) * 8u;
+    static_assert(E % 2 == 0, "paired tiles need an even entry count");
+    return ((pl >> 5) * (uint32_t)(E * kTile) + (pl & 31u) * 2u) * 8u;
 }
 template <int E>
 __device__ __forceinline__ int64_t tidx(int64_t q, int e) {
-    return ((q >> 5) * E + e) * kTile + (q & 31);
+    static_assert(E % 2 == 0, "paired tiles need an even entry count");
+    return ((q >> 5) * E + (e & ~1)) * kTile + (q & 31) * 2 + (e & 1);
 }
+__device__ __forceinline__ constexpr uint32_t tent(int e) { return (uint32_t)((e >> 1) * (2 * kTile * 8) + (e & 1) * 8); }
 __device__ __forceinline__ double ldo(const double* base, uint32_t off, int e) {
-    return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + off + e * (kTile * 8));
+    return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + off + tent(e));
 }
 __device__ __forceinline__ void sto(double* base, uint32_t off, int e, double v) {
-    *reinterpret_cast<double*>(reinterpret_cast<char*>(base) + off + e * (kTile * 8)) = v;
+    *reinterpret_cast<double*>(reinterpret_cast<char*>(base) + off + tent(e)) = v;
 }
 
 // Per-state temporaries of one sweep (views over the same positions): the
@@ -185,6 +208,52 @@ __device__ __forceinline__ void comb(double a0, const double* M0, double a1, con
 PG_UNROLL
     for (int e = 0; e < CNT; ++e) M[e] = lin2(a0, M0[e], a1, M1[e]);
 }
+// Lower triangles (j <= i) of symmetric blocks: raw loads of both sources,
+// their combination, a block built directly, and stores / loads of a
+// symmetric block's lower triangle (the loads fill the upper one).
+template <int n>
+__device__ __forceinline__ void ld2_lo(const double* X0, const double* X1, uint32_t off, double* M0, double* M1) {
+PG_UNROLL
+    for (int i = 0; i < n; ++i)
+PG_UNROLL
+        for (int j = 0; j <= i; ++j) {
+            M0[i * n + j] = ldo(X0, off, i * n + j);
+            M1[i * n + j] = ldo(X1, off, i * n + j);
+        }
+}
+template <int n>
+__device__ __forceinline__ void comb_lo(double a0, const double* M0, double a1, const double* M1, double* M) {
+PG_UNROLL
+    for (int i = 0; i < n; ++i)
+PG_UNROLL
+        for (int j = 0; j <= i; ++j) M[i * n + j] = lin2(a0, M0[i * n + j], a1, M1[i * n + j]);
+}
+template <int n>
+__device__ __forceinline__ void src_D_lo(const BlockSrc& b, uint32_t off, double* M) {
+PG_UNROLL
+    for (int i = 0; i < n; ++i)
+PG_UNROLL
+        for (int j = 0; j <= i; ++j)
+            M[i * n + j] = lin2(b.a0, ldo(b.D0, off, i * n + j), b.a1, ldo(b.D1, off, i * n + j));
+}
+template <int n>
+__device__ __forceinline__ void stt_lo(double* X, uint32_t off, const double* M) {
+PG_UNROLL
+    for (int i = 0; i < n; ++i)
+PG_UNROLL
+        for (int j = 0; j <= i; ++j) sto(X, off, i * n + j, M[i * n + j]);
+}
+template <int n>
+__device__ __forceinline__ void ldt_sym(const double* X, uint32_t off, double* M) {
+PG_UNROLL
+    for (int i = 0; i < n; ++i)
+PG_UNROLL
+        for (int j = 0; j <= i; ++j) {
+            const double v = ldo(X, off, i * n + j);
+            M[i * n + j] = v;
+            M[j * n + i] = v;
+        }
+}
 template <int n>
 __device__ __forceinline__ void src_D(const BlockSrc& b, uint32_t off, double* M) {
 PG_UNROLL
@@ -238,13 +307,15 @@ __device__ __forceinline__ uint32_t sep_pos(int N, int nseg, int j) {
 // Forward elimination of the interior states of segment j.  Matrix blocks
 // come from M, temporaries go to ws; both are chain-order views indexed
 // by plan-local positions.  The loop body has no branches: a missing left
-// separator is a zero fill X, the missing coupling after the last state is
-// a zero U; the blocks of state i + 1 are loaded at the top of step i and
-// combined at its end.
+// separator is a zero fill X, and the coupling stored after the chain's last
+// state is a zero block; the blocks of state i + 1 are loaded at the top of
+// step i and combined at its end.  The pivot P and the fill contribution Z
+// are symmetric: only their lower triangles are formed (P is read only by
+// the inverse; Z is completed once, after the sweep).
 template <int n, bool RHS>
 __device__ __forceinline__ bool seg_forward(const BlockSrc& M, int N, int nseg, int j, const Ws& ws, double* sg,
                                             double* logdet, TS ts) {
-    using G = SegLayout<n>;
+    using G = SegLayout<n, RHS>;
     constexpr int NN = n * n;
     int a, b;
     bool hasL, hasR;
@@ -262,7 +333,7 @@ __device__ __forceinline__ bool seg_forward(const BlockSrc& M, int N, int nseg, 
     PG_MAT(U0n, ts);
     PG_MAT(U1n, ts);
     PG_VEC(y, ts); PG_VEC(yv, ts); PG_VEC(rL, ts); PG_VEC(R0n, ts); PG_VEC(R1n, ts);
-    src_D<n>(M, toff<NN>(ps.at(a)), P);
+    src_D_lo<n>(M, toff<NN>(ps.at(a)), P);
     src_U<n>(M, toff<NN>(ps.at(a)), U);  // every segment has >= 2 states, so U_a exists
     {
         TS ut = ts;
@@ -274,57 +345,68 @@ PG_UNROLL
             for (int c = 0; c < n; ++c) X[r * n + c] = hasL ? UL[c * n + r] : 0.0;
     }
     mzero<n>(Z);
-    if (RHS) {
+    if constexpr (RHS) {
         src_r<n>(M, toff<n>(ps.at(a)), y);
 PG_UNROLL
         for (int e = 0; e < n; ++e) rL[e] = 0.0;
     }
     bool ok = true;
+    DetAcc det;
     for (int i = a; i < b; ++i) {
         TS lt = ts;
         const uint32_t q = ps.at(i), qn = ps.at(i + 1);
         const uint32_t oB = toff<NN>(q), oV = toff<n>(q), oBn = toff<NN>(qn), oVn = toff<n>(qn);
-        const bool hasUn = (i + 1 < b) || hasR;
-        ld2<n, NN>(M.D0, M.D1, oBn, D0n, D1n);
+        ld2_lo<n>(M.D0, M.D1, oBn, D0n, D1n);
         ld2<n, NN>(M.U0, M.U1, oBn, U0n, U1n);
-        if (RHS) ld2<n, n>(M.R0, M.R1, oVn, R0n, R1n);
-        ok = spd_inverse<n>(P, Pinv, RHS ? nullptr : logdet, lt) && ok;
-        if (!RHS) stt<n, NN>(ws.P, oB, Pinv);
+        if constexpr (RHS) ld2<n, n>(M.R0, M.R1, oVn, R0n, R1n);
+        double dblk;
+        ok = spd_inverse<n>(P, Pinv, &dblk, lt) && ok;
+        if constexpr (!RHS) {
+            det.mul(dblk);
+            stt_lo<n>(ws.P, oB, Pinv);
+        }
         mmul<n>(Pinv, U, GU);
         stt<n, NN>(ws.G, oB, GU);
         mmul<n>(Pinv, X, HX);
         stt<n, NN>(ws.H, oB, HX);
-        msub_tn<n>(X, HX, Z);
-        if (RHS) {
+        // the next state's blocks, combined as soon as the pivot is used up
+        // (shorter live ranges for the raw loads)
+        comb_lo<n>(M.a0, D0n, M.a1, D1n, P);
+        PG_MAT(Un, lt);
+        comb<n, n * n>(M.a0, U0n, M.a1, U1n, Un);
+        msub_tn_lo<n>(X, HX, Z);
+        if constexpr (RHS) {
             mvec<n>(Pinv, y, yv);
             stt<n, n>(ws.Y, oV, yv);
             mvec_tn_sub<n>(X, yv, rL);
         }
         // X_{i+1} = -U^T HX, P_{i+1} = D_{i+1} - U^T GU, y_{i+1} = r_{i+1} - U^T yv
-        mmul_tn<n>(U, HX, X);
-PG_UNROLL
-        for (int e = 0; e < n * n; ++e) X[e] = -X[e];
-        comb<n, n * n>(M.a0, D0n, M.a1, D1n, P);
-        msub_tn<n>(U, GU, P);
-        if (RHS) {
+        mmul_tn_neg<n>(U, HX, X);
+        msub_tn_lo<n>(U, GU, P);
+        if constexpr (RHS) {
             comb<n, n>(M.a0, R0n, M.a1, R1n, y);
             mvec_tn_sub<n>(U, yv, y);
         }
-PG_UNROLL
-        for (int e = 0; e < n * n; ++e) U[e] = hasUn ? lin2(M.a0, U0n[e], M.a1, U1n[e]) : 0.0;
+        mcopy<n>(Un, U);
     }
     {
         // last interior state b: its Schur contributions to the separators
         TS lt = ts;
         const uint32_t q = ps.at(b), oB = toff<NN>(q), oV = toff<n>(q);
-        ok = spd_inverse<n>(P, Pinv, RHS ? nullptr : logdet, lt) && ok;
-        if (!RHS) stt<n, NN>(ws.P, oB, Pinv);
+        double dblk;
+        ok = spd_inverse<n>(P, Pinv, &dblk, lt) && ok;
+        if constexpr (!RHS) {
+            det.mul(dblk);
+            stt_lo<n>(ws.P, oB, Pinv);
+            *logdet += det.log_value();
+        }
         mmul<n>(Pinv, U, GU);
         stt<n, NN>(ws.G, oB, GU);
         mmul<n>(Pinv, X, HX);
         stt<n, NN>(ws.H, oB, HX);
-        msub_tn<n>(X, HX, Z);
-        if (RHS) {
+        msub_tn_lo<n>(X, HX, Z);
+        sym_from_lo<n>(Z);
+        if constexpr (RHS) {
             mvec<n>(Pinv, y, yv);
             stt<n, n>(ws.Y, oV, yv);
             mvec_tn_sub<n>(X, yv, rL);
@@ -334,7 +416,7 @@ PG_UNROLL
             mmul_tn<n>(U, GU, T);
 PG_UNROLL
             for (int e = 0; e < n * n; ++e) sgv(sg, j, G::DR + e) = -T[e];
-            if (RHS) {
+            if constexpr (RHS) {
                 PG_VEC(t, lt);
 PG_UNROLL
                 for (int e = 0; e < n; ++e) t[e] = 0.0;
@@ -346,7 +428,7 @@ PG_UNROLL
         if (hasL) {
 PG_UNROLL
             for (int e = 0; e < n * n; ++e) sgv(sg, j, G::DL + e) = Z[e];
-            if (RHS) {
+            if constexpr (RHS) {
 PG_UNROLL
                 for (int e = 0; e < n; ++e) sgv(sg, j, G::RL + e) = rL[e];
             }
@@ -383,7 +465,7 @@ PG_UNROLL
 template <int n, bool RHS>
 __device__ __forceinline__ void cr_assemble_read(const BlockSrc& M, int N, int nseg, int j, double* sg, double* A,
                                                  double* C, double* r) {
-    using G = SegLayout<n>;
+    using G = SegLayout<n, RHS>;
     const int m = nseg - 1;
     const uint32_t q = sep_pos(N, nseg, j);
     src_D<n>(M, toff<n * n>(q), A);
@@ -392,7 +474,7 @@ PG_UNROLL
         A[e] += sgv(sg, j, G::DR + e) + sgv(sg, j + 1, G::DL + e);
         C[e] = j + 1 < m ? sgv(sg, j + 1, G::CLR + e) : 0.0;
     }
-    if (RHS) {
+    if constexpr (RHS) {
         src_r<n>(M, toff<n>(q), r);
 PG_UNROLL
         for (int e = 0; e < n; ++e) r[e] += sgv(sg, j, G::RR + e) + sgv(sg, j + 1, G::RL + e);
@@ -402,10 +484,10 @@ PG_UNROLL
 template <int n, bool RHS>
 __device__ __forceinline__ void cr_assemble_write(int j, double* sg, const double* A, const double* C,
                                                   const double* r) {
-    using G = SegLayout<n>;
+    using G = SegLayout<n, RHS>;
     st_node<n>(sg, j, G::NA, A);
     st_node<n>(sg, j, G::NC, C);
-    if (RHS) {
+    if constexpr (RHS) {
 PG_UNROLL
         for (int e = 0; e < n; ++e) sgv(sg, j, G::NR + e) = r[e];
     }
@@ -417,7 +499,7 @@ PG_UNROLL
 // neighbours and their new right coupling -M(j, k) P M(k, R) (barrier).
 template <int n, bool RHS>
 __device__ __forceinline__ bool cr_forward(int m, int j, double* sg, double* logdet, TS ts) {
-    using G = SegLayout<n>;
+    using G = SegLayout<n, RHS>;
     const int levels = cr_levels(m);
     const bool own = j < m;
     const int lv = own ? __builtin_ctz(j + 1) : -1;
@@ -431,8 +513,10 @@ __device__ __forceinline__ bool cr_forward(int m, int j, double* sg, double* log
             PG_MAT(C, lt);
             PG_MAT(T, lt);
             ld_node<n>(sg, j, G::NA, A);
-            ok = spd_inverse<n>(A, P, RHS ? nullptr : logdet, lt) && ok;
-            st_node<n>(sg, j, G::NP, P);
+            double dblk;
+            ok = spd_inverse<n>(A, P, &dblk, lt) && ok;
+            if constexpr (!RHS) *logdet += log(dblk);
+            if constexpr (!RHS) st_node<n>(sg, j, G::NP, P);
             if (j - h >= 0) {
                 ld_node<n>(sg, j - h, G::NC, C);  // M(L, k)
                 mmul_nt<n>(P, C, T);
@@ -443,7 +527,7 @@ __device__ __forceinline__ bool cr_forward(int m, int j, double* sg, double* log
                 mmul<n>(P, C, T);
                 st_node<n>(sg, j, G::NGR, T);
             }
-            if (RHS) {
+            if constexpr (RHS) {
                 PG_VEC(r, lt);
                 PG_VEC(z, lt);
 PG_UNROLL
@@ -462,7 +546,7 @@ PG_UNROLL
             PG_VEC(r, lt);
             PG_VEC(z, lt);
             ld_node<n>(sg, j, G::NA, A);
-            if (RHS) {
+            if constexpr (RHS) {
 PG_UNROLL
                 for (int e = 0; e < n; ++e) r[e] = sgv(sg, j, G::NR + e);
             }
@@ -473,7 +557,7 @@ PG_UNROLL
                 ld_node<n>(sg, j, G::NC, C);
                 ld_node<n>(sg, k, G::NGL, Gk);
                 msub<n>(C, Gk, A);
-                if (RHS) {
+                if constexpr (RHS) {
 PG_UNROLL
                     for (int e = 0; e < n; ++e) z[e] = sgv(sg, k, G::NZ + e);
                     mvec_sub<n>(C, z, r);
@@ -492,14 +576,14 @@ PG_UNROLL
                 ld_node<n>(sg, k, G::NC, C);
                 ld_node<n>(sg, k, G::NGR, Gk);
                 msub_tn<n>(C, Gk, A);
-                if (RHS) {
+                if constexpr (RHS) {
 PG_UNROLL
                     for (int e = 0; e < n; ++e) z[e] = sgv(sg, k, G::NZ + e);
                     mvec_tn_sub<n>(C, z, r);
                 }
             }
             st_node<n>(sg, j, G::NA, A);
-            if (RHS) {
+            if constexpr (RHS) {
 PG_UNROLL
                 for (int e = 0; e < n; ++e) sgv(sg, j, G::NR + e) = r[e];
             }
@@ -552,7 +636,7 @@ PG_UNROLL
 template <int n, bool TRACE>
 __device__ __forceinline__ void cr_backward_cov(int m, int j, bool run, int N, int nseg, double* sg, double* SDo,
                                                 const double* KH, double* trace, TS ts) {
-    using G = SegLayout<n>;
+    using G = SegLayout<n, false>;
     const int levels = cr_levels(m);
     const bool own = run && j < m;
     const int lv = own ? __builtin_ctz(j + 1) : -1;
@@ -623,7 +707,7 @@ PG_UNROLL
 template <int n, bool QUAD>
 __device__ __forceinline__ void cr_backward_rhs(int m, int j, bool run, int N, int nseg, double* sg, double* xo,
                                                 const double* LD, const double* mu0, double* quad, TS ts) {
-    using G = SegLayout<n>;
+    using G = SegLayout<n, true>;
     const int levels = cr_levels(m);
     const bool own = run && j < m;
     const int lv = own ? __builtin_ctz(j + 1) : -1;
@@ -675,7 +759,7 @@ template <int n, bool TRACE>
 __device__ __forceinline__ void seg_backward_cov(int N, int nseg, int j, const Ws& ws, double* sg, double* SDo,
                                                  double* SUo, const double* KH, const double* KU, double* trace,
                                                  TS ts) {
-    using G = SegLayout<n>;
+    using G = SegLayout<n, false>;
     constexpr int NN = n * n;
     int a, b;
     bool hasL, hasR;
@@ -710,7 +794,7 @@ PG_UNROLL
     PG_MAT(Ku, ts);
     {
         const uint32_t ob = toff<NN>(ps.at(b));
-        ldt<n, NN>(ws.P, ob, Pc);
+        ldt_sym<n>(ws.P, ob, Pc);
         ldt<n, NN>(ws.G, ob, Gc);
         ldt<n, NN>(ws.H, ob, Hc);
     }
@@ -718,7 +802,7 @@ PG_UNROLL
         TS lt = ts;
         const uint32_t oB = toff<NN>(ps.at(i)), oBp = toff<NN>(ps.at(i > a ? i - 1 : a));
         const bool hasNext = i < b || hasR;
-        ldt<n, NN>(ws.P, oBp, Pn);
+        ldt_sym<n>(ws.P, oBp, Pn);
         ldt<n, NN>(ws.G, oBp, Gn);
         ldt<n, NN>(ws.H, oBp, Hn);
         if (TRACE) {
@@ -727,20 +811,17 @@ PG_UNROLL
         }
         PG_MAT(Sin, lt);
         PG_MAT(SiL, lt);
-        PG_MAT(T, lt);
         // Sin = -(GU S_nn + HX S_nL^T), SiL = -(GU S_nL + HX S_LL)
-        mmul<n>(Gc, Snn, Sin);
-        mmul_nt<n>(Hc, SnL, T);
-        mmul<n>(Gc, SnL, SiL);
-PG_UNROLL
-        for (int e = 0; e < n * n; ++e) Sin[e] = -(Sin[e] + T[e]);
-        mmul<n>(Hc, SLL, T);
-PG_UNROLL
-        for (int e = 0; e < n * n; ++e) SiL[e] = -(SiL[e] + T[e]);
-        msub_nt<n>(Sin, Gc, Pc);
-        msub_nt<n>(SiL, Hc, Pc);
+        mmul_neg<n>(Gc, Snn, Sin);
+        msub_nt<n>(Hc, SnL, Sin);
+        mmul_neg<n>(Gc, SnL, SiL);
+        msub<n>(Hc, SLL, SiL);
+        // Sigma_ii is symmetric: its lower triangle, then the upper one
+        msub_nt_lo<n>(Sin, Gc, Pc);
+        msub_nt_lo<n>(SiL, Hc, Pc);
+        sym_from_lo<n>(Pc);
         stt<n, NN>(SUo, oB, Sin);
-        stt_sym<n>(SDo, oB, Pc);
+        stt<n, NN>(SDo, oB, Pc);
         if (TRACE) {
             const double to = tr_off<n>(Ku, Sin);
             *trace += tr_diag<n>(Kd, Pc) + (hasNext ? to : 0.0);
@@ -772,7 +853,7 @@ template <int n, bool QUAD>
 __device__ __forceinline__ void seg_backward_rhs(int N, int nseg, int j, const Ws& ws, double* sg, double* xo,
                                                  const double* LD, const double* LU, const double* mu0, double* quad,
                                                  TS ts) {
-    using G = SegLayout<n>;
+    using G = SegLayout<n, true>;
     constexpr int NN = n * n;
     int a, b;
     bool hasL, hasR;
@@ -1077,7 +1158,7 @@ __global__ void __launch_bounds__(kTrialThreads) chain_kernel(DevState st, int m
     const int N = p.N, nseg = p.nseg;
     const int64_t off = p.off, S = st.S, coff = p.coff;
     __shared__ double sg_lds[NodeLds<n>::size];
-    double* sg = NodeLds<n>::value ? sg_lds + half * kMaxSeg * SegLayout<n>::STRIDE : seg_scratch<n>(st, pid, 0, half);
+    double* sg = NodeLds<n>::value ? sg_lds + half * kMaxSeg * SegLayout<n, false>::STRIDE : seg_scratch<n>(st, pid, 0, half);
     const Ws ws = sweep_ws<n>(st, half, coff);
     TS ts = thread_ws<n>(st, pid, 0);
     const bool prior = mode == CHAIN_INIT || mode == CHAIN_REINIT;
@@ -1094,6 +1175,8 @@ __global__ void __launch_bounds__(kTrialThreads) chain_kernel(DevState st, int m
                 const double u = prior ? st.KU[e * S + s] : st.LU[e * S + s];
                 cU[tidx<NN>(q, e)] = u;
                 if (prior) st.LU[e * S + s] = u;
+            } else {
+                cU[tidx<NN>(q, e)] = 0.0;  // the coupling after the chain's last state is a zero block
             }
         }
         if (mode == CHAIN_INIT)
@@ -1171,10 +1254,9 @@ __global__ void __launch_bounds__(kIterThreads) prep_kernel(DevState st) {
             st.cKD[qe] = kd;
             st.cKH[qe] = kd;
             st.cLD[qe] = st.LD[e * S + s];
-            if (i < N - 1) {
-                st.cKU[qe] = st.KU[e * S + s];
-                st.cLU[qe] = st.LU[e * S + s];
-            }
+            // the coupling after the chain's last state is a zero block
+            st.cKU[qe] = i < N - 1 ? st.KU[e * S + s] : 0.0;
+            st.cLU[qe] = i < N - 1 ? st.LU[e * S + s] : 0.0;
         }
         PG_VEC(r, lt);
         ld_vec<n>(st.eta, S, s, r);
@@ -1224,57 +1306,49 @@ PG_UNROLL
     if (tid == 0) {
         st.psum[((int64_t)pid * nb + y) * 2 + 0] = ecol;
         st.psum[((int64_t)pid * nb + y) * 2 + 1] = epri;
-        if (y == 0) {
-            // first window: all W step sizes, or (lookahead) a few more than
-            // the previous iteration needed
-            const int W = st.W;
-            int w1 = W;
-            if (st.lookahead > 0 && p.iters_done > 0) w1 = min(W, max(1, p.trials + st.lookahead));
-            p.w1 = min(w1, p.max_bisect);
-            p.phase = 0;
-        }
+        if (y == 0) p.phase = 0;
     }
 }
 
-// Window r of an iteration's step sizes: [start, start + width) of the
-// halving sequence, clipped to max_bisect.  Window 0 has the plan's width
-// w1 (set by prep), later windows the full W.
-__device__ __forceinline__ void trial_window(const PlanDev& p, int W, int r, int& start, int& width) {
-    start = r == 0 ? 0 : p.w1 + (r - 1) * W;
-    width = r == 0 ? p.w1 : W;
-    width = max(0, min(width, p.max_bisect - start));
-}
-
-// Part 2: trial step size number start + blockIdx.y of window `round` for plan blockIdx.x:
+// Part 2: one trial step size per workgroup, item j of the window's work
+// list (plan, slot): step size number wstart + slot of the plan's current
+// window.  Workgroup b runs on XCD b mod 8 and takes item
+// (b mod 8) * C + b / 8, C = ceil(items / 8): each XCD gets an equal run of
+// the plan-ordered list, so a plan's trials share one or two L2s.
+// For that step size:
 //   Lambda' = (beta (K^-1 + H) + Lambda_k) / (beta T + 1)  -> marginals, log det, PD
 //   (K^-1 + Lambda_k / beta) mu' = eta - g + Lambda_k mu_k / beta
 //   KL(q' || q_k) = 1/2 [beta (T dim - tr((K^-1 + H) Sigma')) + dmu^T Lambda_k dmu
 //                        + log det Lambda' - log det Lambda_k]
 // (the trace term uses Lambda_k = (beta T + 1) Lambda' - beta (K^-1 + H) and
 // tr(Lambda' Sigma') = dim).  Results go to the trial slot (chain order) and
-// st.tres.
+// st.tres (passed, KL, log det, slot).
 template <int n>
-__global__ void __launch_bounds__(kTrialThreads) trial_kernel(DevState st, int round) {
-    __shared__ double sh_d[kTrialThreads + 1];
+__global__ void __launch_bounds__(kTrialThreads) trial_kernel(DevState st) {
+    const int items = st.wlist[0];
+    const int chunk = (items + kNumXcd - 1) / kNumXcd;
+    const int kx = (int)blockIdx.x / kNumXcd;
+    const int j = ((int)blockIdx.x % kNumXcd) * chunk + kx;
+    if (kx >= chunk || j >= items) return;
+    const int item = st.wlist[1 + j];
+    __shared__ double sh_d[kChainThreads + 1];
     __shared__ int sh_i[kChainThreads + 1];
     __shared__ int sh_j[kChainThreads + 1];
     constexpr int NN = n * n;
-    const int pid = blockIdx.x, t = blockIdx.y;
+    const int pid = item >> 6, t = item & 63;
     const PlanDev& p = st.plans[pid];
-    if (!p.active || p.phase != 0) return;
-    int wstart, wwidth;
-    trial_window(p, st.W, round, wstart, wwidth);
-    if (t >= wwidth) return;
-    const int tt = wstart + t;
-    const double* tr = st.tres + (int64_t)pid * kMaxBisect * 4;
-    for (int k = 0; k < wstart; ++k)  // an earlier window already has a passing step
-        if (tr[4 * k] != 0.0 && tr[4 * k + 1] <= p.kl_bound) return;
+    if (!p.active || p.phase != 0 || t >= p.wwidth) return;
+    const int tt = p.wstart + t;
     const int tid = threadIdx.x;
     const int half = tid / kChainThreads, lane = tid % kChainThreads;
     const int N = p.N, nseg = p.nseg;
     const int64_t coff = p.coff, c0 = (int64_t)t * st.Sc + coff;
-    __shared__ double sg_lds[NodeLds<n>::size];
-    double* sg = NodeLds<n>::value ? sg_lds + half * kMaxSeg * SegLayout<n>::STRIDE : seg_scratch<n>(st, pid, t, half);
+    // With LDS node scratch a trial workgroup takes just under half a CU's
+    // LDS; kTrialLdsPad unused bytes keep it to one workgroup per CU.  Two
+    // per CU run each other ~1.45x slower, and the dispatcher pairs them up
+    // even in windows smaller than the chip.
+    __shared__ double sg_lds[NodeLds<n>::size + (NodeLds<n>::value ? kTrialLdsPad / 8 : 0)];
+    double* sg = NodeLds<n>::value ? sg_lds + half * kMaxSeg * SegLayout<n, false>::STRIDE : seg_scratch<n>(st, pid, t, half);
     const Ws ws = sweep_ws<n>(st, half, c0);
     TS ts = thread_ws<n>(st, pid, t);
     double* res = st.tres + ((int64_t)pid * kMaxBisect + tt) * 4;
@@ -1289,7 +1363,10 @@ __global__ void __launch_bounds__(kTrialThreads) trial_kernel(DevState st, int r
     // wave 0: marginals and PD test of the trial precision, with the trace
     // term; wave 1: trial mean, with the quadratic term.  Both helpers pass
     // the same workgroup barriers.
-    __shared__ double sh_t[kTrialThreads];
+    // per-lane KL partial sums; with LDS node scratch they reuse it (both
+    // helpers end with a barrier after their last scratch access)
+    __shared__ double sh_t_own[NodeLds<n>::value ? 1 : kTrialThreads];
+    double* sh_t = NodeLds<n>::value ? sg_lds : sh_t_own;
     double part = 0.0, ld_trial = 0.0;
     if (half == 0) {
         BlockSrc MT{kh, lD, ku, lU, kh, lD, c * beta, c};
@@ -1307,7 +1384,7 @@ __global__ void __launch_bounds__(kTrialThreads) trial_kernel(DevState st, int r
             res[0] = 0.0;
             res[1] = NAN;
             res[2] = NAN;
-            res[3] = beta;
+            res[3] = t;
         } else {
             // partial sums in lane order: trace from wave 0, quadratic from wave 1
             double trKH = 0.0, quad = 0.0;
@@ -1316,16 +1393,18 @@ __global__ void __launch_bounds__(kTrialThreads) trial_kernel(DevState st, int r
             res[0] = 1.0;
             res[1] = 0.5 * (beta * (T * (double)N * n - trKH) + quad + ld_trial - p.logdet);
             res[2] = ld_trial;
-            res[3] = beta;
+            res[3] = t;
+            if (res[1] <= p.kl_bound) atomicMin(&st.plans[pid].firstpass, tt);
         }
     }
 }
 
 // Part 3 (after the last window): take the first passing step size in
 // halving order and write its trial back, in state order, as the new
-// iterate; a plan with no passing step keeps its state (ENOCONV).  Every
-// step size before the first passing one was evaluated in this iteration,
-// so the scan reads only this iteration's results.  Grid (plans,
+// iterate; a plan with no passing step keeps its state (ENOCONV).  The
+// windows cover step sizes 0 .. wnext-1 of this iteration without gaps and
+// stop after the first passing one, so the scan reads only this
+// iteration's results.  Grid (plans,
 // iter_blocks): every block finds the same pick and copies its share of the
 // states; block 0 does the bookkeeping.
 template <int n>
@@ -1335,24 +1414,18 @@ __global__ void __launch_bounds__(kIterThreads) select_kernel(DevState st, int /
     PlanDev& p = st.plans[pid];
     if (!p.active || p.phase != 0) return;
     const int tid = threadIdx.x;
-    const int W = st.W;
     const double* tr = st.tres + (int64_t)pid * kMaxBisect * 4;
-    int pick = -1;
-    for (int k = 0; k < p.max_bisect; ++k)
-        if (tr[4 * k] != 0.0 && tr[4 * k + 1] <= p.kl_bound) {
-            pick = k;
-            break;
-        }
-    const double last_kl = tr[4 * (p.max_bisect - 1) + 1];
+    const int evaluated = p.wnext;
+    const int pick = p.firstpass != kNoPass ? p.firstpass : -1;
+    const double last_kl = evaluated > 0 ? tr[4 * (evaluated - 1) + 1] : NAN;
     // trial slot of step size number pick: its position in its window
-    int slot = pick;
-    if (pick >= p.w1) slot = (pick - p.w1) % W;
+    const int slot = pick >= 0 ? (int)tr[4 * pick + 3] : 0;
     const int N = p.N, nseg = p.nseg;
     const int64_t S = st.S, off = p.off, coff = p.coff;
     double beta = 0.0, kl = last_kl, ld = 0.0;
     if (pick >= 0) {
         const double* res = tr + 4 * pick;
-        beta = res[3];
+        beta = ldexp(p.beta_max, -pick);
         kl = res[1];
         ld = res[2];
         const double c = 1.0 / fma(beta, p.temperature, 1.0);
@@ -1381,9 +1454,7 @@ __global__ void __launch_bounds__(kIterThreads) select_kernel(DevState st, int /
         p.trials = pick >= 0 ? pick + 1 : p.max_bisect;
         p.trials_total += p.trials;
         // step sizes evaluated: every window up to the one holding the pick
-        int evals = p.max_bisect;
-        if (pick >= 0) evals = pick < p.w1 ? p.w1 : min(p.max_bisect, p.w1 + ((pick - p.w1) / W + 1) * W);
-        p.evals_total += evals;
+        p.evals_total += evaluated;
         p.kl = kl;
         if (pick >= 0) {
             p.logdet = ld;
@@ -1421,13 +1492,16 @@ hipError_t launch_chain_n(const DevState& st, int mode, int lo, int hi, hipStrea
     return hipGetLastError();
 }
 
-// part: 0 = prep, 1 = trial window `round`, 2 = select for window `round`
+// part: 0 = prep, 1 = trial (each plan's current window), 2 = select
 template <int n>
 hipError_t launch_iteration_n(const DevState& st, int phw, int part, int round, hipStream_t s) {
     if (phw <= 0) return hipSuccess;
     const dim3 it(phw, st.iter_blocks);
     if (part == 0) hipLaunchKernelGGL(prep_kernel<n>, it, dim3(kIterThreads), 0, s, st);
-    if (part == 1) hipLaunchKernelGGL(trial_kernel<n>, dim3(phw, st.W), dim3(kTrialThreads), 0, s, st, round);
+    if (part == 1) {
+        const int64_t blocks = ((int64_t)phw * st.W + kNumXcd - 1) / kNumXcd * kNumXcd;
+        hipLaunchKernelGGL(trial_kernel<n>, dim3((unsigned)blocks), dim3(kTrialThreads), 0, s, st);
+    }
     if (part == 2) hipLaunchKernelGGL(select_kernel<n>, it, dim3(kIterThreads), 0, s, st, round);
     return hipGetLastError();
 }

@@ -23,6 +23,8 @@ constexpr int kMaxGH = 10;        // Gauss-Hermite points per dimension
 // live blocks + the first coupling 1 + Cholesky inverse 2 = 18 (8 vectors);
 // segment backward sweep 16 blocks; mean-solve backward sweep 10 vectors.
 constexpr int kTwsBlocks = 20;
+constexpr int32_t kNoPass = 0x7fffffff;
+constexpr int kNumXcd = 8;  // XCDs; workgroup b of a launch runs on XCD b mod 8
 constexpr int kTwsVecs = 16;
 
 // Per-plan parameters and statistics, read by every kernel.  One entry per
@@ -33,7 +35,10 @@ struct PlanDev {
     int32_t d, gh_points, gx, gy;
     int32_t gz, n_spheres, coll_states, status;
     int32_t trials, m, n_iters, trials_total;
-    int32_t w1;   // width of this iteration's first window of step sizes
+    // window of step sizes being evaluated: numbers [wstart, wstart + wwidth);
+    // wnext = step sizes evaluated so far in this iteration
+    int32_t wstart, wwidth, wnext;
+    int32_t firstpass;  // smallest passing step size number so far (kNoPass if none)
     int32_t evals_total;  // step sizes evaluated since the (re)start, speculative ones included
     int32_t ltv;  // 0: every interval has the same dynamics (A, a, B)
     int32_t phase;  // 0 = iteration pending, 1 = no iteration (budget spent)
@@ -81,7 +86,12 @@ struct DevState {
     // (stride W * Sc)
     double *Tmu, *TSD, *TSU;
     double* tres;  // per (plan, step size number < kMaxBisect): passed, KL, log det, beta
-    int32_t W;     // trial step sizes evaluated concurrently
+    int32_t W;     // trial slots per plan = the widest window of step sizes
+    int32_t Wmin;  // the narrowest window (trial_width)
+    int32_t wbudget;      // trial workgroups a window may start at once (compute units)
+    // work list of the current window: [0] = item count, then one item per
+    // trial workgroup, plan * 64 + slot, plan by plan
+    int32_t* wlist;
     int32_t iter_blocks;  // blocks per plan of the prep and select kernels
     int32_t lookahead;    // first-window lookahead (0 = full first window)
     double* psum;         // per (plan, prep block): partial E_coll, E_prior
@@ -172,6 +182,8 @@ hipError_t launch_chain(const DevState& st, int mode, int plan_lo, int plan_hi, 
 // parts of one proximal iteration for plans [0, phw): 0 = prep, 1 = trial
 // window `round`, 2 = select for window `round`
 hipError_t launch_iteration(const DevState& st, int phw, int part, int round, hipStream_t s);
+// Window `round` of step sizes of the current iteration for plans [0, phw).
+hipError_t launch_window(const DevState& st, int phw, int round, hipStream_t s);
 // collision expectations of plans [plan_lo, plan_hi) of up to maxN states each
 hipError_t launch_expect(const DevState& st, int coll_kind, int d, int p, int precision, int lanes, int plan_lo,
                          int plan_hi, int maxN, int respect_budget, hipStream_t s);

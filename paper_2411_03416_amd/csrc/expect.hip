@@ -33,7 +33,6 @@ namespace pg {
 
 constexpr int kExpectThreads = 256;
 constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
-constexpr int kNumXcd = 8;
 
 template <typename R>
 struct Tab;

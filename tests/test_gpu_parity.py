@@ -429,8 +429,8 @@ def test_trial_window_does_not_change_results(pg):
     # (also with a shortened first window that misses and continues)
     probs = [workloads.point2d_problem(s, N=N) for s, N in [(5, 60), (6, 31)]]
     ref = None
-    for w, look in ((1, 0), (3, 0), (16, 0), (16, 1), (4, 2), (16, 3)):
-        ctx = pg.pgvimp_create(probs, use_graph=True, trial_width=w, trial_lookahead=look)
+    for w, look, slots in ((1, 0, 1), (3, 0, 0), (16, 0, 0), (16, 1, 64), (4, 2, 5), (16, 3, 16), (2, 0, 64)):
+        ctx = pg.pgvimp_create(probs, use_graph=True, trial_width=w, trial_lookahead=look, trial_slots=slots)
         stats = [pg.pgvimp_prox_step(ctx, 1) for _ in range(8)]
         states = [pg.pgvimp_get_state(ctx, k) for k in range(len(probs))]
         if ref is None:
@@ -441,4 +441,4 @@ def test_trial_window_does_not_change_results(pg):
                 assert a[k]["beta"] == b[k]["beta"] and a[k]["trials"] == b[k]["trials"]
         for sa, sb in zip(states, ref[1]):
             for x, y in zip(sa, sb):
-                assert np.array_equal(x, y), (w, look)
+                assert np.array_equal(x, y), (w, look, slots)
