@@ -1012,6 +1012,18 @@ __device__ __forceinline__ bool wg_solve(const BlockSrc& M, const Ws& ws, int ti
     return okall;
 }
 
+// Entries per staged chunk of the per-state copies (all loads of a chunk,
+// then its stores).
+template <int NN>
+constexpr int kCopyChunk = NN < 16 ? NN : 16;
+
+// Position of state coordinate r among the plan's collision coordinates, or -1.
+__device__ __forceinline__ int coll_slot(const PlanDev& p, int r) {
+    int a = -1;
+    for (int t = 0; t < p.d; ++t) a = p.coll_index[t] == r ? t : a;
+    return a;
+}
+
 // Collision contributions of state i embedded into the n-dim state.
 template <int n>
 __device__ __forceinline__ bool coll_active(const PlanDev& p, int i) {
@@ -1248,15 +1260,38 @@ __global__ void __launch_bounds__(kIterThreads) prep_kernel(DevState st) {
         TS lt = ts;
         const int64_t s = off + i, q = coff + chain_pos(N, nseg, i);
         const bool act = coll_active<n>(p, i);
-        for (int e = 0; e < NN; ++e) {
-            const int64_t qe = tidx<NN>(q, e);
-            const double kd = st.KD[e * S + s];
-            st.cKD[qe] = kd;
-            st.cKH[qe] = kd;
-            st.cLD[qe] = st.LD[e * S + s];
-            // the coupling after the chain's last state is a zero block
-            st.cKU[qe] = i < N - 1 ? st.KU[e * S + s] : 0.0;
-            st.cLU[qe] = i < N - 1 ? st.LU[e * S + s] : 0.0;
+        const bool notlast = i < N - 1;
+        // Each group's loads come before its stores (the stores go to other
+        // arrays, but the compiler cannot know that): block copies, then the
+        // right-hand side eta - g and Lambda_k mu_k, then the prior costs.
+        for (int e0 = 0; e0 < NN; e0 += kCopyChunk<NN>) {
+            constexpr int CH = kCopyChunk<NN>;
+            double kd[CH], kh[CH], ld[CH], ku[CH], lu[CH];
+#pragma unroll
+            for (int k = 0; k < CH; ++k) {
+                const int e = min(e0 + k, NN - 1);
+                kd[k] = st.KD[e * S + s];
+                ld[k] = st.LD[e * S + s];
+                // the coupling after the chain's last state is a zero block
+                ku[k] = notlast ? st.KU[e * S + s] : 0.0;
+                lu[k] = notlast ? st.LU[e * S + s] : 0.0;
+                kh[k] = kd[k];
+                if (act) {  // collision Hessian on the collision coordinates
+                    const int a = coll_slot(p, e / n), b2 = coll_slot(p, e % n);
+                    if (a >= 0 && b2 >= 0) kh[k] += st.Hcol[(a * d + b2) * S + s];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < CH; ++k) {
+                const int e = e0 + k;
+                if (e >= NN) break;
+                const int64_t qe = tidx<NN>(q, e);
+                st.cKD[qe] = kd[k];
+                st.cKH[qe] = kh[k];
+                st.cLD[qe] = ld[k];
+                st.cKU[qe] = ku[k];
+                st.cLU[qe] = lu[k];
+            }
         }
         PG_VEC(r, lt);
         ld_vec<n>(st.eta, S, s, r);
@@ -1267,38 +1302,45 @@ __global__ void __launch_bounds__(kIterThreads) prep_kernel(DevState st) {
                 const int ca = p.coll_index[a];
 PG_UNROLL
                 for (int e = 0; e < n; ++e) r[e] -= e == ca ? ga : 0.0;  // static indexing keeps r in registers
-                for (int b2 = 0; b2 < d; ++b2) {
-                    const int e = ca * n + p.coll_index[b2];
-                    st.cKH[tidx<NN>(q, e)] = st.KD[e * S + s] + st.Hcol[(a * d + b2) * S + s];
-                }
             }
         }
-        for (int e = 0; e < n; ++e) st.crb[tidx<n>(q, e)] = r[e];
         PG_MAT(Dm, lt);
+        PG_MAT(Um, lt);
+        PG_MAT(Up, lt);
         PG_VEC(m, lt);
+        PG_VEC(mn, lt);
+        PG_VEC(mp, lt);
         PG_VEC(t, lt);
         PG_VEC(acc, lt);
         ld_soa<n>(st.LD, S, s, Dm);
         ld_vec<n>(st.mu, S, s, m);
-        for (int e = 0; e < n; ++e) st.cmu[tidx<n>(q, e)] = m[e];
+        if (notlast) {
+            ld_soa<n>(st.LU, S, s, Um);
+            ld_vec<n>(st.mu, S, s + 1, mn);
+        }
+        if (i > 0) {
+            ld_soa<n>(st.LU, S, s - 1, Up);
+            ld_vec<n>(st.mu, S, s - 1, mp);
+        }
         mvec<n>(Dm, m, acc);
-        if (i < N - 1) {
-            ld_soa<n>(st.LU, S, s, Dm);
-            ld_vec<n>(st.mu, S, s + 1, m);
-            mvec<n>(Dm, m, t);
+        if (notlast) {
+            mvec<n>(Um, mn, t);
 PG_UNROLL
             for (int e = 0; e < n; ++e) acc[e] += t[e];
         }
         if (i > 0) {
-            ld_soa<n>(st.LU, S, s - 1, Dm);
-            ld_vec<n>(st.mu, S, s - 1, m);
 PG_UNROLL
             for (int e = 0; e < n; ++e) t[e] = 0.0;
-            mvec_tn_sub<n>(Dm, m, t);
+            mvec_tn_sub<n>(Up, mp, t);
 PG_UNROLL
             for (int e = 0; e < n; ++e) acc[e] -= t[e];
         }
-        for (int e = 0; e < n; ++e) st.cLmu[tidx<n>(q, e)] = acc[e];
+PG_UNROLL
+        for (int e = 0; e < n; ++e) {
+            st.crb[tidx<n>(q, e)] = r[e];
+            st.cmu[tidx<n>(q, e)] = m[e];
+            st.cLmu[tidx<n>(q, e)] = acc[e];
+        }
         epri += prior_cost_state<n>(st, p, i, nullptr, nullptr, nullptr, lt);
     }
     ecol = block_sum(ecol, sh_d);
@@ -1432,15 +1474,38 @@ __global__ void __launch_bounds__(kIterThreads) select_kernel(DevState st, int /
         const double a0 = c * beta, a1 = c;
         for (int i = y * kIterThreads + tid; i < N; i += nb * kIterThreads) {
             const int64_t s = off + i, qs = coff + chain_pos(N, nseg, i), q = (int64_t)slot * st.Sc + qs;
-            for (int e = 0; e < NN; ++e) {
-                st.LD[e * S + s] = lin2(a0, st.cKH[tidx<NN>(qs, e)], a1, st.LD[e * S + s]);
-                st.SD[e * S + s] = st.TSD[tidx<NN>(q, e)];
-                if (i < N - 1) {
-                    st.LU[e * S + s] = lin2(a0, st.KU[e * S + s], a1, st.LU[e * S + s]);
-                    st.SU[e * S + s] = st.TSU[tidx<NN>(q, e)];
+            const bool notlast = i < N - 1;
+            for (int e0 = 0; e0 < NN; e0 += kCopyChunk<NN>) {
+                // every load of the chunk before its stores (see prep_kernel)
+                constexpr int CH = kCopyChunk<NN>;
+                double kh[CH], ld[CH], sd[CH], ku[CH], lu[CH], su[CH];
+#pragma unroll
+                for (int k = 0; k < CH; ++k) {
+                    const int e = min(e0 + k, NN - 1);
+                    kh[k] = st.cKH[tidx<NN>(qs, e)];
+                    ld[k] = st.LD[e * S + s];
+                    sd[k] = st.TSD[tidx<NN>(q, e)];
+                    ku[k] = notlast ? st.KU[e * S + s] : 0.0;
+                    lu[k] = notlast ? st.LU[e * S + s] : 0.0;
+                    su[k] = notlast ? st.TSU[tidx<NN>(q, e)] : 0.0;
+                }
+#pragma unroll
+                for (int k = 0; k < CH; ++k) {
+                    const int e = e0 + k;
+                    if (e >= NN) break;
+                    st.LD[e * S + s] = lin2(a0, kh[k], a1, ld[k]);
+                    st.SD[e * S + s] = sd[k];
+                    if (notlast) {
+                        st.LU[e * S + s] = lin2(a0, ku[k], a1, lu[k]);
+                        st.SU[e * S + s] = su[k];
+                    }
                 }
             }
-            for (int e = 0; e < n; ++e) st.mu[e * S + s] = st.Tmu[tidx<n>(q, e)];
+            double m[n];
+#pragma unroll
+            for (int e = 0; e < n; ++e) m[e] = st.Tmu[tidx<n>(q, e)];
+#pragma unroll
+            for (int e = 0; e < n; ++e) st.mu[e * S + s] = m[e];
         }
     }
     if (y == 0 && tid == 0) {
