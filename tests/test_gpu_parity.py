@@ -442,3 +442,37 @@ def test_trial_window_does_not_change_results(pg):
         for sa, sb in zip(states, ref[1]):
             for x, y in zip(sa, sb):
                 assert np.array_equal(x, y), (w, look, slots)
+
+
+def test_trial_windows_many_plans_and_exhausted_searches(pg):
+    # More plans than one window's workgroup budget, mixed step-size limits,
+    # and plans whose searches never pass (no step meets a tiny KL bound):
+    # windows of any width give the first passing step of the halving
+    # sequence and bitwise the same iterates, and exhausted searches report
+    # ENOCONV with the state kept.
+    probs = []
+    for k in range(70):
+        p = workloads.point2d_problem(100 + k, N=20 + (k % 5) * 5)
+        p["max_bisect"] = (3, 7, 12, 20)[k % 4]
+        if k % 9 == 0:
+            p["kl_bound"] = 1e-30
+        probs.append(p)
+    ref = None
+    for w, look, slots in ((1, 0, 1), (4, 0, 16), (8, 2, 64), (2, 1, 3)):
+        ctx = pg.pgvimp_create(probs, use_graph=True, trial_width=w, trial_lookahead=look, trial_slots=slots)
+        stats = [pg.pgvimp_prox_step(ctx, 1) for _ in range(4)]
+        states = [pg.pgvimp_get_state(ctx, k) for k in range(len(probs))]
+        for it in stats:
+            for k, s in it.items():
+                assert s["evals_total"] >= s["trials_total"]
+                if k % 9 == 0:
+                    assert s["status"] == pg.ENOCONV and s["trials"] == probs[k]["max_bisect"]
+        if ref is None:
+            ref = (stats, states)
+            continue
+        for a, b in zip(stats, ref[0]):
+            for k in a:
+                assert (a[k]["beta"], a[k]["trials"], a[k]["status"]) == (b[k]["beta"], b[k]["trials"], b[k]["status"])
+        for sa, sb in zip(states, ref[1]):
+            for x, y in zip(sa, sb):
+                assert np.array_equal(x, y), (w, look, slots)
