@@ -1177,22 +1177,41 @@ __global__ void __launch_bounds__(kTrialThreads) chain_kernel(DevState st, int m
     // precision to factor (K^-1 or the current Lambda) in chain order
     double* cD = prior ? st.cKD : st.cLD;
     double* cU = prior ? st.cKU : st.cLU;
+    const double* sD = prior ? st.KD : st.LD;
+    const double* sU = prior ? st.KU : st.LU;
     for (int i = tid; i < N; i += nt) {
         const int64_t s = off + i, q = coff + chain_pos(N, nseg, i);
-        for (int e = 0; e < NN; ++e) {
-            const double d = prior ? st.KD[e * S + s] : st.LD[e * S + s];
-            cD[tidx<NN>(q, e)] = d;
-            if (prior) st.LD[e * S + s] = d;
-            if (i < N - 1) {
-                const double u = prior ? st.KU[e * S + s] : st.LU[e * S + s];
-                cU[tidx<NN>(q, e)] = u;
-                if (prior) st.LU[e * S + s] = u;
-            } else {
-                cU[tidx<NN>(q, e)] = 0.0;  // the coupling after the chain's last state is a zero block
+        const bool notlast = i < N - 1;
+        for (int e0 = 0; e0 < NN; e0 += kCopyChunk<NN>) {
+            // every load of the chunk before its stores (see prep_kernel)
+            constexpr int CH = kCopyChunk<NN>;
+            double dv[CH], uv[CH];
+#pragma unroll
+            for (int k = 0; k < CH; ++k) {
+                const int e = min(e0 + k, NN - 1);
+                dv[k] = sD[e * S + s];
+                // the coupling after the chain's last state is a zero block
+                uv[k] = notlast ? sU[e * S + s] : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < CH; ++k) {
+                const int e = e0 + k;
+                if (e >= NN) break;
+                cD[tidx<NN>(q, e)] = dv[k];
+                cU[tidx<NN>(q, e)] = uv[k];
+                if (prior) {
+                    st.LD[e * S + s] = dv[k];
+                    if (notlast) st.LU[e * S + s] = uv[k];
+                }
             }
         }
-        if (mode == CHAIN_INIT)
-            for (int e = 0; e < n; ++e) st.crb[tidx<n>(q, e)] = st.eta[e * S + s];
+        if (mode == CHAIN_INIT) {
+            double r[n];
+#pragma unroll
+            for (int e = 0; e < n; ++e) r[e] = st.eta[e * S + s];
+#pragma unroll
+            for (int e = 0; e < n; ++e) st.crb[tidx<n>(q, e)] = r[e];
+        }
     }
     __syncthreads();
     if (half == 0) {
@@ -1220,14 +1239,33 @@ __global__ void __launch_bounds__(kTrialThreads) chain_kernel(DevState st, int m
     }
     for (int i = tid; i < N; i += nt) {
         const int64_t s = off + i, q = coff + chain_pos(N, nseg, i);
+        const bool notlast = i < N - 1;
         if (ok) {
-            for (int e = 0; e < NN; ++e) {
-                st.SD[e * S + s] = st.TSD[tidx<NN>(q, e)];
-                if (i < N - 1) st.SU[e * S + s] = st.TSU[tidx<NN>(q, e)];
+            for (int e0 = 0; e0 < NN; e0 += kCopyChunk<NN>) {
+                constexpr int CH = kCopyChunk<NN>;
+                double dv[CH], uv[CH];
+#pragma unroll
+                for (int k = 0; k < CH; ++k) {
+                    const int e = min(e0 + k, NN - 1);
+                    dv[k] = st.TSD[tidx<NN>(q, e)];
+                    uv[k] = notlast ? st.TSU[tidx<NN>(q, e)] : 0.0;
+                }
+#pragma unroll
+                for (int k = 0; k < CH; ++k) {
+                    const int e = e0 + k;
+                    if (e >= NN) break;
+                    st.SD[e * S + s] = dv[k];
+                    if (notlast) st.SU[e * S + s] = uv[k];
+                }
             }
         }
-        if (mode == CHAIN_INIT)
-            for (int e = 0; e < n; ++e) st.mu[e * S + s] = st.Tmu[tidx<n>(q, e)];
+        if (mode == CHAIN_INIT) {
+            double m[n];
+#pragma unroll
+            for (int e = 0; e < n; ++e) m[e] = st.Tmu[tidx<n>(q, e)];
+#pragma unroll
+            for (int e = 0; e < n; ++e) st.mu[e * S + s] = m[e];
+        }
     }
 }
 
