@@ -47,45 +47,71 @@ hipError_t launch_iteration(const DevState& st, int phw, int part, int round, hi
 // accepted step.  One block; plans are taken in chunks of 256, thread tid
 // owning plan chunk + tid.
 constexpr int kWindowThreads = 256;
+constexpr int kWindowPlansPerThread = 4;  // plans a thread keeps in registers between the passes
 __global__ void __launch_bounds__(kWindowThreads) window_kernel(DevState st, int phw, int round) {
     __shared__ int sh[kWindowThreads];
     __shared__ int total;
     const int tid = threadIdx.x;
     if (tid == 0) total = 0;
     __syncthreads();
+    // pass 1: which plans still search; every field a plan needs is loaded
+    // at once (no short-circuit chains of dependent loads)
+    int next[kWindowPlansPerThread], want[kWindowPlansPerThread];
     int mine = 0;
-    for (int pid = tid; pid < phw; pid += kWindowThreads) {
-        PlanDev& p = st.plans[pid];
-        int s = 0;
-        if (p.active && p.phase == 0) {
-            if (round == 0) {
-                p.wnext = 0;
-                p.firstpass = kNoPass;
-            }
-            s = p.firstpass == kNoPass && p.wnext < p.max_bisect;
-        }
-        p.wwidth = s;  // flag until the width is known
+#pragma unroll
+    for (int k = 0; k < kWindowPlansPerThread; ++k) {
+        const int pid = tid + k * kWindowThreads;
+        next[k] = 0;
+        want[k] = 0;
+        if (pid >= phw) continue;
+        const PlanDev& p = st.plans[pid];
+        const int active = p.active, phase = p.phase, fp = p.firstpass, wn = p.wnext, mb = p.max_bisect;
+        const int it = p.iters_done, tr = p.trials;
+        const int live = active != 0 && phase == 0;
+        next[k] = round == 0 ? 0 : wn;
+        const int s = live && (round == 0 || fp == kNoPass) && next[k] < mb;
+        // a plan's own cap: max_bisect, and in window 0 the lookahead cut
+        int cap = mb - next[k];
+        if (round == 0 && st.lookahead > 0 && it > 0) cap = min(cap, max(1, tr + st.lookahead));
+        want[k] = s ? cap : 0;
         mine += s;
+    }
+    // plans beyond the register-held ones are visited again in pass 2
+    for (int pid = tid + kWindowPlansPerThread * kWindowThreads; pid < phw; pid += kWindowThreads) {
+        const PlanDev& p = st.plans[pid];
+        const int fp = p.firstpass, wn = round == 0 ? 0 : p.wnext;
+        mine += p.active && p.phase == 0 && (round == 0 || fp == kNoPass) && wn < p.max_bisect;
     }
     atomicAdd(&total, mine);
     __syncthreads();
     const int width = max(st.Wmin, min(st.W, st.wbudget / max(total, 1)));
-    int base = 0;  // items of the plans before this chunk
-    for (int c0 = 0; c0 < phw; c0 += kWindowThreads) {
+    // pass 2: widths, then the work list in plan order (a block-wide scan per
+    // chunk of 256 plans)
+    int base = 0;
+    for (int c0 = 0, k = 0; c0 < phw; c0 += kWindowThreads, ++k) {
         const int pid = c0 + tid;
         int w = 0;
         if (pid < phw) {
             PlanDev& p = st.plans[pid];
-            if (p.wwidth) {
-                w = width;
-                if (round == 0 && st.lookahead > 0 && p.iters_done > 0) w = min(w, max(1, p.trials + st.lookahead));
-                w = min(w, p.max_bisect - p.wnext);
-                p.wstart = p.wnext;
-                p.wnext += w;
+            int nx, cap;
+            if (k < kWindowPlansPerThread) {
+                nx = next[k];
+                cap = want[k];
+            } else {
+                const int active = p.active, phase = p.phase, fp = p.firstpass, wn = p.wnext, mb = p.max_bisect;
+                const int it = p.iters_done, tr = p.trials;
+                nx = round == 0 ? 0 : wn;
+                const int s = active != 0 && phase == 0 && (round == 0 || fp == kNoPass) && nx < mb;
+                cap = mb - nx;
+                if (round == 0 && st.lookahead > 0 && it > 0) cap = min(cap, max(1, tr + st.lookahead));
+                cap = s ? cap : 0;
             }
+            w = min(width, cap);
+            if (round == 0 && p.active && p.phase == 0) p.firstpass = kNoPass;
+            p.wstart = nx;
+            p.wnext = nx + w;
             p.wwidth = w;
         }
-        // exclusive scan of the widths over the chunk (in plan order)
         __syncthreads();
         sh[tid] = w;
         __syncthreads();

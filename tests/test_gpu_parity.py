@@ -476,3 +476,29 @@ def test_trial_windows_many_plans_and_exhausted_searches(pg):
         for sa, sb in zip(states, ref[1]):
             for x, y in zip(sa, sb):
                 assert np.array_equal(x, y), (w, look, slots)
+
+
+def test_trial_windows_beyond_register_held_plans(pg):
+    # The window planner keeps the fields of up to 1024 plans in registers
+    # between its passes and re-reads the rest: 1030 small plans take both
+    # paths, and the chosen steps and iterates match one-step-at-a-time
+    # evaluation bitwise.
+    probs = []
+    for k in range(1030):
+        p = workloads.point2d_problem(3000 + k, N=8 + (k % 3))
+        p["max_bisect"] = (4, 9)[k % 2]
+        probs.append(p)
+    ref = None
+    for w, slots in ((1, 1), (8, 16)):
+        ctx = pg.pgvimp_create(probs, use_graph=True, trial_width=w, trial_slots=slots)
+        stats = [pg.pgvimp_prox_step(ctx, 1) for _ in range(2)]
+        states = [pg.pgvimp_get_state(ctx, k) for k in (0, 1, 1023, 1024, 1029)]
+        if ref is None:
+            ref = (stats, states)
+            continue
+        for a, b in zip(stats, ref[0]):
+            for k in a:
+                assert (a[k]["beta"], a[k]["trials"], a[k]["status"]) == (b[k]["beta"], b[k]["trials"], b[k]["status"])
+        for sa, sb in zip(states, ref[1]):
+            for x, y in zip(sa, sb):
+                assert np.array_equal(x, y), (w, slots)
