@@ -129,7 +129,8 @@ __global__ void __launch_bounds__(kWindowThreads) window_kernel(DevState st, int
 }
 
 hipError_t launch_window(const DevState& st, int phw, int round, hipStream_t s) {
-    if (phw <= 0) return hipSuccess;
+    // without a lookahead, window 0 is uniform and set by the prep kernel
+    if (phw <= 0 || (round == 0 && st.lookahead == 0)) return hipSuccess;
     hipLaunchKernelGGL(window_kernel, dim3(1), dim3(kWindowThreads), 0, s, st, phw, round);
     return hipGetLastError();
 }

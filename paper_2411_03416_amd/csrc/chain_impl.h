@@ -1383,16 +1383,35 @@ PG_UNROLL
     }
     ecol = block_sum(ecol, sh_d);
     epri = block_sum(epri, sh_d);
+    // Window 0 of the step sizes (no lookahead): the same width for every
+    // plan with an iteration to run, the compute units shared among them;
+    // wlist[0] = -width tells the trial kernel to take its items as
+    // (plan, slot) = (j / width, j % width).
+    int live = 0;
+    if (y == 0 && st.lookahead == 0)
+        for (int q = tid; q < (int)gridDim.x; q += kIterThreads) live += st.plans[q].active && st.plans[q].iters_left > 0;
+    const double nlive = (y == 0 && st.lookahead == 0) ? block_sum((double)live, sh_d) : 0.0;
     if (tid == 0) {
         st.psum[((int64_t)pid * nb + y) * 2 + 0] = ecol;
         st.psum[((int64_t)pid * nb + y) * 2 + 1] = epri;
-        if (y == 0) p.phase = 0;
+        if (y == 0) {
+            if (st.lookahead == 0) {
+                const int w0 = max(st.Wmin, min(st.W, st.wbudget / max((int)nlive, 1)));
+                p.wstart = 0;
+                p.wwidth = min(w0, p.max_bisect);
+                p.wnext = p.wwidth;
+                p.firstpass = kNoPass;
+                st.wlist[0] = -w0;  // the same value from every plan
+            }
+            p.phase = 0;
+        }
     }
 }
 
 // Part 2: one trial step size per workgroup, item j of the window's work
-// list (plan, slot): step size number wstart + slot of the plan's current
-// window.  Workgroup b runs on XCD b mod 8 and takes item
+// list (plan, slot), or of the uniform first window set by the prep kernel:
+// step size number wstart + slot of the plan's current window.  Workgroup b
+// runs on XCD b mod 8 and takes item
 // (b mod 8) * C + b / 8, C = ceil(items / 8): each XCD gets an equal run of
 // the plan-ordered list, so a plan's trials share one or two L2s.
 // For that step size:
@@ -1404,13 +1423,15 @@ PG_UNROLL
 // tr(Lambda' Sigma') = dim).  Results go to the trial slot (chain order) and
 // st.tres (passed, KL, log det, slot).
 template <int n>
-__global__ void __launch_bounds__(kTrialThreads) trial_kernel(DevState st) {
-    const int items = st.wlist[0];
+__global__ void __launch_bounds__(kTrialThreads) trial_kernel(DevState st, int phw) {
+    // work list, or (wlist[0] = -w) the uniform first window of width w
+    const int head = st.wlist[0];
+    const int items = head < 0 ? phw * -head : head;
     const int chunk = (items + kNumXcd - 1) / kNumXcd;
     const int kx = (int)blockIdx.x / kNumXcd;
     const int j = ((int)blockIdx.x % kNumXcd) * chunk + kx;
     if (kx >= chunk || j >= items) return;
-    const int item = st.wlist[1 + j];
+    const int item = head < 0 ? (j / -head) * 64 + j % -head : st.wlist[1 + j];
     __shared__ double sh_d[kChainThreads + 1];
     __shared__ int sh_i[kChainThreads + 1];
     __shared__ int sh_j[kChainThreads + 1];
@@ -1603,7 +1624,7 @@ hipError_t launch_iteration_n(const DevState& st, int phw, int part, int round, 
     if (part == 0) hipLaunchKernelGGL(prep_kernel<n>, it, dim3(kIterThreads), 0, s, st);
     if (part == 1) {
         const int64_t blocks = ((int64_t)phw * st.W + kNumXcd - 1) / kNumXcd * kNumXcd;
-        hipLaunchKernelGGL(trial_kernel<n>, dim3((unsigned)blocks), dim3(kTrialThreads), 0, s, st);
+        hipLaunchKernelGGL(trial_kernel<n>, dim3((unsigned)blocks), dim3(kTrialThreads), 0, s, st, phw);
     }
     if (part == 2) hipLaunchKernelGGL(select_kernel<n>, it, dim3(kIterThreads), 0, s, st, round);
     return hipGetLastError();
