@@ -1138,6 +1138,27 @@ __device__ __forceinline__ TS thread_ws(const DevState& st, int pid, int t) {
     double* base = st.tws + (((int64_t)pid * st.W + t) * kTrialThreads + threadIdx.x) * st.tws_stride;
     return TS{base, base + st.tws_stride, st.flags};
 }
+// Block temporaries of the chain and trial kernels in LDS (n = 6, plans of
+// at most kLdsWsSegments segments): a slice of STRIDE doubles per lane of
+// both halves, the stride odd so that the lanes of a wave spread over the
+// banks.  Lanes past the slices (they run no sweep and no reduced-chain
+// work) and plans of more segments keep their workspace slices in HBM.
+template <int n>
+struct LdsWs {
+    static constexpr bool value = n == 6;
+    static constexpr int STRIDE = (kTwsBlocks * n * n + kTwsVecs * n) | 1;
+    static constexpr int size = value ? 2 * kLdsWsSegments * STRIDE : 1;
+};
+template <int n>
+__device__ __forceinline__ TS chain_ws(const DevState& st, double* lds, int pid, int t, int half, int lane,
+                                       int nseg) {
+    if (LdsWs<n>::value && nseg <= kLdsWsSegments && lane < kLdsWsSegments) {
+        double* base = lds + (half * kLdsWsSegments + lane) * LdsWs<n>::STRIDE;
+        return TS{base, base + LdsWs<n>::STRIDE, st.flags};
+    }
+    return thread_ws<n>(st, pid, t);
+}
+
 // Sweep temporaries of one half for the chain range starting at position c0
 // (trial slot included): four tiled arrays of W * Sc positions each.
 template <int n>
@@ -1170,9 +1191,10 @@ __global__ void __launch_bounds__(kTrialThreads) chain_kernel(DevState st, int m
     const int N = p.N, nseg = p.nseg;
     const int64_t off = p.off, S = st.S, coff = p.coff;
     __shared__ double sg_lds[NodeLds<n>::size];
+    __shared__ double ws_lds[LdsWs<n>::size];
     double* sg = NodeLds<n>::value ? sg_lds + half * kMaxSeg * SegLayout<n, false>::STRIDE : seg_scratch<n>(st, pid, 0, half);
     const Ws ws = sweep_ws<n>(st, half, coff);
-    TS ts = thread_ws<n>(st, pid, 0);
+    TS ts = chain_ws<n>(st, ws_lds, pid, 0, half, lane, nseg);
     const bool prior = mode == CHAIN_INIT || mode == CHAIN_REINIT;
     // precision to factor (K^-1 or the current Lambda) in chain order
     double* cD = prior ? st.cKD : st.cLD;
@@ -1451,7 +1473,8 @@ __global__ void __launch_bounds__(kTrialThreads) trial_kernel(DevState st, int p
     __shared__ double sg_lds[NodeLds<n>::size + (NodeLds<n>::value ? kTrialLdsPad / 8 : 0)];
     double* sg = NodeLds<n>::value ? sg_lds + half * kMaxSeg * SegLayout<n, false>::STRIDE : seg_scratch<n>(st, pid, t, half);
     const Ws ws = sweep_ws<n>(st, half, c0);
-    TS ts = thread_ws<n>(st, pid, t);
+    __shared__ double ws_lds[LdsWs<n>::size];
+    TS ts = chain_ws<n>(st, ws_lds, pid, t, half, lane, nseg);
     double* res = st.tres + ((int64_t)pid * kMaxBisect + tt) * 4;
     const double beta = ldexp(p.beta_max, -tt);
     const double T = p.temperature;

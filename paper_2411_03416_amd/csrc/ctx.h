@@ -23,6 +23,9 @@ constexpr int kMaxGH = 10;        // Gauss-Hermite points per dimension
 // live blocks + the first coupling 1 + Cholesky inverse 2 = 18 (8 vectors);
 // segment backward sweep 16 blocks; mean-solve backward sweep 10 vectors.
 constexpr int kTwsBlocks = 20;
+// For n = 6, plans of at most this many segments keep the sweeps' block
+// temporaries in LDS (one slice per lane of both halves).
+constexpr int kLdsWsSegments = 12;
 constexpr int32_t kNoPass = 0x7fffffff;
 constexpr int kNumXcd = 8;  // XCDs; workgroup b of a launch runs on XCD b mod 8
 constexpr int kTwsVecs = 16;

@@ -56,13 +56,15 @@ def test_marginals_random_chain(pg, n, N):
     assert np.array_equal(mu2, mu) and np.array_equal(D2, D) and (N == 1 or np.array_equal(U2, U))
 
 
-def test_marginals_segment_counts_agree(pg):
+@pytest.mark.parametrize("n", [4, 6])
+def test_marginals_segment_counts_agree(pg, n):
+    # for n = 6, up to 12 segments keep the block temporaries in LDS, more in HBM
     rng = np.random.default_rng(7)
-    N, n = 200, 4
+    N = 200
     D, U = rand_chain(rng, N, n)
     Sr, Sor, ldr = gbp.gbp_marginals(D, U)
-    prob = workloads.free_problem(n_dof=2, N=N)
-    for seg in (1, 2, 5, 16, 33, 64):
+    prob = workloads.free_problem(n_dof=n // 2, N=N)
+    for seg in (1, 2, 5, 12, 13, 16, 33, 64):
         ctx = pg.pgvimp_create([prob], segments=seg, use_graph=False)
         pg.pgvimp_set_state(ctx, 0, np.zeros((N, n)), D, U)
         S, So, ld = pg.pgvimp_marginals(ctx, 0)
@@ -255,6 +257,28 @@ def test_prox_iteration_config0_fp64(pg):
         assert s["beta"] == so["beta"] and s["trials"] == so["trials"], it
         # the GPU may differ from the oracle by rounding (kappa eps per
         # iteration) amplified as the iteration amplifies it
+        assert rel(mu, st["mu"]) < max((it + 1) * tol, 100 * dmu_self), it
+        assert rel(D, st["D"]) < max((it + 1) * tol, 100 * dD_self), it
+
+
+@pytest.mark.parametrize("seg", [6, 12, 24])
+def test_prox_iteration_point3d_fp64(pg, seg):
+    # n = 6 iterations against the oracle, with the block temporaries of the
+    # sweeps in LDS (6, 12 segments) and in HBM (24 segments)
+    p = workloads.point3d_problem(4, N=60)
+    p["segments"] = seg
+    pri = prior.build_prior(p)
+    ref = _oracle_self_divergence(p, pri, 4)
+    ctx = pg.pgvimp_create([p], precision=pg.FP64, use_graph=False)
+    tol = fp64_tol(_kappa(pri))
+    for it, (st, so, dmu_self, dD_self, same) in enumerate(ref):
+        s = pg.pgvimp_prox_step(ctx, 1)[0]
+        mu, D, U = pg.pgvimp_get_state(ctx, 0)
+        print(seg, it, s["beta"], s["trials"], "gpu-oracle", rel(mu, st["mu"]), rel(D, st["D"]), flush=True)
+        if not same:
+            break
+        assert s["status"] == so["status"] == 0
+        assert s["beta"] == so["beta"] and s["trials"] == so["trials"], it
         assert rel(mu, st["mu"]) < max((it + 1) * tol, 100 * dmu_self), it
         assert rel(D, st["D"]) < max((it + 1) * tol, 100 * dD_self), it
 
