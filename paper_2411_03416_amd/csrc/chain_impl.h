@@ -1433,9 +1433,11 @@ PG_UNROLL
 // Part 2: one trial step size per workgroup, item j of the window's work
 // list (plan, slot), or of the uniform first window set by the prep kernel:
 // step size number wstart + slot of the plan's current window.  Workgroup b
-// runs on XCD b mod 8 and takes item
-// (b mod 8) * C + b / 8, C = ceil(items / 8): each XCD gets an equal run of
-// the plan-ordered list, so a plan's trials share one or two L2s.
+// runs on XCD b mod 8.  From a list it takes item (b mod 8) * C + b / 8,
+// C = ceil(items / 8): each XCD gets an equal run of the plan-ordered list,
+// so a plan's trials share one or two L2s.  In the uniform window, plan q
+// runs on XCD q mod 8 (live plans spread over the XCDs even when they hold
+// neighbouring slots of a larger context).
 // For that step size:
 //   Lambda' = (beta (K^-1 + H) + Lambda_k) / (beta T + 1)  -> marginals, log det, PD
 //   (K^-1 + Lambda_k / beta) mu' = eta - g + Lambda_k mu_k / beta
@@ -1448,12 +1450,21 @@ template <int n>
 __global__ void __launch_bounds__(kTrialThreads) trial_kernel(DevState st, int phw) {
     // work list, or (wlist[0] = -w) the uniform first window of width w
     const int head = st.wlist[0];
-    const int items = head < 0 ? phw * -head : head;
-    const int chunk = (items + kNumXcd - 1) / kNumXcd;
-    const int kx = (int)blockIdx.x / kNumXcd;
-    const int j = ((int)blockIdx.x % kNumXcd) * chunk + kx;
-    if (kx >= chunk || j >= items) return;
-    const int item = head < 0 ? (j / -head) * 64 + j % -head : st.wlist[1 + j];
+    const int kx = (int)blockIdx.x / kNumXcd, x = (int)blockIdx.x % kNumXcd;
+    int item;
+    if (head < 0) {
+        // plan q on XCD q mod 8 with its w slots together, whichever plan
+        // slots are live
+        const int w = -head, q = x + kNumXcd * (kx / w);
+        if (q >= phw) return;
+        item = q * 64 + kx % w;
+    } else {
+        const int items = head;
+        const int chunk = (items + kNumXcd - 1) / kNumXcd;
+        const int j = x * chunk + kx;
+        if (kx >= chunk || j >= items) return;
+        item = st.wlist[1 + j];
+    }
     __shared__ double sh_d[kChainThreads + 1];
     __shared__ int sh_i[kChainThreads + 1];
     __shared__ int sh_j[kChainThreads + 1];
@@ -1646,7 +1657,8 @@ hipError_t launch_iteration_n(const DevState& st, int phw, int part, int round, 
     const dim3 it(phw, st.iter_blocks);
     if (part == 0) hipLaunchKernelGGL(prep_kernel<n>, it, dim3(kIterThreads), 0, s, st);
     if (part == 1) {
-        const int64_t blocks = ((int64_t)phw * st.W + kNumXcd - 1) / kNumXcd * kNumXcd;
+        // covers a list of up to phw * W items and the uniform window
+        const int64_t blocks = (int64_t)((phw + kNumXcd - 1) / kNumXcd) * kNumXcd * st.W;
         hipLaunchKernelGGL(trial_kernel<n>, dim3((unsigned)blocks), dim3(kTrialThreads), 0, s, st, phw);
     }
     if (part == 2) hipLaunchKernelGGL(select_kernel<n>, it, dim3(kIterThreads), 0, s, st, round);
