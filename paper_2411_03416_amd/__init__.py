@@ -158,10 +158,11 @@ class Context:
             pass
 
 
-def pgvimp_arena_bytes(n, max_plans, max_states, heap_bytes, trial_width=0):
+def pgvimp_arena_bytes(n, max_plans, max_states, heap_bytes, trial_width=0, trial_slots=0):
     cfg = _abi.EngineCfg()
     cfg.n, cfg.max_plans, cfg.max_states, cfg.heap_bytes = n, max_plans, max_states, heap_bytes
     cfg.trial_width = trial_width
+    cfg.trial_slots = trial_slots
     return int(_abi.load().pgvimp_arena_bytes(C.byref(cfg)))
 
 

@@ -410,6 +410,23 @@ def test_add_remove_plans_reuses_slots(pg):
             assert np.array_equal(x, y)
 
 
+@pytest.mark.parametrize("use_graph", [1, 2])
+def test_sparse_live_plans_equal_plans_alone(pg, use_graph):
+    # live plans with empty slots between them in a larger context (the
+    # serving layout; use_graph = 2 sizes the graph to every slot): each
+    # equals the same plan solved alone, bitwise
+    probs = [workloads.point2d_problem(40 + k, N=20 + 7 * k) for k in range(9)]
+    ctx = pg.pgvimp_create(probs, max_plans=24, max_states=2000, use_graph=use_graph)
+    for k in (0, 2, 3, 5, 8):
+        pg.pgvimp_remove_plan(ctx, k)
+    pg.pgvimp_prox_step(ctx, 4)
+    for k in (1, 4, 6, 7):
+        alone = pg.pgvimp_create([probs[k]], use_graph=True)
+        pg.pgvimp_prox_step(alone, 4)
+        for x, y in zip(pg.pgvimp_get_state(alone, 0), pg.pgvimp_get_state(ctx, k)):
+            assert np.array_equal(x, y), (use_graph, k)
+
+
 def test_invalid_problems_are_rejected(pg):
     p = workloads.point2d_problem(0, N=10)
     for bad in (dict(p, N=0), dict(p, dt=-1.0), dict(p, Sig_start=-np.eye(4)), dict(p, gh_points=9),
