@@ -23,12 +23,12 @@ constexpr int kMaxGH = 10;        // Gauss-Hermite points per dimension
 // live blocks + the first coupling 1 + Cholesky inverse 2 = 18 (8 vectors);
 // segment backward sweep 16 blocks; mean-solve backward sweep 10 vectors.
 constexpr int kTwsBlocks = 20;
+constexpr int kTwsVecs = 16;
 // For n = 6, plans of at most this many segments keep the sweeps' block
 // temporaries in LDS (one slice per lane of both halves).
 constexpr int kLdsWsSegments = 12;
 constexpr int32_t kNoPass = 0x7fffffff;
 constexpr int kNumXcd = 8;  // XCDs; workgroup b of a launch runs on XCD b mod 8
-constexpr int kTwsVecs = 16;
 
 // Per-plan parameters and statistics, read by every kernel.  One entry per
 // plan slot; an empty slot has active = 0.
@@ -88,12 +88,13 @@ struct DevState {
     // trial iterates in chain order: W slots, slot t of position q at t * Sc + q
     // (stride W * Sc)
     double *Tmu, *TSD, *TSU;
-    double* tres;  // per (plan, step size number < kMaxBisect): passed, KL, log det, beta
+    double* tres;  // per (plan, step size number < kMaxBisect): passed, KL, log det, trial slot
     int32_t W;     // trial slots per plan = the widest window of step sizes
     int32_t Wmin;  // the narrowest window (trial_width)
     int32_t wbudget;      // trial workgroups a window may start at once (compute units)
     // work list of the current window: [0] = item count, then one item per
-    // trial workgroup, plan * 64 + slot, plan by plan
+    // trial workgroup, plan * 64 + slot, plan by plan; [0] = -w marks the
+    // uniform first window of width w (items decoded from the workgroup)
     int32_t* wlist;
     int32_t iter_blocks;  // blocks per plan of the prep and select kernels
     int32_t lookahead;    // first-window lookahead (0 = full first window)
@@ -183,7 +184,7 @@ hipError_t launch_prior_build(const DevState& st, int plan_lo, int plan_hi, int 
 hipError_t launch_prior_assemble(const DevState& st, int plan_lo, int plan_hi, int maxN, hipStream_t s);
 hipError_t launch_chain(const DevState& st, int mode, int plan_lo, int plan_hi, hipStream_t s);
 // parts of one proximal iteration for plans [0, phw): 0 = prep, 1 = trial
-// window `round`, 2 = select for window `round`
+// (each plan's current window), 2 = select
 hipError_t launch_iteration(const DevState& st, int phw, int part, int round, hipStream_t s);
 // Window `round` of step sizes of the current iteration for plans [0, phw).
 hipError_t launch_window(const DevState& st, int phw, int round, hipStream_t s);
