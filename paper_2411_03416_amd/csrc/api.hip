@@ -782,6 +782,12 @@ static int plan_high_water(pgvimp_ctx* c) {
     return hw;
 }
 
+static int active_plans(pgvimp_ctx* c) {
+    int a = 0;
+    for (auto& ph : c->plans) a += ph.active ? 1 : 0;
+    return a;
+}
+
 static int max_live_N(pgvimp_ctx* c) {
     int m = 0;
     for (auto& ph : c->plans)
@@ -848,7 +854,12 @@ static int enqueue_iters(pgvimp_ctx* c, int n_iters, const std::vector<ClassKey>
         for (int r = 0; r < rounds; ++r) {
             HCK(c, launch_window(c->st, phw, r, c->stream));
             if ((rc = begin(PGVIMP_K_TRIAL))) return rc;
-            HCK(c, launch_iteration(c->st, phw, 1, r, c->stream));
+            // the first window of a batch larger than the chip may pair
+            // workgroups on a CU (not for capacity-sized serving graphs,
+            // where the live plans are unknown when the graph is captured)
+            const bool pair = r == 0 && c->cfg.use_graph != 2 && c->st.lookahead == 0 &&
+                              (int64_t)active_plans(c) * c->st.Wmin > c->st.wbudget;
+            HCK(c, launch_iteration(c->st, phw, pair ? 5 : 1, r, c->stream));
             if ((rc = end())) return rc;
         }
         if ((rc = begin(PGVIMP_K_SELECT))) return rc;

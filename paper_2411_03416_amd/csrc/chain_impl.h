@@ -1445,8 +1445,8 @@ PG_UNROLL
 //                        + log det Lambda' - log det Lambda_k]
 // (the trace term uses Lambda_k = (beta T + 1) Lambda' - beta (K^-1 + H) and
 // tr(Lambda' Sigma') = dim).  Results go to the trial slot (chain order) and
-// st.tres (passed, KL, log det, slot).
-template <int n>
+// st.tres (passed, KL, log det, slot).  PAD: see the node scratch below.
+template <int n, bool PAD>
 __global__ void __launch_bounds__(kTrialThreads) trial_kernel(DevState st, int phw) {
     // work list, or (wlist[0] = -w) the uniform first window of width w
     const int head = st.wlist[0];
@@ -1478,10 +1478,11 @@ __global__ void __launch_bounds__(kTrialThreads) trial_kernel(DevState st, int p
     const int N = p.N, nseg = p.nseg;
     const int64_t coff = p.coff, c0 = (int64_t)t * st.Sc + coff;
     // With LDS node scratch a trial workgroup takes just under half a CU's
-    // LDS; kTrialLdsPad unused bytes keep it to one workgroup per CU.  Two
-    // per CU run each other ~1.45x slower, and the dispatcher pairs them up
-    // even in windows smaller than the chip.
-    __shared__ double sg_lds[NodeLds<n>::size + (NodeLds<n>::value ? kTrialLdsPad / 8 : 0)];
+    // LDS; with PAD, kTrialLdsPad unused bytes keep it to one workgroup per
+    // CU.  Two per CU run each other ~1.5x slower, and the dispatcher pairs
+    // them up even in windows smaller than the chip; only windows of more
+    // workgroups than CUs gain from pairs (1.12x the throughput).
+    __shared__ double sg_lds[NodeLds<n>::size + (NodeLds<n>::value && PAD ? kTrialLdsPad / 8 : 0)];
     double* sg = NodeLds<n>::value ? sg_lds + half * kMaxSeg * SegLayout<n, false>::STRIDE : seg_scratch<n>(st, pid, t, half);
     const Ws ws = sweep_ws<n>(st, half, c0);
     __shared__ double ws_lds[LdsWs<n>::size];
@@ -1650,16 +1651,20 @@ hipError_t launch_chain_n(const DevState& st, int mode, int lo, int hi, hipStrea
     return hipGetLastError();
 }
 
-// part: 0 = prep, 1 = trial (each plan's current window), 2 = select
+// part: 0 = prep, 1 = trial (each plan's current window), 2 = select,
+// 5 = trial allowing two workgroups per CU (windows larger than the chip)
 template <int n>
 hipError_t launch_iteration_n(const DevState& st, int phw, int part, int round, hipStream_t s) {
     if (phw <= 0) return hipSuccess;
     const dim3 it(phw, st.iter_blocks);
     if (part == 0) hipLaunchKernelGGL(prep_kernel<n>, it, dim3(kIterThreads), 0, s, st);
-    if (part == 1) {
+    if (part == 1 || part == 5) {
         // covers a list of up to phw * W items and the uniform window
         const int64_t blocks = (int64_t)((phw + kNumXcd - 1) / kNumXcd) * kNumXcd * st.W;
-        hipLaunchKernelGGL(trial_kernel<n>, dim3((unsigned)blocks), dim3(kTrialThreads), 0, s, st, phw);
+        if (part == 5 && NodeLds<n>::value)
+            hipLaunchKernelGGL((trial_kernel<n, false>), dim3((unsigned)blocks), dim3(kTrialThreads), 0, s, st, phw);
+        else
+            hipLaunchKernelGGL((trial_kernel<n, true>), dim3((unsigned)blocks), dim3(kTrialThreads), 0, s, st, phw);
     }
     if (part == 2) hipLaunchKernelGGL(select_kernel<n>, it, dim3(kIterThreads), 0, s, st, round);
     return hipGetLastError();
