@@ -1222,6 +1222,9 @@ __global__ void __launch_bounds__(kTrialThreads) chain_kernel(DevState st, int m
                 cD[tidx<NN>(q, e)] = dv[k];
                 cU[tidx<NN>(q, e)] = uv[k];
                 if (prior) {
+                    // K^-1 + H outside the collision blocks: K^-1 until the
+                    // next prior build (prep writes the collision blocks)
+                    st.cKH[tidx<NN>(q, e)] = dv[k];
                     st.LD[e * S + s] = dv[k];
                     if (notlast) st.LU[e * S + s] = uv[k];
                 }
@@ -1322,34 +1325,33 @@ __global__ void __launch_bounds__(kIterThreads) prep_kernel(DevState st) {
         const bool act = coll_active<n>(p, i);
         const bool notlast = i < N - 1;
         // Each group's loads come before its stores (the stores go to other
-        // arrays, but the compiler cannot know that): block copies, then the
-        // right-hand side eta - g and Lambda_k mu_k, then the prior costs.
+        // arrays, but the compiler cannot know that): Lambda_k's blocks and
+        // the collision blocks of K^-1 + H, then the right-hand side eta - g
+        // and Lambda_k mu_k, then the prior costs.  K^-1 itself and K^-1 + H
+        // outside the collision blocks are written by the set-up chain kernel
+        // after every prior build (K^-1 does not change between builds).
         for (int e0 = 0; e0 < NN; e0 += kCopyChunk<NN>) {
             constexpr int CH = kCopyChunk<NN>;
-            double kd[CH], kh[CH], ld[CH], ku[CH], lu[CH];
+            double kh[CH], ld[CH], lu[CH];
+            bool ce[CH];
 #pragma unroll
             for (int k = 0; k < CH; ++k) {
                 const int e = min(e0 + k, NN - 1);
-                kd[k] = st.KD[e * S + s];
                 ld[k] = st.LD[e * S + s];
                 // the coupling after the chain's last state is a zero block
-                ku[k] = notlast ? st.KU[e * S + s] : 0.0;
                 lu[k] = notlast ? st.LU[e * S + s] : 0.0;
-                kh[k] = kd[k];
-                if (act) {  // collision Hessian on the collision coordinates
-                    const int a = coll_slot(p, e / n), b2 = coll_slot(p, e % n);
-                    if (a >= 0 && b2 >= 0) kh[k] += st.Hcol[(a * d + b2) * S + s];
-                }
+                // collision Hessian on the collision coordinates
+                const int a = coll_slot(p, e / n), b2 = coll_slot(p, e % n);
+                ce[k] = act && a >= 0 && b2 >= 0;
+                kh[k] = ce[k] ? st.KD[e * S + s] + st.Hcol[(a * d + b2) * S + s] : 0.0;
             }
 #pragma unroll
             for (int k = 0; k < CH; ++k) {
                 const int e = e0 + k;
                 if (e >= NN) break;
                 const int64_t qe = tidx<NN>(q, e);
-                st.cKD[qe] = kd[k];
-                st.cKH[qe] = kh[k];
+                if (ce[k]) st.cKH[qe] = kh[k];
                 st.cLD[qe] = ld[k];
-                st.cKU[qe] = ku[k];
                 st.cLU[qe] = lu[k];
             }
         }
