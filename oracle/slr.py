@@ -66,11 +66,12 @@ def linearised_problem(prob, A_t, a_t):
     return q
 
 
-def run_ipgvimp(prob, n_rounds=None, n_iters=None, history=False):
+def run_ipgvimp(prob, n_rounds=None, n_iters=None, history=False, drift=None):
     """Alg. 2: alternate SLR and P-GVIMP; returns the final state and the
     list of (A_t, a_t) per round (with history=True, (A_t, a_t, state after
-    the round's iterations) per round)."""
-    f = lambda x: quadrotor_drift(x, prob["quad"])  # noqa: E731
+    the round's iterations) per round).  drift (a callable on [K, n] points)
+    replaces the quadrotor drift of the problem when given."""
+    f = drift if drift is not None else (lambda x: quadrotor_drift(x, prob["quad"]))  # noqa: E731
     mu = np.array(prob["nominal_mean"], dtype=np.float64)
     Sig = np.array(prob["nominal_cov"], dtype=np.float64)
     n_rounds = prob["n_rounds"] if n_rounds is None else n_rounds

@@ -419,6 +419,63 @@ def affine_sdf_problem(slope=(0.25, -0.125), offset=2.0, N=10, kappa_eps=10.0,
     return p
 
 
+def affine_grid_3d(slope, offset, g, cell):
+    """float32 [g,g,g] grid (z, y, x) of the affine field slope . x + offset at
+    nodes cell * (ix, iy, iz); dyadic slope, offset and cell keep every value
+    exact in FP32, and trilinear interpolation reproduces the field."""
+    xs = cell * np.arange(g, dtype=np.float64)
+    Z, Y, X = np.meshgrid(xs, xs, xs, indexing="ij")
+    f = slope[0] * X + slope[1] * Y + slope[2] * Z + offset
+    grid = f.astype(np.float32)
+    assert np.array_equal(grid.astype(np.float64), f)
+    return grid
+
+
+def affine_sdf3_problem(slope=(0.25, -0.125, 0.5), offset=2.0, N=10, kappa_eps=10.0,
+                        weight=1.0, gh_points=3, seed=0):
+    """3-D point robot (n = 6) over an affine SDF on a 64^3 dyadic grid
+    (cell 0.125, an 8 m cube).  With a huge hinge margin every hinge term is
+    active and the collision cost is an exact quadratic in the position."""
+    rng = _rng(seed)
+    A, a, B = double_integrator(3)
+    s = np.concatenate([rng.uniform(2.0, 2.5, size=3), np.zeros(3)])
+    t = np.concatenate([rng.uniform(5.5, 6.0, size=3), np.zeros(3)])
+    p = _base(6, 3, N, 0.1, A, a, B, 0.8 * np.eye(3), s, t)
+    p.update({
+        "coll_kind": "point3d", "coll_index": np.array([0, 1, 2], dtype=np.int32),
+        "gh_points": gh_points, "sdf": affine_grid_3d(slope, offset, 64, 0.125),
+        "origin": np.zeros(3), "cell": 0.125, "hinge_eps": kappa_eps,
+        "obs_weight": weight, "sphere_radius": np.zeros(1),
+        "affine": (np.array(slope, dtype=np.float64), float(offset)), "seed": seed,
+    })
+    return p
+
+
+def arm_affine_problem(slope=(0.25, -0.125, 0.5), offset=2.0, N=6, kappa_eps=10.0,
+                       weight=1.0, gh_points=2, seed=0):
+    """7-DOF arm over an affine SDF on a 48^3 dyadic grid (cell 0.125, a 6 m
+    cube), base at its centre, seven links of 0.25 m (reach 1.75 m, so every
+    sphere stays inside the grid for any joint angles), twenty spheres of
+    distinct radii 0.02 + 0.01 s.  Every hinge is active."""
+    rng = _rng(seed)
+    chain = arm_chain(rng)
+    chain["base"] = np.array([3.0, 3.0, 3.0])
+    chain["link_len"] = np.full(ARM_DOF, 0.25)
+    q0 = rng.uniform(-1.0, 1.0, size=ARM_DOF)
+    q1 = rng.uniform(-1.0, 1.0, size=ARM_DOF)
+    A, a, B = double_integrator(ARM_DOF)
+    p = _base(14, 7, N, 0.1, A, a, B, 0.8 * np.eye(7),
+              np.concatenate([q0, np.zeros(7)]), np.concatenate([q1, np.zeros(7)]))
+    p.update({
+        "coll_kind": "arm3d", "coll_index": np.arange(7, dtype=np.int32),
+        "gh_points": gh_points, "sdf": affine_grid_3d(slope, offset, 48, 0.125),
+        "origin": np.zeros(3), "cell": 0.125, "hinge_eps": kappa_eps,
+        "obs_weight": weight, "sphere_radius": 0.02 + 0.01 * np.arange(20),
+        "fk": chain, "affine": (np.array(slope, dtype=np.float64), float(offset)), "seed": seed,
+    })
+    return p
+
+
 def serving_mix(seed=0, count=100, qps=50.0, n_range=(50, 1000)):
     """Request stream: Poisson arrivals, each drawing a config 0..3 shape.
 
