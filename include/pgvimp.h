@@ -218,15 +218,6 @@ int pgvimp_remove_plan(pgvimp_ctx *ctx, int32_t plan);
 int pgvimp_marginals(pgvimp_ctx *ctx, int32_t plan, double *cov_diag, double *cov_off, double *logdet);
 
 /*
- * Per-factor expectations at the plan's current (mu, marginals):
- * E_coll [N] = E[psi_i]; grad [N][n] = Sigma_i^-1 E[(x - mu_i) psi_i];
- * hess [N][n][n] = 2 grad_Sigma = Sigma_i^-1 (E[(x-mu)(x-mu)^T psi] -
- * E[psi] Sigma_i) Sigma_i^-1 (Sec. 4.1 eq. gradients_psid), embedded with
- * zeros outside the configuration coordinates; E_prior [N+1] = closed-form
- * expected prior factor costs 1/2 E[r^T W r] ordered (start, transitions
- * 0..N-2, goal).  Any output pointer may be NULL.
- */
-/*
  * Evaluate the collision-factor expectations (Sec. 4.1 eq. gradients_psid,
  * Sec. 4.3) of every live plan at its current mean and marginals, reps >= 1
  * times, leaving them on the device (no readback; the results are the ones
@@ -236,6 +227,15 @@ int pgvimp_marginals(pgvimp_ctx *ctx, int32_t plan, double *cov_diag, double *co
  */
 int pgvimp_expect_all(pgvimp_ctx *ctx, int32_t reps);
 
+/*
+ * Per-factor expectations at the plan's current (mu, marginals):
+ * E_coll [N] = E[psi_i]; grad [N][n] = Sigma_i^-1 E[(x - mu_i) psi_i];
+ * hess [N][n][n] = 2 grad_Sigma = Sigma_i^-1 (E[(x-mu)(x-mu)^T psi] -
+ * E[psi] Sigma_i) Sigma_i^-1 (Sec. 4.1 eq. gradients_psid), embedded with
+ * zeros outside the configuration coordinates; E_prior [N+1] = closed-form
+ * expected prior factor costs 1/2 E[r^T W r] ordered (start, transitions
+ * 0..N-2, goal).  Any output pointer may be NULL.
+ */
 int pgvimp_factor_expectations(pgvimp_ctx *ctx, int32_t plan, double *E_coll, double *grad,
                                double *hess, double *E_prior);
 
@@ -267,6 +267,26 @@ int pgvimp_solve(pgvimp_ctx *ctx, int32_t n_iters, pgvimp_stats *per_plan);
  */
 int pgvimp_slr_linearize(pgvimp_ctx *ctx, int32_t plan, int32_t model, const double *model_params,
                          int32_t gh_points, int32_t rebuild_prior, double *A_out, double *a_out);
+
+/*
+ * One round of Alg. 2 (i-P-GVIMP): statistical linearisation of the model's
+ * drift (Sec. 6.2, as pgvimp_slr_linearize with rebuild_prior = 1), then the
+ * plan's iteration budget is set to n_iters, so the next pgvimp_prox_step
+ * calls run the round's P-GVIMP iterations (Alg. 1) on the rebuilt LTV
+ * prior.  The first round passes the nominal trajectory: nominal_mean
+ * [N][n] and per-state covariances nominal_cov [N][n][n] (host, SPD); they
+ * become the plan's mean and marginals before the regression, and the mean
+ * is kept when the precision restarts from the new K^-1.  Later rounds pass
+ * NULL for both and linearise about the plan's current marginals.  A_out
+ * and a_out as in pgvimp_slr_linearize (either may be NULL).  Errors: EINVAL
+ * (only one of the nominal arrays given, a non-finite value, a covariance
+ * block that is not SPD, n_iters < 0, a model the context's n does not
+ * fit; the plan is unchanged), ENOTPD (the linearised prior is not positive
+ * definite), EDEVICE.
+ */
+int pgvimp_slr_round(pgvimp_ctx *ctx, int32_t plan, int32_t model, const double *model_params,
+                     int32_t gh_points, const double *nominal_mean, const double *nominal_cov,
+                     int32_t n_iters, double *A_out, double *a_out);
 
 /* Read the plan's mean [N][n] and precision blocks D [N][n][n], U [N-1][n][n]. */
 int pgvimp_get_state(pgvimp_ctx *ctx, int32_t plan, double *mu, double *prec_diag, double *prec_off);

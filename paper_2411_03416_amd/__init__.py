@@ -21,7 +21,7 @@ __all__ = [
     "pgvimp_marginals", "pgvimp_factor_expectations", "pgvimp_prox_step", "pgvimp_solve", "pgvimp_slr_linearize",
     "pgvimp_get_state", "pgvimp_set_state", "pgvimp_set_budget", "pgvimp_kernel_times", "pgvimp_profile",
     "pgvimp_launch_shape", "pgvimp_arena_bytes", "problem_struct", "library_path", "ipgvimp_begin",
-    "ipgvimp_next_round", "pgvimp_expect_all",
+    "ipgvimp_next_round", "pgvimp_expect_all", "pgvimp_slr_round",
 ]
 
 _KIND = {"none": COLL_NONE, "point2d": COLL_POINT2D, "point3d": COLL_POINT3D, "arm3d": COLL_ARM3D}
@@ -297,30 +297,36 @@ def pgvimp_slr_linearize(ctx, plan, gravity=9.81, gh_points=3, rebuild_prior=Tru
     return A, a
 
 
-def ipgvimp_begin(ctx, plan, prob):
-    """First round of Alg. 2 for a nonlinear plan: linearise the drift about
-    the nominal trajectory (mean prob['nominal_mean'], covariance
-    prob['nominal_cov'] per state), rebuild the prior, restart the precision
-    from the new K^-1 keeping the nominal mean, and give the plan its
-    iteration budget.  Returns (A_t, a_t)."""
+def pgvimp_slr_round(ctx, plan, gravity=9.81, gh_points=3, n_iters=0, nominal_mean=None, nominal_cov=None):
+    """One round of Alg. 2 in the library (see pgvimp_slr_round in
+    include/pgvimp.h); returns (A_t, a_t)."""
     N, n = ctx.plan_N[plan], ctx.n
-    cov = np.asarray(prob["nominal_cov"], dtype=np.float64).reshape(N, n, n)
-    prec = np.linalg.inv(cov)
-    pgvimp_set_state(ctx, plan, prob["nominal_mean"], prec, np.zeros((max(N - 1, 0), n, n)))
-    A, a = pgvimp_slr_linearize(ctx, plan, gravity=prob["quad"]["gravity"], gh_points=prob.get("slr_points", 3),
-                                rebuild_prior=True)
-    pgvimp_set_budget(ctx, plan, int(prob["n_iters"]))
+    A = np.zeros((N, n, n))
+    a = np.zeros((N, n))
+    prm = np.array([gravity], dtype=np.float64)
+    m = c = None
+    if nominal_mean is not None:
+        m = np.ascontiguousarray(nominal_mean, dtype=np.float64).reshape(N, n)
+        c = np.ascontiguousarray(nominal_cov, dtype=np.float64).reshape(N, n, n)
+    _check(_abi.load().pgvimp_slr_round(ctx.handle, plan, _abi.MODEL_QUAD2D, _dptr(prm), gh_points,
+                                        None if m is None else m.ctypes.data, None if c is None else c.ctypes.data,
+                                        int(n_iters), A.ctypes.data, a.ctypes.data), ctx.handle)
     return A, a
+
+
+def ipgvimp_begin(ctx, plan, prob):
+    """First round of Alg. 2 for a nonlinear plan: pgvimp_slr_round about the
+    nominal trajectory (prob['nominal_mean'], prob['nominal_cov'])."""
+    return pgvimp_slr_round(ctx, plan, gravity=prob["quad"]["gravity"], gh_points=prob.get("slr_points", 3),
+                            n_iters=int(prob["n_iters"]), nominal_mean=prob["nominal_mean"],
+                            nominal_cov=prob["nominal_cov"])
 
 
 def ipgvimp_next_round(ctx, plan, prob):
-    """Later rounds of Alg. 2: linearise about the plan's current marginals,
-    rebuild the prior (precision restarts from K^-1, mean kept) and reset the
-    iteration budget."""
-    A, a = pgvimp_slr_linearize(ctx, plan, gravity=prob["quad"]["gravity"], gh_points=prob.get("slr_points", 3),
-                                rebuild_prior=True)
-    pgvimp_set_budget(ctx, plan, int(prob["n_iters"]))
-    return A, a
+    """Later rounds of Alg. 2: pgvimp_slr_round about the plan's current
+    marginals."""
+    return pgvimp_slr_round(ctx, plan, gravity=prob["quad"]["gravity"], gh_points=prob.get("slr_points", 3),
+                            n_iters=int(prob["n_iters"]))
 
 
 def pgvimp_get_state(ctx, plan):

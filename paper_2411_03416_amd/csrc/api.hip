@@ -1088,6 +1088,40 @@ int pgvimp_slr_linearize(pgvimp_ctx* c, int32_t plan, int32_t model, const doubl
     return PGVIMP_OK;
 }
 
+int pgvimp_slr_round(pgvimp_ctx* c, int32_t plan, int32_t model, const double* model_params, int32_t gh_points,
+                     const double* nominal_mean, const double* nominal_cov, int32_t n_iters, double* A_out,
+                     double* a_out) {
+    if (!plan_ok(c, plan)) return PGVIMP_EINVAL;
+    if (n_iters < 0) FAIL(c, PGVIMP_EINVAL, "negative iteration budget");
+    if ((nominal_mean == nullptr) != (nominal_cov == nullptr))
+        FAIL(c, PGVIMP_EINVAL, "the nominal mean and covariance are given together");
+    HCK(c, hipSetDevice(c->cfg.device));
+    const int N = c->plans[plan].N, n = c->n;
+    if (nominal_mean) {
+        // the first round linearises about the nominal N(xbar_i, Sigbar_i):
+        // it becomes the plan's mean and marginals before the regression
+        const size_t nm = (size_t)N * n, nd = (size_t)N * n * n;
+        if (!finite_all(nominal_mean, nm) || !finite_all(nominal_cov, nd))
+            FAIL(c, PGVIMP_EINVAL, "non-finite nominal trajectory");
+        for (int i = 0; i < N; ++i)
+            if (!host_spd(nominal_cov + (size_t)i * n * n, n))
+                FAIL(c, PGVIMP_EINVAL, "nominal covariance of state %d is not symmetric positive definite", i);
+        int rc = ensure_stage(c, (nm + nd) * 8);
+        if (rc) return rc;
+        HCK(c, hipMemcpyAsync(c->stage, nominal_mean, nm * 8, hipMemcpyHostToDevice, c->stream));
+        HCK(c, hipMemcpyAsync(c->stage + nm, nominal_cov, nd * 8, hipMemcpyHostToDevice, c->stream));
+        HCK(c, launch_scatter(c->st, G_MU, plan, N, c->stage, c->stream));
+        HCK(c, launch_scatter(c->st, G_SD, plan, N, c->stage + nm, c->stream));
+        HCK(c, hipStreamSynchronize(c->stream));
+    }
+    int rc = pgvimp_slr_linearize(c, plan, model, model_params, gh_points, 1, A_out, a_out);
+    if (rc) return rc;
+    c->pdev[plan].iters_left = n_iters;
+    if ((rc = upload_plan(c, plan))) return rc;
+    HCK(c, hipStreamSynchronize(c->stream));
+    return PGVIMP_OK;
+}
+
 int pgvimp_launch_shape(pgvimp_ctx* c, int32_t N, int32_t* segments, int32_t* lanes) {
     if (!c || N < 1) return PGVIMP_EINVAL;
     if (segments) {

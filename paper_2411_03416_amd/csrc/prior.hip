@@ -329,6 +329,8 @@ __global__ void scatter_kernel(DevState st, int what, int plan, const double* in
         for (int e = 0; e < n2; ++e) st.LD[e * S + s] = in[(int64_t)i * n2 + e];
     if (what == G_LU && i < N - 1)
         for (int e = 0; e < n2; ++e) st.LU[e * S + s] = in[(int64_t)i * n2 + e];
+    if (what == G_SD && i < N)
+        for (int e = 0; e < n2; ++e) st.SD[e * S + s] = in[(int64_t)i * n2 + e];
 }
 
 hipError_t launch_gather(const DevState& st, int what, int plan, int N, double* out, hipStream_t s) {

@@ -83,3 +83,32 @@ def test_serving_matches_plans_solved_alone(pg):
         alone.close()
         assert np.array_equal(rec["result"]["mu"], r2[0]["result"]["mu"]), rec["id"]
         assert np.array_equal(rec["result"]["cov_diag"], r2[0]["result"]["cov_diag"]), rec["id"]
+
+
+def test_slr_round_rejects_bad_nominal_and_keeps_plan(pg):
+    # Alg. 2's first round validates the nominal trajectory in the library:
+    # a covariance block that is not SPD, or a mean without covariances, is
+    # EINVAL and leaves the plan as it was
+    import ctypes as C
+    from paper_2411_03416_amd import _abi
+    p = workloads.quadrotor_problem(5, N=30)
+    ctx = pg.pgvimp_create([p], use_graph=False, mu_init=[p["nominal_mean"]])
+    before = pg.pgvimp_get_state(ctx, 0)
+    bad = np.array(p["nominal_cov"], dtype=np.float64).copy()
+    bad[7] = -bad[7]
+    with pytest.raises(pg.PgvimpError) as e:
+        pg.pgvimp_slr_round(ctx, 0, gravity=p["quad"]["gravity"], n_iters=3, nominal_mean=p["nominal_mean"],
+                            nominal_cov=bad)
+    assert e.value.code == pg.EINVAL
+    mean = np.ascontiguousarray(p["nominal_mean"], dtype=np.float64)
+    prm = np.array([p["quad"]["gravity"]])
+    rc = _abi.load().pgvimp_slr_round(ctx.handle, 0, _abi.MODEL_QUAD2D, prm.ctypes.data_as(C.POINTER(C.c_double)),
+                                      3, mean.ctypes.data, None, 3, None, None)
+    assert rc == pg.EINVAL
+    for x, y in zip(before, pg.pgvimp_get_state(ctx, 0)):
+        assert np.array_equal(x, y)
+    # a valid first round: the budget is the round's iteration count
+    pg.pgvimp_slr_round(ctx, 0, gravity=p["quad"]["gravity"], n_iters=3, nominal_mean=p["nominal_mean"],
+                        nominal_cov=p["nominal_cov"])
+    st = pg.pgvimp_prox_step(ctx, 5)[0]
+    assert st["iters_done"] == 3 and st["iters_left"] == 0
