@@ -240,6 +240,23 @@ int pgvimp_factor_expectations(pgvimp_ctx *ctx, int32_t plan, double *E_coll, do
                                double *hess, double *E_prior);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * outputs as pgvimp_factor_expectations, but host outputs are staged through
+ * a fixed library array of 4 MiB per device (2^19 doubles) instead of a
+ * buffer allocated on first use, and the call makes no device allocation or
+ * free.  The array's device address is looked up once per device when the
+ * first context on it is created.  ENOMEM if the largest output
+ * (max(N*n*n, N+1) doubles) exceeds the array (host outputs only; with
+ * io_on_device = 1 nothing is staged).  Every call on one device shares that
+ * device's array: calls that overlap on one device (from several threads or
+ * contexts) race and must be serialised by the caller.  The call
+ * synchronises the context's stream before it returns.
+ */
+int pgvimp_factor_expectations_noalloc(pgvimp_ctx *ctx, int32_t plan, double *E_coll, double *grad,
+                                       double *hess, double *E_prior);
+
+/*
  * Run n_iters KL-proximal iterations (Alg. 1) on every live plan that has
  * budget left: expectations, step-size selection, update (Theorem 1), new
  * marginals.  per_plan (host, may be NULL) receives max_plans entries;

@@ -271,6 +271,19 @@ def pgvimp_factor_expectations(ctx, plan):
     return E, g, H, Ep
 
 
+def pgvimp_factor_expectations_noalloc(ctx, plan):
+    """As pgvimp_factor_expectations, through the library's allocation-free
+    entry point (fixed per-device staging array)."""
+    N, n = ctx.plan_N[plan], ctx.n
+    E = np.zeros(N)
+    g = np.zeros((N, n))
+    H = np.zeros((N, n, n))
+    Ep = np.zeros(N + 1)
+    _check(_abi.load().pgvimp_factor_expectations_noalloc(ctx.handle, plan, E.ctypes.data, g.ctypes.data,
+                                                          H.ctypes.data, Ep.ctypes.data), ctx.handle)
+    return E, g, H, Ep
+
+
 def pgvimp_prox_step(ctx, n_iters=1):
     """Run n_iters iterations on all live plans; returns {plan: stats dict}."""
     P = ctx.cfg.max_plans

@@ -79,6 +79,8 @@ SIGNATURES = [
     ("pgvimp_remove_plan", C.c_int, [C.c_void_p, C.c_int32]),
     ("pgvimp_marginals", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, _dp]),
     ("pgvimp_factor_expectations", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("pgvimp_factor_expectations_noalloc", C.c_int,
+     [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("pgvimp_expect_all", C.c_int, [C.c_void_p, C.c_int32]),
     ("pgvimp_prox_step", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Stats)]),
     ("pgvimp_solve", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Stats)]),

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <type_traits>
 #include <cstdio>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -217,17 +218,22 @@ int ensure_stage(pgvimp_ctx* c, size_t bytes) {
     return PGVIMP_OK;
 }
 
-// Copy an [N][...] array gathered on the device to the caller.
-int gather_out(pgvimp_ctx* c, int what, int plan, int N, double* out, size_t count) {
+// Copy an [N][...] array gathered on the device to the caller.  Host
+// output goes through `stage` when given (at least count doubles), else
+// through the context's own staging buffer.
+int gather_out(pgvimp_ctx* c, int what, int plan, int N, double* out, size_t count, double* stage = nullptr) {
     if (!out) return PGVIMP_OK;
     if (c->cfg.io_on_device) {
         HCK(c, launch_gather(c->st, what, plan, N, out, c->stream));
         return PGVIMP_OK;
     }
-    int rc = ensure_stage(c, std::max<size_t>(count, 1) * sizeof(double));
-    if (rc) return rc;
-    HCK(c, launch_gather(c->st, what, plan, N, c->stage, c->stream));
-    HCK(c, hipMemcpyAsync(out, c->stage, count * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    if (!stage) {
+        int rc = ensure_stage(c, std::max<size_t>(count, 1) * sizeof(double));
+        if (rc) return rc;
+        stage = c->stage;
+    }
+    HCK(c, launch_gather(c->st, what, plan, N, stage, c->stream));
+    HCK(c, hipMemcpyAsync(out, stage, count * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HCK(c, hipStreamSynchronize(c->stream));
     return PGVIMP_OK;
 }
@@ -308,6 +314,34 @@ int validate_problem(pgvimp_ctx* c, const pgvimp_problem* p) {
     return PGVIMP_OK;
 }
 
+}  // namespace
+
+// Staging area of the allocation-free entry point (host output of
+// pgvimp_factor_expectations_noalloc).  Each device holds its own copy for
+// the life of the process; host code must use the per-device address from
+// hipGetSymbolAddress, never the array's name.
+constexpr int64_t kNoAllocDoubles = int64_t(1) << 19;  // 4 MiB
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (which must be current), looked
+// up once per device.
+hipError_t scratch_address(int device, double** out) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = (double*)ptr;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
 }  // namespace
 
 extern "C" {
@@ -471,6 +505,12 @@ int pgvimp_create(const pgvimp_problem* probs, int32_t n_probs, const pgvimp_eng
     int rc = PGVIMP_OK;
     if (hipSetDevice(cfg->device) != hipSuccess) {
         g_create_err = "hipSetDevice failed";
+        delete c;
+        return PGVIMP_EDEVICE;
+    }
+    double* scr = nullptr;
+    if (scratch_address(cfg->device, &scr) != hipSuccess) {
+        g_create_err = "hipGetSymbolAddress of the staging scratch failed";
         delete c;
         return PGVIMP_EDEVICE;
     }
@@ -760,6 +800,31 @@ int pgvimp_factor_expectations(pgvimp_ctx* c, int32_t plan, double* E_coll, doub
     if ((rc = gather_out(c, G_GEMB, plan, N, grad, (size_t)N * n))) return rc;
     if ((rc = gather_out(c, G_HEMB, plan, N, hess, (size_t)N * n * n))) return rc;
     if ((rc = gather_out(c, G_EPRI, plan, N, E_prior, (size_t)N + 1))) return rc;
+    HCK(c, hipStreamSynchronize(c->stream));
+    return PGVIMP_OK;
+}
+
+int pgvimp_factor_expectations_noalloc(pgvimp_ctx* c, int32_t plan, double* E_coll, double* grad, double* hess,
+                                       double* E_prior) {
+    if (!plan_ok(c, plan)) return PGVIMP_EINVAL;
+    HCK(c, hipSetDevice(c->cfg.device));
+    const PlanHost& ph = c->plans[plan];
+    const int N = ph.N, n = c->n;
+    const int64_t need = std::max<int64_t>((int64_t)N * n * n, (int64_t)N + 1);
+    if (!c->cfg.io_on_device && need > kNoAllocDoubles)
+        FAIL(c, PGVIMP_ENOMEM, "plan %d needs %lld doubles of staging, the allocation-free limit is %lld", plan,
+             (long long)need, (long long)kNoAllocDoubles);
+    double* stage = nullptr;
+    HCK(c, scratch_address(c->cfg.device, &stage));
+    if (ph.coll_kind != PGVIMP_COLL_NONE)
+        HCK(c, launch_expect(c->st, ph.coll_kind, ph.d, ph.p, c->cfg.precision, ph.lanes, plan, plan + 1, N, 0,
+                             c->stream));
+    HCK(c, launch_prior_costs(c->st, plan, N, c->stream));
+    int rc;
+    if ((rc = gather_out(c, G_ECOL, plan, N, E_coll, N, stage))) return rc;
+    if ((rc = gather_out(c, G_GEMB, plan, N, grad, (size_t)N * n, stage))) return rc;
+    if ((rc = gather_out(c, G_HEMB, plan, N, hess, (size_t)N * n * n, stage))) return rc;
+    if ((rc = gather_out(c, G_EPRI, plan, N, E_prior, (size_t)N + 1, stage))) return rc;
     HCK(c, hipStreamSynchronize(c->stream));
     return PGVIMP_OK;
 }
