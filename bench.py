@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
     ap.add_argument("--segments", type=int, default=0)
-    ap.add_argument("--lanes", type=int, default=0)
+    ap.add_argument("--group", type=int, default=0, help="factors per expectation workgroup (0 = per launch)")
     ap.add_argument("--trial-width", type=int, default=0, help="trial step sizes per window (0 = library default)")
     ap.add_argument("--trial-slots", type=int, default=0, help="widest trial window (0 = library default)")
     ap.add_argument("--trial-lookahead", type=int, default=0,
@@ -50,6 +50,9 @@ def parse():
     ap.add_argument("--qps", type=float, default=20.0)
     ap.add_argument("--requests", type=int, default=60)
     ap.add_argument("--sweep-plans", type=int, nargs="*", default=None, help="plan counts of --expect-sweep")
+    ap.add_argument("--sweep-prec", choices=("mixed", "fp64", "both"), default="both",
+                    help="precisions of --expect-sweep")
+    ap.add_argument("--sweep-reps", type=int, default=20, help="timed launches per --expect-sweep point")
     ap.add_argument("--expect-sweep", action="store_true",
                     help="time the expectation kernel alone over a batch sweep (32 plans, growing N)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -98,21 +101,23 @@ def expect_sweep(args, pg):
         for k in range(n_plans):
             q = dict(base[k % 32])
             q["n_iters"] = 1
-            if args.lanes:
-                q["lanes_per_factor"] = args.lanes
+            if args.group:
+                q["expect_group"] = args.group
             probs.append(q)
         for name, prec in (("mixed", pg.MIXED), ("fp64", pg.FP64)):
+            if args.sweep_prec not in ("both", name):
+                continue
             ctx = pg.pgvimp_create(probs, precision=prec, use_graph=False, trial_width=1)
             pg.pgvimp_expect_all(ctx, 3)
             pg.pgvimp_profile(ctx, True)
             pg.pgvimp_kernel_times(ctx, reset=True)
-            pg.pgvimp_expect_all(ctx, 20)
+            pg.pgvimp_expect_all(ctx, args.sweep_reps)
             kt = pg.pgvimp_kernel_times(ctx, reset=True)
             pg.pgvimp_destroy(ctx)
             torch.cuda.synchronize()
             ms = kt["expect"][0]
             f = n_plans * N
-            rows.append({"factors": f, "precision": name, "lanes": args.lanes or "tuned", "ms": ms,
+            rows.append({"factors": f, "precision": name, "group": args.group or "auto", "ms": ms,
                          "factors_per_s": f / (ms * 1e-3),
                          "hbm_GBs": 88.0 * f / (ms * 1e-3) / 1e9, "hbm_frac": 88.0 * f / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                          "gather_GBs": 400.0 * f / (ms * 1e-3) / 1e9,
@@ -134,7 +139,7 @@ def make_batch(n_plans, N, iters):
     return probs
 
 
-def timed_solve(pg, probs, precision, steps, warmup, iters, segments=0, lanes=0, profile=True, trial_width=0,
+def timed_solve(pg, probs, precision, steps, warmup, iters, segments=0, group=0, profile=True, trial_width=0,
                 trial_lookahead=0, trial_slots=0):
     """Create one context for the batch, warm up, then time `steps` solves,
     each one HIP graph replay.  With profile, the same number of solves is
@@ -142,15 +147,15 @@ def timed_solve(pg, probs, precision, steps, warmup, iters, segments=0, lanes=0,
     (launched directly, since events inside a graph cannot be timed) to get
     each kernel's mean duration."""
     import torch
-    if segments or lanes:
+    if segments or group:
         # explicit shapes override the tuned per-plan ones
         probs = [dict(p) for p in probs]
         for p in probs:
             if segments:
                 p["segments"] = segments
-            if lanes:
-                p["lanes_per_factor"] = lanes
-    ctx = pg.pgvimp_create(probs, precision=precision, use_graph=True, segments=segments, lanes=lanes,
+            if group:
+                p["expect_group"] = group
+    ctx = pg.pgvimp_create(probs, precision=precision, use_graph=True, segments=segments, expect_group=group,
                            trial_width=trial_width, trial_lookahead=trial_lookahead, trial_slots=trial_slots)
     for _ in range(warmup):
         pg.pgvimp_solve(ctx, iters)
@@ -177,10 +182,10 @@ def timed_solve(pg, probs, precision, steps, warmup, iters, segments=0, lanes=0,
         kt["eager_ms_per_step"] = 1e3 * (time.perf_counter() - t1) / steps
         pg.pgvimp_profile(ctx, False)
     status = [v["status"] for v in st.values()]
-    seg, lanes_used = pg.pgvimp_launch_shape(ctx, probs[0]["N"])
+    seg, group_used = pg.pgvimp_launch_shape(ctx, probs[0]["N"])
     pg.pgvimp_destroy(ctx)
     return {"wall_s": wall, "step_ms": step_ms, "trials": trials, "kt": kt, "status": status,
-            "segments": seg, "lanes": lanes_used, "evals": evals}
+            "segments": seg, "group": group_used, "evals": evals}
 
 
 def counter_traffic(kernel):
@@ -268,7 +273,7 @@ def main():
     probs = make_batch(args.plans, args.N, args.iters)
     B, N, K = args.plans, args.N, args.iters
     n = probs[0]["n"]
-    mixed = timed_solve(pg, probs, pg.MIXED, args.steps, args.warmup, K, args.segments, args.lanes,
+    mixed = timed_solve(pg, probs, pg.MIXED, args.steps, args.warmup, K, args.segments, args.group,
                         trial_width=args.trial_width, trial_lookahead=args.trial_lookahead,
                         trial_slots=args.trial_slots)
     ms = 1e3 * mixed["wall_s"] / args.steps
@@ -281,7 +286,7 @@ def main():
         "config": {"workload": f"point robot, {B} seeded maps 500x500 (40 discs/boxes), N={N}, GH p=5, "
                                f"{K} prox iterations per solve, one HIP graph per solve",
                    "plans": B, "N": N, "iters": K, "n": n, "segments": mixed["segments"],
-                   "lanes_per_factor": mixed["lanes"]},
+                   "expect_group": mixed["group"]},
         "plans_per_s": B / (ms / 1e3),
         "latency_ms": {"p50": pct(mixed["step_ms"], 50), "p99": pct(mixed["step_ms"], 99)},
         "status_ok": all(s == 0 for s in mixed["status"]),
@@ -310,7 +315,7 @@ def main():
                   "avg_ms": trial_ms, "bytes_per_launch": bytes_per_launch, "unit_bytes": unit_bytes,
                   "units_per_launch": units_per_launch,
                   "fp64_tflops": 18.0 * n ** 3 * units_per_launch / (trial_ms * 1e-3) / 1e12}
-        rexp = {"kernel": "expect_kernel<float,2,5,32,point2d>", "bound": "hbm", "achieved": exp_gbs,
+        rexp = {"kernel": "expect_kernel<float,2,5,point2d>", "bound": "hbm", "achieved": exp_gbs,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": exp_gbs / HBM_PEAK_GBS, "traffic": None,
                 "avg_ms": exp_ms, "bytes_per_launch": exp_bytes}
         dominant = max(totals, key=totals.get)
@@ -320,7 +325,7 @@ def main():
         out["kernel_avg_ms"] = {k: v[0] for k, v in kt.items() if isinstance(v, tuple)}
         out["eager_ms_per_step"] = kt["eager_ms_per_step"]
     if not args.no_fp64:
-        f64 = timed_solve(pg, probs, pg.FP64, max(2, args.steps // 2), 1, K, args.segments, args.lanes,
+        f64 = timed_solve(pg, probs, pg.FP64, max(2, args.steps // 2), 1, K, args.segments, args.group,
                           profile=False, trial_width=args.trial_width, trial_lookahead=args.trial_lookahead,
                           trial_slots=args.trial_slots)
         ms64 = 1e3 * f64["wall_s"] / max(2, args.steps // 2)
@@ -328,7 +333,7 @@ def main():
                        "plans_per_s": B / (ms64 / 1e3),
                        "latency_ms": {"p50": pct(f64["step_ms"], 50), "p99": pct(f64["step_ms"], 99)}}
         # serial FP64: the same plans solved one at a time
-        ser = timed_solve(pg, probs[:1], pg.FP64, 3, 1, K, args.segments, args.lanes, profile=False)
+        ser = timed_solve(pg, probs[:1], pg.FP64, 3, 1, K, args.segments, args.group, profile=False)
         ser_ms = 1e3 * ser["wall_s"] / 3
         out["serial_fp64"] = {"plans_per_s": 1.0 / (ser_ms / 1e3), "ms_per_plan": ser_ms}
     if not args.no_cpu:

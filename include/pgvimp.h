@@ -127,7 +127,8 @@ typedef struct pgvimp_problem {
     const int32_t *fk_axes, *fk_sphere_link;
     const double *mu_init; /* optional [N][n] initial mean; NULL -> prior mean */
     int32_t segments;      /* chain segments for this plan (0 = context default) */
-    int32_t lanes_per_factor; /* expectation lanes per factor (0 = default)  */
+    int32_t expect_group;  /* factors per expectation workgroup: 32, 64, 128,
+                              256 or 0 = chosen per launch (speed only)   */
 } pgvimp_problem;
 
 /*
@@ -139,8 +140,11 @@ typedef struct pgvimp_problem {
  * default priority created and owned by the context).  If
  * dev_arena is non-NULL the context sub-allocates all its device memory
  * from that caller-owned buffer of arena_bytes bytes (which must outlive
- * the context); otherwise it allocates its own.  segments and
- * lanes_per_factor override the tuned launch shapes (0 = tuned default);
+ * the context); otherwise it allocates its own.  segments overrides the
+ * tuned chain segments (0 = tuned default); expect_group fixes the factors
+ * per workgroup of the expectation kernel (32, 64, 128 or 256; 0 = the
+ * largest that gives every compute unit four workgroups; the arm always
+ * uses 32; speed only, never results);
  * use_graph = 1 captures pgvimp_prox_step's iterations in a HIP graph sized
  * to the plans present (re-captured when they change); use_graph = 2 sizes
  * the graph to the full capacity so plans can join and leave without a new
@@ -164,7 +168,7 @@ typedef struct pgvimp_engine_cfg {
     void *stream;
     void *dev_arena;
     uint64_t arena_bytes;
-    int32_t io_on_device, segments, lanes_per_factor, use_graph;
+    int32_t io_on_device, segments, expect_group, use_graph;
     int32_t trial_width, trial_lookahead, trial_slots;
 } pgvimp_engine_cfg;
 
@@ -328,10 +332,11 @@ int pgvimp_sync(pgvimp_ctx *ctx);
 
 /*
  * Launch shapes in use: *segments = chain segments of the first live plan of
- * N states (the context default for N if there is none), *lanes = lanes
- * per factor of the expectation kernel for this context.
+ * N states (the context default for N if there is none), *group = factors
+ * per workgroup of the expectation kernel for the live plans (of the first
+ * live plan's request).  Either pointer may be NULL.
  */
-int pgvimp_launch_shape(pgvimp_ctx *ctx, int32_t N, int32_t *segments, int32_t *lanes);
+int pgvimp_launch_shape(pgvimp_ctx *ctx, int32_t N, int32_t *segments, int32_t *group);
 
 /* kernel kinds reported by pgvimp_kernel_times */
 #define PGVIMP_K_EXPECT 0  /* collision-factor expectations                */

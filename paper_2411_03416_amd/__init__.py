@@ -108,35 +108,30 @@ def problem_struct(prob, mu_init=None):
             s.fk_sphere_link = arr(fk["sphere_link"], np.int32).ctypes.data_as(C.POINTER(C.c_int32))
     if mu_init is not None:
         s.mu_init = _dptr(arr(np.asarray(mu_init).reshape(N, n)))
-    seg, lanes = _tuned_shape(prob)
-    s.segments = int(prob.get("segments", seg))
-    s.lanes_per_factor = int(prob.get("lanes_per_factor", lanes))
+    s.segments = int(prob.get("segments", _tuned_segments(prob)))
+    s.expect_group = int(prob.get("expect_group", 0))
     return s, keep
 
 
 _TUNED = None
 
 
-def _tuned_shape(prob):
-    """Launch shape for a plan from the autotuner's table (tuned.json next
-    to this file), keyed by the plan's own state dimension, length and
-    quadrature class only; (0, 0) = library defaults."""
+def _tuned_segments(prob):
+    """Chain segments for a plan from the autotuner's table (tuned.json next
+    to this file), keyed by the plan's own state dimension and length only;
+    0 = library default."""
     global _TUNED
     if _TUNED is None:
         import json
         import os
         path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
         _TUNED = json.load(open(path)) if os.path.exists(path) else {}
-    seg = 0
     table = _TUNED.get("segments", {}).get(str(int(prob["n"])))
-    if table:
-        # entries [N, segments] sorted by N: take the nearest tuned length
-        N = int(prob["N"])
-        seg = min(table, key=lambda e: abs(e[0] - N))[1]
-    lanes = 0
-    key = f'{prob.get("coll_kind", "none")}/{int(prob.get("gh_points", 0))}'
-    lanes = int(_TUNED.get("lanes", {}).get(key, 0))
-    return seg, lanes
+    if not table:
+        return 0
+    # entries [N, segments] sorted by N: take the nearest tuned length
+    N = int(prob["N"])
+    return min(table, key=lambda e: abs(e[0] - N))[1]
 
 
 class Context:
@@ -176,7 +171,7 @@ def _heap_need(probs):
 
 
 def pgvimp_create(problems, n=None, precision=FP64, max_plans=None, max_states=None, heap_bytes=None,
-                  device=0, use_torch=True, stream=None, segments=0, lanes=0, use_graph=True, mu_init=None,
+                  device=0, use_torch=True, stream=None, segments=0, expect_group=0, use_graph=True, mu_init=None,
                   trial_width=0, trial_lookahead=0, trial_slots=0):
     """Create a context holding `problems` (list of dicts); see pgvimp_create
     in include/pgvimp.h.  With use_torch the device arena is a torch uint8
@@ -191,7 +186,7 @@ def pgvimp_create(problems, n=None, precision=FP64, max_plans=None, max_states=N
     cfg = _abi.EngineCfg()
     cfg.device, cfg.n, cfg.precision, cfg.max_plans = device, n, precision, max_plans
     cfg.max_states, cfg.heap_bytes = max_states, heap_bytes
-    cfg.segments, cfg.lanes_per_factor = segments, lanes
+    cfg.segments, cfg.expect_group = segments, expect_group
     cfg.use_graph = int(use_graph) if not isinstance(use_graph, bool) else (1 if use_graph else 0)
     cfg.trial_width = trial_width
     cfg.trial_lookahead = trial_lookahead

@@ -44,7 +44,7 @@ class Problem(C.Structure):
         ("fk_base", _dp), ("fk_link_len", _dp), ("fk_sphere_frac", _dp),
         ("fk_axes", _ip), ("fk_sphere_link", _ip),
         ("mu_init", _dp),
-        ("segments", C.c_int32), ("lanes_per_factor", C.c_int32),
+        ("segments", C.c_int32), ("expect_group", C.c_int32),
     ]
 
 
@@ -53,7 +53,7 @@ class EngineCfg(C.Structure):
         ("device", C.c_int32), ("n", C.c_int32), ("precision", C.c_int32), ("max_plans", C.c_int32),
         ("max_states", C.c_int64), ("heap_bytes", C.c_int64),
         ("stream", C.c_void_p), ("dev_arena", C.c_void_p), ("arena_bytes", C.c_uint64),
-        ("io_on_device", C.c_int32), ("segments", C.c_int32), ("lanes_per_factor", C.c_int32),
+        ("io_on_device", C.c_int32), ("segments", C.c_int32), ("expect_group", C.c_int32),
         ("use_graph", C.c_int32), ("trial_width", C.c_int32), ("trial_lookahead", C.c_int32),
         ("trial_slots", C.c_int32),
     ]

@@ -7,9 +7,10 @@ the batch it runs in):
 
   * segments: chain segments per plan, per state dimension n and length N
     (the depth of the marginals/mean-solve sweeps is about
-    2 N / segments + 2 segments block steps);
-  * lanes: lanes per factor of the expectation kernel per collision class
-    and Gauss-Hermite order.
+    2 N / segments + 2 segments block steps).
+
+The expectation kernel needs no table: its factors per workgroup are
+chosen per launch from the batch and never change results.
 
 Usage: python -m paper_2411_03416_amd.autotune [--quick]
 """
@@ -38,19 +39,10 @@ def _time_solve(pg, probs, iters, reps=3, **kw):
     return dt
 
 
-def _time_expect(pg, probs, iters, lanes):
-    ctx = pg.pgvimp_create(probs, use_graph=True, lanes=lanes)
-    pg.pgvimp_profile(ctx, True)
-    pg.pgvimp_solve(ctx, iters)
-    kt = pg.pgvimp_kernel_times(ctx, reset=True)
-    pg.pgvimp_destroy(ctx)
-    return kt["expect"][0]
-
-
 def tune(quick=False):
     import paper_2411_03416_amd as pg
     import workloads
-    out = {"segments": {}, "lanes": {}, "device": None}
+    out = {"segments": {}, "device": None}
     import torch
     out["device"] = torch.cuda.get_device_name(0)
     Ns = [50, 150, 400, 750, 1000] if not quick else [50, 750]
@@ -76,22 +68,6 @@ def tune(quick=False):
                     best = (c, dt)
             rows.append([N, best[0]])
         out["segments"][str(n)] = rows
-    for key, maker, cand in (("point2d/3", lambda s: workloads.point2d_problem(s, N=750), (8, 16, 32)),
-                             ("point2d/5", lambda s: workloads.config1_problem(s), (16, 32, 64)),
-                             ("point3d/3", lambda s: workloads.point3d_problem(s, N=400), (16, 32, 64)),
-                             ("arm3d/2", lambda s: workloads.arm_problem(s, N=100), (16, 32, 64))):
-        plans = [maker(k) for k in range(8 if "arm" not in key else 2)]
-        for p in plans:
-            p["n_iters"] = 2
-        best = None
-        for lanes in cand:
-            for p in plans:
-                p["lanes_per_factor"] = lanes
-            ms = _time_expect(pg, plans, 2, lanes)
-            print(f"{key} lanes={lanes}: expect {ms * 1e3:.1f} us", flush=True)
-            if best is None or ms < best[1]:
-                best = (lanes, ms)
-        out["lanes"][key] = best[0]
     return out
 
 

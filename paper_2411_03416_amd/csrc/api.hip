@@ -29,14 +29,14 @@ struct PlanHost {
     int64_t heap_off = -1;
     int coll_kind = 0, d = 0, p = 0;
     double dt = 0.0;
-    int lanes = 0;
+    int group = 0;  // factors per expectation workgroup (0 = chosen per launch)
     int max_bisect = 0;
 };
 
 struct ClassKey {
-    int kind, d, p, lanes;
+    int kind, d, p, group;
     bool operator==(const ClassKey& o) const {
-        return kind == o.kind && d == o.d && p == o.p && lanes == o.lanes;
+        return kind == o.kind && d == o.d && p == o.p && group == o.group;
     }
 };
 
@@ -285,12 +285,10 @@ int validate_problem(pgvimp_ctx* c, const pgvimp_problem* p) {
     if (d == 0 || p->coll_dim != d || d > n) FAIL(c, PGVIMP_EINVAL, "collision kind/dim mismatch");
     for (int k = 0; k < d; ++k)
         if (p->coll_index[k] < 0 || p->coll_index[k] >= n) FAIL(c, PGVIMP_EINVAL, "coll_index out of range");
-    const int lanes = p->lanes_per_factor > 0   ? p->lanes_per_factor
-                      : c->cfg.lanes_per_factor > 0 ? c->cfg.lanes_per_factor
-                                                    : default_lanes(p->coll_kind, d, p->gh_points);
-    if (!expect_supported(p->coll_kind, d, p->gh_points, lanes))
-        FAIL(c, PGVIMP_EINVAL, "unsupported quadrature shape kind=%d d=%d p=%d lanes=%d", p->coll_kind, d,
-             p->gh_points, lanes);
+    const int group = p->expect_group > 0 ? p->expect_group : c->cfg.expect_group;
+    if (!expect_supported(p->coll_kind, d, p->gh_points, group))
+        FAIL(c, PGVIMP_EINVAL, "unsupported quadrature shape kind=%d d=%d p=%d group=%d", p->coll_kind, d,
+             p->gh_points, group);
     const bool is3 = p->coll_kind != PGVIMP_COLL_POINT2D;
     if (!p->sdf || p->gx < 2 || p->gy < 2 || (is3 ? p->gz < 2 : p->gz != 1))
         FAIL(c, PGVIMP_EINVAL, "bad SDF grid");
@@ -715,10 +713,7 @@ int pgvimp_add_plan(pgvimp_ctx* c, const pgvimp_problem* p, int32_t* plan_out) {
     ph.p = p->gh_points;
     ph.dt = p->dt;
     ph.max_bisect = p->max_bisect;
-    ph.lanes = !coll                      ? 0
-               : p->lanes_per_factor > 0   ? p->lanes_per_factor
-               : c->cfg.lanes_per_factor > 0 ? c->cfg.lanes_per_factor
-                                             : default_lanes(p->coll_kind, pd.d, p->gh_points);
+    ph.group = !coll ? 0 : p->expect_group > 0 ? p->expect_group : c->cfg.expect_group;
     // prior (Alg. 1) and initial state
     HCK(c, launch_prior_build(c->st, slot, slot + 1, N, c->stream));
     HCK(c, launch_prior_assemble(c->st, slot, slot + 1, N, c->stream));
@@ -792,7 +787,7 @@ int pgvimp_factor_expectations(pgvimp_ctx* c, int32_t plan, double* E_coll, doub
     const PlanHost& ph = c->plans[plan];
     const int N = ph.N, n = c->n;
     if (ph.coll_kind != PGVIMP_COLL_NONE)
-        HCK(c, launch_expect(c->st, ph.coll_kind, ph.d, ph.p, c->cfg.precision, ph.lanes, plan, plan + 1, N, 0,
+        HCK(c, launch_expect(c->st, ph.coll_kind, ph.d, ph.p, c->cfg.precision, ph.group, plan, plan + 1, N, 0,
                              c->stream));
     HCK(c, launch_prior_costs(c->st, plan, N, c->stream));
     int rc;
@@ -817,7 +812,7 @@ int pgvimp_factor_expectations_noalloc(pgvimp_ctx* c, int32_t plan, double* E_co
     double* stage = nullptr;
     HCK(c, scratch_address(c->cfg.device, &stage));
     if (ph.coll_kind != PGVIMP_COLL_NONE)
-        HCK(c, launch_expect(c->st, ph.coll_kind, ph.d, ph.p, c->cfg.precision, ph.lanes, plan, plan + 1, N, 0,
+        HCK(c, launch_expect(c->st, ph.coll_kind, ph.d, ph.p, c->cfg.precision, ph.group, plan, plan + 1, N, 0,
                              c->stream));
     HCK(c, launch_prior_costs(c->st, plan, N, c->stream));
     int rc;
@@ -834,7 +829,7 @@ static std::vector<ClassKey> live_classes(pgvimp_ctx* c) {
     std::vector<ClassKey> v;
     for (auto& ph : c->plans) {
         if (!ph.active || ph.coll_kind == PGVIMP_COLL_NONE) continue;
-        ClassKey k{ph.coll_kind, ph.d, ph.p, ph.lanes};
+        ClassKey k{ph.coll_kind, ph.d, ph.p, ph.group};
         if (std::find(v.begin(), v.end(), k) == v.end()) v.push_back(k);
     }
     return v;
@@ -910,7 +905,7 @@ static int enqueue_iters(pgvimp_ctx* c, int n_iters, const std::vector<ClassKey>
     for (int it = 0; it < n_iters; ++it) {
         for (auto& k : cls) {
             if ((rc = begin(PGVIMP_K_EXPECT))) return rc;
-            HCK(c, launch_expect(c->st, k.kind, k.d, k.p, c->cfg.precision, k.lanes, 0, phw, maxN, 1, c->stream));
+            HCK(c, launch_expect(c->st, k.kind, k.d, k.p, c->cfg.precision, k.group, 0, phw, maxN, 1, c->stream));
             if ((rc = end())) return rc;
         }
         if ((rc = begin(PGVIMP_K_PREP))) return rc;
@@ -965,7 +960,7 @@ int pgvimp_expect_all(pgvimp_ctx* c, int32_t reps) {
                 c->ev_kind[c->ev_used] = PGVIMP_K_EXPECT;
                 HCK(c, hipEventRecord(c->ev[c->ev_used], c->stream));
             }
-            HCK(c, launch_expect(c->st, k.kind, k.d, k.p, c->cfg.precision, k.lanes, 0, (int)c->plans.size(),
+            HCK(c, launch_expect(c->st, k.kind, k.d, k.p, c->cfg.precision, k.group, 0, (int)c->plans.size(),
                                  max_live_N(c), 1, c->stream));
             if (c->profile) {
                 HCK(c, hipEventRecord(c->ev[c->ev_used + 1], c->stream));
@@ -1187,7 +1182,7 @@ int pgvimp_slr_round(pgvimp_ctx* c, int32_t plan, int32_t model, const double* m
     return PGVIMP_OK;
 }
 
-int pgvimp_launch_shape(pgvimp_ctx* c, int32_t N, int32_t* segments, int32_t* lanes) {
+int pgvimp_launch_shape(pgvimp_ctx* c, int32_t N, int32_t* segments, int32_t* group) {
     if (!c || N < 1) return PGVIMP_EINVAL;
     if (segments) {
         // the segments of the first live plan of N states, else the default
@@ -1198,13 +1193,16 @@ int pgvimp_launch_shape(pgvimp_ctx* c, int32_t N, int32_t* segments, int32_t* la
                 break;
             }
     }
-    if (lanes) {
-        *lanes = c->cfg.lanes_per_factor;
+    if (group) {
+        // the group the expectation kernel takes for the live plans' class
+        // of the first live plan (the default when none is live)
+        int req = c->cfg.expect_group;
         for (auto& ph : c->plans)
-            if (ph.active && ph.lanes) {
-                *lanes = ph.lanes;
+            if (ph.active && ph.coll_kind != PGVIMP_COLL_NONE) {
+                req = ph.group;
                 break;
             }
+        *group = expect_group_for(req, plan_high_water(c), std::max(max_live_N(c), 1), c->st.wbudget);
     }
     return PGVIMP_OK;
 }

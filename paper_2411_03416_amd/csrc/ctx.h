@@ -189,7 +189,7 @@ hipError_t launch_iteration(const DevState& st, int phw, int part, int round, hi
 // Window `round` of step sizes of the current iteration for plans [0, phw).
 hipError_t launch_window(const DevState& st, int phw, int round, hipStream_t s);
 // collision expectations of plans [plan_lo, plan_hi) of up to maxN states each
-hipError_t launch_expect(const DevState& st, int coll_kind, int d, int p, int precision, int lanes, int plan_lo,
+hipError_t launch_expect(const DevState& st, int coll_kind, int d, int p, int precision, int group, int plan_lo,
                          int plan_hi, int maxN, int respect_budget, hipStream_t s);
 hipError_t launch_prior_costs(const DevState& st, int plan, int N, hipStream_t s);
 hipError_t launch_gather(const DevState& st, int what, int plan, int N, double* out, hipStream_t s);
@@ -197,8 +197,10 @@ hipError_t launch_scatter(const DevState& st, int what, int plan, int N, const d
 hipError_t launch_slr_model(const DevState& st, int plan, int N, double gravity, int p, double* A_out,
                             double* a_out, int write_model, hipStream_t s);
 bool chain_supported(int n);
-bool expect_supported(int coll_kind, int d, int p, int lanes);
-int default_lanes(int coll_kind, int d, int p);
+bool expect_supported(int coll_kind, int d, int p, int group);
+// factors per expectation workgroup for a launch over `plans` plan slots of
+// at most maxN states (group 0 = chosen from the batch)
+int expect_group_for(int group, int plans, int maxN, int cus);
 
 // modes of the chain kernel
 enum ChainMode { CHAIN_INIT = 0, CHAIN_MARGINALS = 1, CHAIN_REINIT = 3 };
