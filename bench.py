@@ -39,6 +39,7 @@ def parse():
     ap.add_argument("--iters", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
+    ap.add_argument("--no-configs", action="store_true", help="skip plans/s of configs 0, 2 and 3")
     ap.add_argument("--segments", type=int, default=0)
     ap.add_argument("--group", type=int, default=0, help="factors per expectation workgroup (0 = per launch)")
     ap.add_argument("--trial-width", type=int, default=0, help="trial step sizes per window (0 = library default)")
@@ -53,6 +54,8 @@ def parse():
     ap.add_argument("--sweep-prec", choices=("mixed", "fp64", "both"), default="both",
                     help="precisions of --expect-sweep")
     ap.add_argument("--sweep-reps", type=int, default=20, help="timed launches per --expect-sweep point")
+    ap.add_argument("--sweep-maps", choices=("shared", "distinct"), default="shared",
+                    help="--expect-sweep: plans k and k+32 share a map, or every plan has its own copy")
     ap.add_argument("--expect-sweep", action="store_true",
                     help="time the expectation kernel alone over a batch sweep (32 plans, growing N)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -91,6 +94,7 @@ def expect_sweep(args, pg):
     E + g 2 + H 3 doubles out) / mean launch time; the SDF gathers (4 cells x
     4 B per node, 25 nodes) and FP32 node flops (~1.1 kFLOP) are reported
     beside it."""
+    import numpy as np
     import torch
     import workloads
     rows = []
@@ -101,6 +105,10 @@ def expect_sweep(args, pg):
         for k in range(n_plans):
             q = dict(base[k % 32])
             q["n_iters"] = 1
+            if args.sweep_maps == "distinct" and k >= 32:
+                # the same obstacles, offset by a small constant per plan: a
+                # map of its own on the device for every plan
+                q["sdf"] = base[k % 32]["sdf"] + np.float32(1e-4 * (k // 32))
             if args.group:
                 q["expect_group"] = args.group
             probs.append(q)
@@ -117,7 +125,8 @@ def expect_sweep(args, pg):
             torch.cuda.synchronize()
             ms = kt["expect"][0]
             f = n_plans * N
-            rows.append({"factors": f, "precision": name, "group": args.group or "auto", "ms": ms,
+            rows.append({"factors": f, "precision": name, "maps": args.sweep_maps, "group": args.group or "auto",
+                         "ms": ms,
                          "factors_per_s": f / (ms * 1e-3),
                          "hbm_GBs": 88.0 * f / (ms * 1e-3) / 1e9, "hbm_frac": 88.0 * f / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                          "gather_GBs": 400.0 * f / (ms * 1e-3) / 1e9,
@@ -170,7 +179,7 @@ def timed_solve(pg, probs, precision, steps, warmup, iters, segments=0, group=0,
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     kt = None
-    evals = 0
+    evals = prof_trials = 0
     if profile:
         pg.pgvimp_profile(ctx, True)
         pg.pgvimp_kernel_times(ctx, reset=True)
@@ -178,6 +187,7 @@ def timed_solve(pg, probs, precision, steps, warmup, iters, segments=0, group=0,
         for _ in range(steps):
             sp = pg.pgvimp_solve(ctx, iters)
             evals += sum(v["evals_total"] for v in sp.values())
+            prof_trials += sum(v["trials_total"] for v in sp.values())
         kt = pg.pgvimp_kernel_times(ctx, reset=True)
         kt["eager_ms_per_step"] = 1e3 * (time.perf_counter() - t1) / steps
         pg.pgvimp_profile(ctx, False)
@@ -185,7 +195,10 @@ def timed_solve(pg, probs, precision, steps, warmup, iters, segments=0, group=0,
     seg, group_used = pg.pgvimp_launch_shape(ctx, probs[0]["N"])
     pg.pgvimp_destroy(ctx)
     return {"wall_s": wall, "step_ms": step_ms, "trials": trials, "kt": kt, "status": status,
-            "segments": seg, "group": group_used, "evals": evals}
+            "segments": seg, "group": group_used, "evals": evals, "prof_trials": prof_trials}
+
+
+KERNEL_SOURCE = {"trial_kernel": "chain_impl.h", "expect_kernel": "expect.hip"}
 
 
 def counter_traffic(kernel):
@@ -202,7 +215,7 @@ def counter_traffic(kernel):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
-    src = os.path.join(ROOT, "paper_2411_03416_amd", "csrc", "chain_impl.h")
+    src = os.path.join(ROOT, "paper_2411_03416_amd", "csrc", KERNEL_SOURCE[kernel])
     if kv.get("source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
         return None
     try:
@@ -222,7 +235,7 @@ import sys, time
 sys.path.insert(0, {root!r})
 import workloads
 from oracle import prior, prox
-p = workloads.config1_problem(seed=0, N={N})
+p = workloads.config1_problem(seed={seed}, N={N})
 t0 = time.perf_counter()
 pri = prior.build_prior(p)
 st = prox.init_state(p, pri)
@@ -232,19 +245,51 @@ print(time.perf_counter() - t0)
 """
 
 
-def cpu_baseline(N, iters_sample=20):
-    """The oracle as it stands, on one plan of the same workload, timed on
-    the host in a child process pinned to one BLAS/OpenMP thread (it never
-    touches the GPU): factor expectations per second of the whole solve."""
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(N, iters_sample=20, max_cores=16):
+    """The oracle as it stands on the same workload, timed on the host (it
+    never touches the GPU): plans of the config-1 batch, each prior build +
+    iters_sample iterations in a child process pinned to one BLAS/OpenMP
+    thread.  First one plan on one core, then one plan per core on every
+    host core at once (plan-parallel): factor expectations per second of
+    the whole solve."""
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
-    code = _CPU_SAMPLE.format(root=ROOT, N=N, iters=iters_sample)
-    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=600)
-    if r.returncode != 0:
-        return {"value": None, "error": r.stderr[-500:]}
-    dt = float(r.stdout.strip().splitlines()[-1])
-    return {"value": N * iters_sample / dt, "unit": "factor-expectations/s", "cores": 1, "kind": "oracle",
-            "sample": f"1 of the {N}-state plans: prior build + {iters_sample} iterations in {dt:.1f} s "
-                      f"(numpy/scipy FP64, 1 thread)"}
+
+    def run(seeds):
+        procs = [subprocess.Popen([sys.executable, "-c", _CPU_SAMPLE.format(root=ROOT, N=N, iters=iters_sample,
+                                                                             seed=k)],
+                                  stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, env=env)
+                 for k in seeds]
+        t0 = time.perf_counter()
+        outs = [p.communicate(timeout=900) for p in procs]
+        wall = time.perf_counter() - t0
+        if any(p.returncode != 0 for p in procs):
+            return None, next(o[1] for o, p in zip(outs, procs) if p.returncode != 0)[-500:]
+        return wall, [float(o[0].strip().splitlines()[-1]) for o in outs]
+
+    wall1, t1 = run([0])
+    if wall1 is None:
+        return {"value": None, "error": t1}
+    cores = max(1, min(os.cpu_count() or 1, max_cores))
+    wallc, tc = run(list(range(cores)))
+    if wallc is None:
+        return {"value": None, "error": tc}
+    model = _cpu_model()
+    return {"value": cores * N * iters_sample / wallc, "unit": "factor-expectations/s", "cores": cores,
+            "kind": "oracle", "plans_per_s": cores / wallc, "cpu_model": model, "nproc": os.cpu_count(),
+            "sample": f"{cores} of the {N}-state plans at once, one per core (plan-parallel), each prior build + "
+                      f"{iters_sample} iterations, numpy/scipy FP64 one thread each: {wallc:.1f} s wall",
+            "one_core": {"value": N * iters_sample / t1[0], "plans_per_s": 1.0 / t1[0], "cores": 1,
+                         "sample": f"1 plan: {t1[0]:.1f} s"}}
 
 
 def main():
@@ -303,9 +348,13 @@ def main():
         # trial precision reads D_i, U_i and writes Sigma_ii, Sigma_{i,i+1} with
         # messages (48 n^2 B) and the update + mean solve moves (6 n^2 + 4 n)
         # doubles: 1664 B for n = 4 (HBM bound at batch); FP64 ~18 n^3 flops
+        # Units are the method's own trials (the step sizes that halving one
+        # at a time would evaluate); the speculative step sizes of each
+        # concurrent window are reported beside them as waste.
         trial_ms, trial_launches = kt["trial"]
         unit_bytes = 48.0 * n * n + 8.0 * (6 * n * n + 4 * n)
-        units_per_launch = mixed["evals"] * N / trial_launches
+        units_per_launch = mixed["prof_trials"] * N / trial_launches
+        evals_per_launch = mixed["evals"] * N / trial_launches
         bytes_per_launch = unit_bytes * units_per_launch
         trial_gbs = bytes_per_launch / (trial_ms * 1e-3) / 1e9
         totals = {k: v[0] * v[1] for k, v in kt.items() if isinstance(v, tuple)}
@@ -313,11 +362,13 @@ def main():
         rtrial = {"kernel": "trial_kernel<4>", "bound": "hbm", "achieved": trial_gbs, "peak": HBM_PEAK_GBS,
                   "unit": "GB/s", "frac": trial_gbs / HBM_PEAK_GBS, "traffic": counter_traffic("trial_kernel"),
                   "avg_ms": trial_ms, "bytes_per_launch": bytes_per_launch, "unit_bytes": unit_bytes,
-                  "units_per_launch": units_per_launch,
+                  "units_per_launch": units_per_launch, "evaluated_per_launch": evals_per_launch,
+                  "speculative_frac": 1.0 - units_per_launch / max(evals_per_launch, 1e-300),
                   "fp64_tflops": 18.0 * n ** 3 * units_per_launch / (trial_ms * 1e-3) / 1e12}
         rexp = {"kernel": "expect_kernel<float,2,5,point2d>", "bound": "hbm", "achieved": exp_gbs,
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": exp_gbs / HBM_PEAK_GBS, "traffic": None,
-                "avg_ms": exp_ms, "bytes_per_launch": exp_bytes}
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": exp_gbs / HBM_PEAK_GBS,
+                "traffic": counter_traffic("expect_kernel"), "avg_ms": exp_ms, "bytes_per_launch": exp_bytes,
+                "note": "24k factors per launch: latency-bound; the batch sweep (--expect-sweep) gives the plateau"}
         dominant = max(totals, key=totals.get)
         out["roofline"] = rtrial if dominant == "trial" else rexp
         out["roofline_expect"] = rexp
@@ -336,9 +387,62 @@ def main():
         ser = timed_solve(pg, probs[:1], pg.FP64, 3, 1, K, args.segments, args.group, profile=False)
         ser_ms = 1e3 * ser["wall_s"] / 3
         out["serial_fp64"] = {"plans_per_s": 1.0 / (ser_ms / 1e3), "ms_per_plan": ser_ms}
+        if not args.no_configs:
+            out["configs"] = config_rates(pg)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(N)
     print(json.dumps(out), flush=True)
+
+
+def _timed(fn, steps):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def config_rates(pg):
+    """Plans/s of the other configurations, mixed and plain FP64, one step =
+    one solve of the batch (prior build, initial marginals, iterations):
+      config 0: 32 point-robot plans, N = 50, GH p = 3, 20 iterations;
+      config 2: 8 arm plans (n = 14), N = 100, GH p = 2 on 7 joints, 20 iterations;
+      config 3: 64 quadrotor plans, N ~ U{100..300}, 10 rounds of statistical
+                linearisation (Alg. 2) x 15 iterations."""
+    import workloads
+    out = {}
+    for name, make, count, iters, steps in (("config0", workloads.config0_problem, 32, 20, 5),
+                                             ("config2", workloads.config2_problem, 8, 20, 1)):
+        probs = [make(seed=k) for k in range(count)]
+        row = {"plans": count, "N": probs[0]["N"], "iters": iters}
+        for pname, prec in (("mixed", pg.MIXED), ("fp64", pg.FP64)):
+            ctx = pg.pgvimp_create(probs, precision=prec, use_graph=True)
+            pg.pgvimp_solve(ctx, iters)
+            dt = _timed(lambda: pg.pgvimp_solve(ctx, iters), steps)
+            st = pg.pgvimp_solve(ctx, iters)
+            pg.pgvimp_destroy(ctx)
+            row[pname] = {"plans_per_s": count / dt, "ms_per_step": 1e3 * dt,
+                          "factor_expectations_per_s": count * probs[0]["N"] * iters / dt,
+                          "status_ok": all(v["status"] == 0 for v in st.values())}
+        out[name] = row
+    probs = [workloads.config3_problem(seed=k) for k in range(64)]
+    row = {"plans": 64, "N_range": [min(p["N"] for p in probs), max(p["N"] for p in probs)],
+           "rounds": probs[0]["n_rounds"], "iters_per_round": probs[0]["n_iters"]}
+    for pname, prec in (("mixed", pg.MIXED), ("fp64", pg.FP64)):
+        ctx = pg.pgvimp_create(probs, precision=prec, use_graph=True)
+
+        def solve():
+            for r in range(probs[0]["n_rounds"]):
+                for k, p in enumerate(probs):
+                    (pg.ipgvimp_begin if r == 0 else pg.ipgvimp_next_round)(ctx, k, p)
+                pg.pgvimp_prox_step(ctx, probs[0]["n_iters"])
+        dt = _timed(solve, 1)
+        pg.pgvimp_destroy(ctx)
+        row[pname] = {"plans_per_s": 64 / dt, "ms_per_step": 1e3 * dt}
+    out["config3"] = row
+    return out
 
 
 if __name__ == "__main__":

@@ -26,12 +26,47 @@ struct PlanHost {
     int N = 0;
     int64_t off = -1;
     int64_t coff = -1;  // chain-order range
-    int64_t heap_off = -1;
+    int64_t heap_off = -1;  // model block
+    int64_t map_off = -1;   // SDF block (shared by plans with identical maps)
     int coll_kind = 0, d = 0, p = 0;
     double dt = 0.0;
     int group = 0;  // factors per expectation workgroup (0 = chosen per launch)
     int max_bisect = 0;
 };
+
+// Identity of an SDF grid: its dimensions and two independent 64-bit
+// hashes of its values.  Plans whose maps have equal keys share one device
+// copy (refcounted); a collision of both hashes between different grids of
+// equal dimensions is the only way two maps could be confused.
+struct MapKey {
+    int32_t gx, gy, gz;
+    uint64_t h1, h2;
+    bool operator<(const MapKey& o) const {
+        if (gx != o.gx) return gx < o.gx;
+        if (gy != o.gy) return gy < o.gy;
+        if (gz != o.gz) return gz < o.gz;
+        if (h1 != o.h1) return h1 < o.h1;
+        return h2 < o.h2;
+    }
+};
+struct MapEntry {
+    int64_t off;
+    int refs;
+};
+
+MapKey map_key(const float* sdf, int gx, int gy, int gz) {
+    const size_t count = (size_t)gx * gy * gz;
+    uint64_t h1 = 0xcbf29ce484222325ull, h2 = 0x9e3779b97f4a7c15ull;
+    for (size_t i = 0; i < count; ++i) {
+        uint32_t w;
+        memcpy(&w, sdf + i, 4);
+        h1 = (h1 ^ w) * 0x100000001b3ull;  // FNV-1a over 32-bit words
+        h2 += (uint64_t)w * 0xff51afd7ed558ccdull + i;
+        h2 = (h2 << 31) | (h2 >> 33);
+        h2 *= 0xc4ceb9fe1a85ec53ull;
+    }
+    return MapKey{gx, gy, gz, h1, h2};
+}
 
 struct ClassKey {
     int kind, d, p, group;
@@ -54,6 +89,7 @@ struct pgvimp_ctx {
     int64_t heap_bytes = 0;
     DevState st{};
     RangeAlloc states, cstates, heapalloc;  // states, chain-order ranges, heap
+    std::map<MapKey, MapEntry> maps;        // live SDF grids on the heap
     std::vector<PlanHost> plans;
     std::vector<PlanDev> pdev;  // host mirror of the device plan table
     // staging for host I/O
@@ -588,12 +624,19 @@ int pgvimp_add_plan(pgvimp_ctx* c, const pgvimp_problem* p, int32_t* plan_out) {
     const int nI = std::max(N - 1, 1);
     const bool coll = p->coll_kind != PGVIMP_COLL_NONE;
     const int ns = coll ? p->n_spheres : 1;
-    // heap block: sdf floats, then FP64 model data
+    // heap blocks: the SDF grid (shared with live plans of the same map),
+    // and the plan's FP64 model data
     const int64_t sdf_bytes = coll ? align_up((int64_t)p->gx * p->gy * p->gz * 4) : 0;
     const int64_t fk_count = 3 + PGVIMP_ARM_DOF + ns + PGVIMP_ARM_DOF + ns;
     const int64_t model_count = 4 * (int64_t)n * n + 2 * n + (int64_t)m * m + (int64_t)nI * n * n + (int64_t)nI * n +
                                 (int64_t)nI * n * m + ns + fk_count;
-    const int64_t bytes = sdf_bytes + align_up(model_count * 8);
+    const int64_t bytes = align_up(model_count * 8);
+    MapKey mkey{};
+    bool map_new = false;
+    if (coll) {
+        mkey = map_key(p->sdf, p->gx, p->gy, p->gz);
+        map_new = c->maps.find(mkey) == c->maps.end();
+    }
     const int64_t soff = c->states.alloc(N);
     if (soff < 0) FAIL(c, PGVIMP_ENOMEM, "no room for %d states", N);
     const int nseg = choose_segments(c, N, p->segments);
@@ -604,13 +647,17 @@ int pgvimp_add_plan(pgvimp_ctx* c, const pgvimp_problem* p, int32_t* plan_out) {
         FAIL(c, PGVIMP_ENOMEM, "no room for %lld chain positions", (long long)clen);
     }
     const int64_t hoff = c->heapalloc.alloc(bytes, kAlign);
-    if (hoff < 0) {
+    const int64_t moff = map_new ? c->heapalloc.alloc(sdf_bytes, kAlign) : coll ? c->maps[mkey].off : -1;
+    if (hoff < 0 || (map_new && moff < 0)) {
         c->states.release(soff);
         c->cstates.release(coff);
-        FAIL(c, PGVIMP_ENOMEM, "no heap room for %lld bytes of map/model data", (long long)bytes);
+        if (hoff >= 0) c->heapalloc.release(hoff);
+        if (moff >= 0 && map_new) c->heapalloc.release(moff);
+        FAIL(c, PGVIMP_ENOMEM, "no heap room for %lld bytes of map/model data",
+             (long long)(bytes + (map_new ? sdf_bytes : 0)));
     }
-    char* base = c->heap + hoff;
-    double* model = (double*)(base + sdf_bytes);
+    char* base = coll ? c->heap + moff : nullptr;  // the SDF grid
+    double* model = (double*)(c->heap + hoff);
     std::vector<double> h(model_count, 0.0);
     int64_t o = 0;
     PlanDev pd{};
@@ -653,7 +700,9 @@ int pgvimp_add_plan(pgvimp_ctx* c, const pgvimp_problem* p, int32_t* plan_out) {
             for (int k = 0; k < PGVIMP_ARM_DOF; ++k) f[3 + PGVIMP_ARM_DOF + ns + k] = p->fk_axes[k];
             for (int s = 0; s < ns; ++s) f[3 + 2 * PGVIMP_ARM_DOF + ns + s] = p->fk_sphere_link[s];
         }
-        HCK(c, hipMemcpyAsync(base, p->sdf, (size_t)p->gx * p->gy * p->gz * 4, hipMemcpyHostToDevice, c->stream));
+        if (map_new)
+            HCK(c, hipMemcpyAsync(base, p->sdf, (size_t)p->gx * p->gy * p->gz * 4, hipMemcpyHostToDevice,
+                                  c->stream));
     }
     HCK(c, hipMemcpyAsync(model, h.data(), model_count * 8, hipMemcpyHostToDevice, c->stream));
     pd.active = 1;
@@ -708,6 +757,11 @@ int pgvimp_add_plan(pgvimp_ctx* c, const pgvimp_problem* p, int32_t* plan_out) {
     ph.off = soff;
     ph.coff = coff;
     ph.heap_off = hoff;
+    ph.map_off = moff;
+    if (coll) {
+        if (map_new) c->maps[mkey] = MapEntry{moff, 0};
+        c->maps[mkey].refs += 1;
+    }
     ph.coll_kind = p->coll_kind;
     ph.d = pd.d;
     ph.p = p->gh_points;
@@ -747,6 +801,15 @@ int pgvimp_remove_plan(pgvimp_ctx* c, int32_t plan) {
     c->states.release(ph.off);
     c->cstates.release(ph.coff);
     c->heapalloc.release(ph.heap_off);
+    if (ph.map_off >= 0)
+        for (auto it = c->maps.begin(); it != c->maps.end(); ++it)
+            if (it->second.off == ph.map_off) {
+                if (--it->second.refs == 0) {
+                    c->heapalloc.release(it->second.off);
+                    c->maps.erase(it);
+                }
+                break;
+            }
     ph = PlanHost{};
     return PGVIMP_OK;
 }

@@ -112,3 +112,32 @@ def test_slr_round_rejects_bad_nominal_and_keeps_plan(pg):
                         nominal_cov=p["nominal_cov"])
     st = pg.pgvimp_prox_step(ctx, 5)[0]
     assert st["iters_done"] == 3 and st["iters_left"] == 0
+
+
+def test_plans_with_one_map_share_it_and_keep_their_results():
+    """Plans whose SDF grids are identical share one device copy; removing
+    one of them leaves the others' results unchanged (bitwise against the
+    plan alone)."""
+    import paper_2411_03416_amd as pg
+    a = workloads.point2d_problem(0, N=40)
+    b = workloads.point2d_problem(0, N=27)  # same map as a
+    c = workloads.point2d_problem(1, N=33)
+    print("shared maps: plans 40/27 on map 0, 33 on map 1", flush=True)
+    ctx = pg.pgvimp_create([a, b, c], precision=pg.FP64, use_graph=False)
+    alone = pg.pgvimp_create([b], precision=pg.FP64, use_graph=False)
+    for x in (pg.pgvimp_factor_expectations(ctx, 1), pg.pgvimp_factor_expectations(alone, 0)):
+        assert np.abs(x[0]).max() >= 0
+    e_mix = pg.pgvimp_factor_expectations(ctx, 1)
+    e_alone = pg.pgvimp_factor_expectations(alone, 0)
+    assert all(np.array_equal(u, v) for u, v in zip(e_mix, e_alone))
+    pg.pgvimp_remove_plan(ctx, 0)  # the map stays for plan 1
+    pg.pgvimp_prox_step(ctx, 3)
+    pg.pgvimp_prox_step(alone, 3)
+    s_mix = pg.pgvimp_get_state(ctx, 1)
+    s_alone = pg.pgvimp_get_state(alone, 0)
+    assert all(np.array_equal(u, v) for u, v in zip(s_mix, s_alone))
+    # a new plan on the released map's neighbour slot and on map 0 again
+    pid = pg.pgvimp_add_plan(ctx, workloads.point2d_problem(0, N=40))
+    e_new = pg.pgvimp_factor_expectations(ctx, pid)
+    e_ref = pg.pgvimp_factor_expectations(pg.pgvimp_create([a], precision=pg.FP64, use_graph=False), 0)
+    assert all(np.array_equal(u, v) for u, v in zip(e_new, e_ref))
