@@ -27,6 +27,12 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-ffp-contract=fast", "-Wno-unused-result", "-Wno-cuda-compat", "-Wno-zero-length-array",
 ]
+# Per-source flags.  The expectation kernels contract a * b + c into FMAs
+# only within one expression: both launch shapes then round every node
+# value and moment update the same way, whether the node value is kept in a
+# register or passed through LDS (cross-statement contraction would fuse
+# psi = w h^2 with psi - c in one shape only).
+SOURCE_FLAGS = {"expect.hip": ["-ffp-contract=on"]}
 # extra flags for a resource report (set PGVIMP_RESOURCE_REPORT=1)
 if os.environ.get("PGVIMP_RESOURCE_REPORT"):
     FLAGS += ["-Rpass-analysis=kernel-resource-usage"]
@@ -52,7 +58,7 @@ def _compile(src: str, incremental: bool = False) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     if incremental and not _stale(src, obj):
         return obj
-    cmd = [hipcc(), *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [hipcc(), *FLAGS, *SOURCE_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile of {src} failed:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

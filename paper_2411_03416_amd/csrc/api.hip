@@ -328,6 +328,8 @@ int validate_problem(pgvimp_ctx* c, const pgvimp_problem* p) {
     const bool is3 = p->coll_kind != PGVIMP_COLL_POINT2D;
     if (!p->sdf || p->gx < 2 || p->gy < 2 || (is3 ? p->gz < 2 : p->gz != 1))
         FAIL(c, PGVIMP_EINVAL, "bad SDF grid");
+    // lookups address the grid with 32-bit byte offsets
+    if ((int64_t)p->gx * p->gy * p->gz * 4 > INT32_MAX) FAIL(c, PGVIMP_EINVAL, "SDF grid over 2 GiB");
     if (!(p->cell > 0.0) || !std::isfinite(p->hinge_eps) || !(p->obs_weight >= 0.0))
         FAIL(c, PGVIMP_EINVAL, "bad grid cell or hinge parameters");
     if (p->n_spheres < 1 || p->n_spheres > PGVIMP_MAX_SPHERES || !p->sphere_radius)

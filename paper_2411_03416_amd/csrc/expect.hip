@@ -76,13 +76,26 @@ __device__ __forceinline__ void axis_cell(R x, R o_ic, R inv_cell, R top, R last
     t = u - k;
 }
 
-// Grid values are read through global (not flat) address-space pointers.
-typedef const __attribute__((address_space(1))) float gfloat;
+// Grid values are read by raw buffer loads through a resource that spans
+// exactly the grid: 32-bit byte offsets (one VGPR per address), and an
+// offset past the grid reads 0 instead of faulting.
+struct Grid {
+    __amdgpu_buffer_rsrc_t rsrc;
+    __device__ void init(const float* g, int64_t count) {
+        // word 3 = 0x00020000: 32-bit data format, as raw dword loads need on CDNA
+        rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)g, (short)0, (int)(count * 4), 0x00020000);
+    }
+};
 // Two horizontally adjacent grid values (the cell's corners along x) in one
 // 8-byte load: the cell index is at most g - 2, so both lie in the row.
-typedef float f2u __attribute__((ext_vector_type(2), aligned(4)));
-typedef const __attribute__((address_space(1))) f2u gf2u;
-__device__ __forceinline__ f2u row2(gfloat* grid, uint32_t off) { return *(gf2u*)(grid + off); }
+typedef unsigned int u2v __attribute__((ext_vector_type(2)));
+struct f2 {
+    float x, y;
+};
+__device__ __forceinline__ f2 row2(const Grid& grid, uint32_t off) {
+    const u2v v = __builtin_amdgcn_raw_buffer_load_b64(grid.rsrc, off * 4u, 0, 0);
+    return f2{__uint_as_float(v.x), __uint_as_float(v.y)};
+}
 
 // Per-axis constants of a grid lookup in type R.
 template <typename R>
@@ -96,13 +109,13 @@ struct Axis {
 };
 
 template <typename R>
-__device__ __forceinline__ R sdf2(gfloat* grid, uint32_t gx, const Axis<R>& ax, const Axis<R>& ay, R ic, R x, R y) {
+__device__ __forceinline__ R sdf2(const Grid& grid, uint32_t gx, const Axis<R>& ax, const Axis<R>& ay, R ic, R x, R y) {
     uint32_t ix, iy;
     R tx, ty;
     axis_cell<R>(x, ax.o_ic, ic, ax.top, ax.last, ix, tx);
     axis_cell<R>(y, ay.o_ic, ic, ay.top, ay.last, iy, ty);
     const uint32_t o0 = iy * gx + ix;
-    const f2u r0 = row2(grid, o0), r1 = row2(grid, o0 + gx);
+    const f2 r0 = row2(grid, o0), r1 = row2(grid, o0 + gx);
     const R v00 = (R)r0.x, v01 = (R)r0.y, v10 = (R)r1.x, v11 = (R)r1.y;
     const R a = v00 + tx * (v01 - v00);
     const R b = v10 + tx * (v11 - v10);
@@ -110,7 +123,7 @@ __device__ __forceinline__ R sdf2(gfloat* grid, uint32_t gx, const Axis<R>& ax, 
 }
 
 template <typename R>
-__device__ __forceinline__ R sdf3(gfloat* grid, uint32_t gx, uint32_t gxy, const Axis<R>& ax, const Axis<R>& ay,
+__device__ __forceinline__ R sdf3(const Grid& grid, uint32_t gx, uint32_t gxy, const Axis<R>& ax, const Axis<R>& ay,
                                   const Axis<R>& az, R ic, R x, R y, R z) {
     uint32_t ix, iy, iz;
     R tx, ty, tz;
@@ -118,8 +131,8 @@ __device__ __forceinline__ R sdf3(gfloat* grid, uint32_t gx, uint32_t gxy, const
     axis_cell<R>(y, ay.o_ic, ic, ay.top, ay.last, iy, ty);
     axis_cell<R>(z, az.o_ic, ic, az.top, az.last, iz, tz);
     const uint32_t o = iz * gxy + iy * gx + ix;
-    const f2u r00 = row2(grid, o), r01 = row2(grid, o + gx), r10 = row2(grid, o + gxy),
-              r11 = row2(grid, o + gxy + gx);
+    const f2 r00 = row2(grid, o), r01 = row2(grid, o + gx), r10 = row2(grid, o + gxy),
+             r11 = row2(grid, o + gxy + gx);
     const R a0 = (R)r00.x + tx * ((R)r00.y - (R)r00.x);
     const R a1 = (R)r01.x + tx * ((R)r01.y - (R)r01.x);
     const R a2 = (R)r10.x + tx * ((R)r10.y - (R)r10.x);
@@ -145,12 +158,12 @@ struct Cost;
 
 template <typename R, int D>
 struct Cost<R, D, PGVIMP_COLL_POINT2D> {
-    gfloat* grid;
+    Grid grid;
     uint32_t gx;
     Axis<R> ax, ay;
     R ic, er, w;
     __device__ void init(const PlanDev& p) {
-        grid = (gfloat*)p.sdf;
+        grid.init(p.sdf, (int64_t)p.gx * p.gy * p.gz);
         gx = (uint32_t)p.gx;
         ax.init(p.origin[0], p.inv_cell, p.gx);
         ay.init(p.origin[1], p.inv_cell, p.gy);
@@ -163,12 +176,12 @@ struct Cost<R, D, PGVIMP_COLL_POINT2D> {
 
 template <typename R, int D>
 struct Cost<R, D, PGVIMP_COLL_POINT3D> {
-    gfloat* grid;
+    Grid grid;
     uint32_t gx, gxy;
     Axis<R> ax, ay, az;
     R ic, er, w;
     __device__ void init(const PlanDev& p) {
-        grid = (gfloat*)p.sdf;
+        grid.init(p.sdf, (int64_t)p.gx * p.gy * p.gz);
         gx = (uint32_t)p.gx;
         gxy = (uint32_t)p.gx * (uint32_t)p.gy;
         ax.init(p.origin[0], p.inv_cell, p.gx);
@@ -186,7 +199,7 @@ struct Cost<R, D, PGVIMP_COLL_POINT3D> {
 // Serial chain of PGVIMP_ARM_DOF revolute joints; spheres sorted by link.
 template <typename R, int D>
 struct Cost<R, D, PGVIMP_COLL_ARM3D> {
-    gfloat* grid;
+    Grid grid;
     const double* fk;
     const double* rad;
     uint32_t gx, gxy;
@@ -194,7 +207,7 @@ struct Cost<R, D, PGVIMP_COLL_ARM3D> {
     Axis<R> ax, ay, az;
     R ic, eps, w;
     __device__ void init(const PlanDev& p) {
-        grid = (gfloat*)p.sdf;
+        grid.init(p.sdf, (int64_t)p.gx * p.gy * p.gz);
         gx = (uint32_t)p.gx;
         gxy = (uint32_t)p.gx * (uint32_t)p.gy;
         ax.init(p.origin[0], p.inv_cell, p.gx);
@@ -283,92 +296,223 @@ __device__ __forceinline__ bool chol_packed(const double* A, double* L) {
     return ok;
 }
 
-// Shape of one instantiation: F factors per workgroup of T = 256 threads
-// (F < T at small batches: more threads per factor shorten each thread's
-// chain of dependent node evaluations), node
-// evaluations per factor NE (the centre first in mixed mode), chunks of CH
-// evaluations whose LDS rows have an odd stride CHS (no bank conflicts when
-// thread f walks its row).
+// Shape of one instantiation: F factors per workgroup of T = 256 threads,
+// node evaluations per factor NE (the centre first in mixed mode), chunks
+// of CH evaluations whose LDS rows have an odd stride CHS (no bank
+// conflicts when thread f walks its row).
 template <typename R, int D, int P, int F, int KIND>
 struct ExpectShape {
     static constexpr int T = 256;
     static constexpr int NODES = ipow(P, D);
     static constexpr bool CENTRE = sizeof(R) == 4 && P >= 2;
     static constexpr int NE = NODES + (CENTRE ? 1 : 0);
-    static constexpr int PS = D + D * (D + 1) / 2;  // mu, then L packed by rows
+    static constexpr int NS2 = D * (D + 1) / 2;
+    static constexpr int PS = D + NS2;  // mu, then L packed by rows
     static constexpr int CHMAX = ((expect_lds(KIND) / (int)sizeof(R)) / F - 1) | 1;  // odd, < budget
     static constexpr int CH = cmin(NE, CHMAX);
     static constexpr int CHS = CH | 1;
     static constexpr int NCH = (NE + CH - 1) / CH;
-    // rule points of every evaluation in an LDS table when it is small
+    // rule points and weights of every evaluation in an LDS table when small
     static constexpr bool TAB = NE * D <= 1024;
+    static constexpr int TS = D + 1;  // table row: xi[0..D-1], W
 };
 
-template <typename R, int D, int P, int KIND, int F>
-__global__ void __launch_bounds__((ExpectShape<R, D, P, F, KIND>::T))
-    expect_kernel(DevState st, int plan_lo, int plan_hi, int tiles, int respect_budget) {
-    using Sh = ExpectShape<R, D, P, F, KIND>;
-    constexpr int T = Sh::T, NE = Sh::NE, PS = Sh::PS, CH = Sh::CH, CHS = Sh::CHS, NCH = Sh::NCH;
-    constexpr bool CENTRE = Sh::CENTRE;
+// Rule point xi and weight W of evaluation e: the centre (xi = 0) first in
+// mixed mode, then the tensor nodes with coordinate 0 varying fastest.  x1
+// and w1 are the 1-D rule of p points.
+template <typename R, int D, int P, bool CENTRE>
+__device__ __forceinline__ void rule_point(const R* x1, const R* w1, uint32_t e, R* xi, R& W) {
+    uint32_t node = CENTRE ? (e == 0 ? 0u : e - 1u) : e;
+    W = R(1);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        const uint32_t q = node % (uint32_t)P;
+        node /= (uint32_t)P;
+        xi[a] = (CENTRE && e == 0) ? R(0) : x1[q];
+        W *= w1[q];
+    }
+}
+
+// x = mu + L xi (L lower, packed by rows), with explicit FMAs
+template <typename R, int D>
+__device__ __forceinline__ void node_point(const R* mu, const R* L, const R* xi, R* x) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        R v = mu[a];
+#pragma unroll
+        for (int c = 0; c <= a; ++c) v = fma(L[a * (a + 1) / 2 + c], xi[c], v);
+        x[a] = v;
+    }
+}
+
+// Running moments of one factor: s0 = sum W (psi - c), s1 = sum W (psi - c)
+// xi, S2 = sum W (psi - c) xi xi^T (upper triangle by rows), added in node
+// order by both kernels with the same operations (this file is built with
+// contraction within expressions only, so psi - c is never fused with the
+// product that formed psi: that product is in registers in one kernel and
+// behind an LDS store in the other); the FMAs are explicit.
+template <typename R, int D>
+struct Moments {
+    static constexpr int NS2 = D * (D + 1) / 2;
+    R s0, s1[D], S2[NS2];
+    __device__ void zero() {
+        s0 = R(0);
+#pragma unroll
+        for (int a = 0; a < D; ++a) s1[a] = R(0);
+#pragma unroll
+        for (int e = 0; e < NS2; ++e) S2[e] = R(0);
+    }
+    __device__ __forceinline__ void add(R v, R centre, R W, const R* xi) {
+        const R wp = W * (v - centre);
+        s0 = s0 + wp;
+        int t = 0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            const R wa = wp * xi[a];
+            s1[a] = s1[a] + wa;
+#pragma unroll
+            for (int c = a; c < D; ++c, ++t) S2[t] = fma(wa, xi[c], S2[t]);
+        }
+    }
+};
+
+// The factor's covariance (lower triangle, configuration coordinates) from
+// the marginals and its FP64 Cholesky factor; false if it is not PD.
+template <int D>
+__device__ __forceinline__ bool factor_chol(const DevState& st, const PlanDev& p, int64_t s, double* L) {
     constexpr int NS2 = D * (D + 1) / 2;
+    double A[NS2];
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int c = 0; c <= a; ++c)
+            A[a * (a + 1) / 2 + c] = st.SD[(int64_t)(p.coll_index[a] * st.n + p.coll_index[c]) * st.S + s];
+    return chol_packed<D>(A, L);
+}
+
+// FP64 epilogue: Li = L^-1 (lower), E = s0 + c, g = Li^T s1,
+// H = Li^T (S2 - s0 I) Li; NaN outputs for a factor that is not PD.
+template <typename R, int D>
+__device__ __forceinline__ void store_factor(const DevState& st, int64_t s, bool ok, const double* L,
+                                             const Moments<R, D>& m, R centre) {
+    const int64_t S = st.S;
+    if (!ok) {
+        st.Ecol[s] = NAN;
+#pragma unroll
+        for (int a = 0; a < D; ++a) st.gcol[a * S + s] = NAN;
+#pragma unroll
+        for (int a = 0; a < D * D; ++a) st.Hcol[a * S + s] = NAN;
+        return;
+    }
+    constexpr int NS2 = D * (D + 1) / 2;
+    // Li packed by rows like L: Li[a(a+1)/2 + c], c <= a
+    double Li[NS2];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        const double inv = 1.0 / L[a * (a + 1) / 2 + a];
+        Li[a * (a + 1) / 2 + a] = inv;
+#pragma unroll
+        for (int c = 0; c < a; ++c) {
+            double v = 0.0;
+#pragma unroll
+            for (int q = c; q < a; ++q) v = fma(L[a * (a + 1) / 2 + q], Li[q * (q + 1) / 2 + c], v);
+            Li[a * (a + 1) / 2 + c] = -v * inv;
+        }
+    }
+    const double e0 = (double)m.s0;
+    // M = S2 - s0 I from the upper-triangle accumulators
+    auto M = [&](int a, int c) {
+        const int lo2 = a < c ? a : c, hi2 = a < c ? c : a;
+        const int t = lo2 * D - lo2 * (lo2 - 1) / 2 + (hi2 - lo2);
+        return (double)m.S2[t] - (a == c ? e0 : 0.0);
+    };
+    st.Ecol[s] = e0 + (double)centre;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        double v = 0.0;
+#pragma unroll
+        for (int q = a; q < D; ++q) v = fma(Li[q * (q + 1) / 2 + a], (double)m.s1[q], v);
+        st.gcol[a * S + s] = v;
+    }
+    // row a of H: t = (Li^T M)_a = sum_q Li[q][a] M[q][.], then H_ac = t Li[.][c]
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        double t[D];
+#pragma unroll
+        for (int r = 0; r < D; ++r) {
+            double v = 0.0;
+#pragma unroll
+            for (int q = a; q < D; ++q) v = fma(Li[q * (q + 1) / 2 + a], M(q, r), v);
+            t[r] = v;
+        }
+#pragma unroll
+        for (int c = a; c < D; ++c) {
+            double v = 0.0;
+#pragma unroll
+            for (int r = c; r < D; ++r) v = fma(t[r], Li[r * (r + 1) / 2 + c], v);
+            st.Hcol[(a * D + c) * S + s] = v;
+            st.Hcol[(c * D + a) * S + s] = v;
+        }
+    }
+}
+
+// Block b of a launch serves plan plan_lo + 8*slot + (b mod 8) (slot =
+// (b / 8) / tiles) and its rounds of F factors starting at tile (b / 8) mod
+// tiles; false if the block has nothing to do.
+__device__ __forceinline__ bool expect_block_plan(const DevState& st, int plan_lo, int plan_hi, int tiles,
+                                                  int respect_budget, int kind, int gh, int& pid, int& tile) {
+    const int b = blockIdx.x;
+    const int k = b / kNumXcd;
+    pid = plan_lo + (k / tiles) * kNumXcd + b % kNumXcd;
+    tile = k % tiles;
+    if (pid >= plan_hi) return false;
+    const PlanDev& p = st.plans[pid];
+    if (!p.active || p.coll_kind != kind || p.gh_points != gh) return false;
+    return !(respect_budget && p.iters_left <= 0);
+}
+
+// Small batches: F factors per workgroup of 256 threads in three stages
+// (see the top of this file).
+template <typename R, int D, int P, int KIND, int F>
+__global__ void __launch_bounds__(256) expect_kernel(DevState st, int plan_lo, int plan_hi, int tiles,
+                                                     int respect_budget) {
+    using Sh = ExpectShape<R, D, P, F, KIND>;
+    constexpr int T = Sh::T, NE = Sh::NE, PS = Sh::PS, CH = Sh::CH, CHS = Sh::CHS, NCH = Sh::NCH, TS = Sh::TS;
+    constexpr bool CENTRE = Sh::CENTRE;
+    constexpr int NS2 = Sh::NS2;
     __shared__ R psi[F * CHS];
     __shared__ R par[F * PS];
     __shared__ R xs[P], ws[P];
-    __shared__ R xtab[Sh::TAB ? NE * D : 1];  // xi of evaluation e at [e * D + a]
+    __shared__ R ntab[Sh::TAB ? NE * TS : 1];  // row e: xi of evaluation e, then its weight
 
-    const int b = blockIdx.x;
-    const int k = b / kNumXcd;
-    const int pid = plan_lo + (k / tiles) * kNumXcd + b % kNumXcd;
-    if (pid >= plan_hi) return;
+    int pid, tile;
+    if (!expect_block_plan(st, plan_lo, plan_hi, tiles, respect_budget, KIND, P, pid, tile)) return;
     const PlanDev& p = st.plans[pid];
-    if (!p.active || p.coll_kind != KIND || p.gh_points != P) return;
-    if (respect_budget && p.iters_left <= 0) return;
     const int tid = threadIdx.x;
     const int N = p.N;
     const int lo = p.coll_states == 1 ? 1 : 0;
     const int hi = p.coll_states == 1 ? N - 1 : N;
     const int64_t S = st.S;
-    const int n = st.n;
-    const R* xg = Tab<R>::x(st) + P * kMaxGH;
     if (tid < P) {
-        xs[tid] = xg[tid];
+        xs[tid] = Tab<R>::x(st)[P * kMaxGH + tid];
         ws[tid] = Tab<R>::w(st)[P * kMaxGH + tid];
     }
-    // rule point of evaluation e (the centre, then the tensor nodes with
-    // coordinate 0 varying fastest)
-    auto point = [&](const R* x1, uint32_t e, R* xi) {
-        uint32_t node = CENTRE ? (e == 0 ? 0u : e - 1u) : e;
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-            const uint32_t q = node % (uint32_t)P;
-            node /= (uint32_t)P;
-            xi[a] = (CENTRE && e == 0) ? R(0) : x1[q];
-        }
-    };
-    if (Sh::TAB)
-        for (int e = tid; e < NE; e += T) point(xg, (uint32_t)e, xtab + e * D);
+    if (Sh::TAB) {
+        __syncthreads();
+        for (int e = tid; e < NE; e += T) rule_point<R, D, P, CENTRE>(xs, ws, (uint32_t)e, ntab + e * TS, ntab[e * TS + D]);
+    }
     Cost<R, D, KIND> cost;
     cost.init(p);
 
-    for (int i0 = (k % tiles) * F; i0 < N; i0 += tiles * F) {
+    for (int i0 = tile * F; i0 < N; i0 += tiles * F) {
         // A: marginal of factor i0 + tid, its FP64 Cholesky factor, mu and L to LDS
         const int i = i0 + tid;
         const bool mine = tid < F && i >= lo && i < hi;
         const int64_t s = p.off + i;
-        // the factor's covariance (lower triangle) and its FP64 Cholesky factor
-        auto factor = [&](double* L) {
-            double A[NS2];
-#pragma unroll
-            for (int a = 0; a < D; ++a)
-#pragma unroll
-                for (int c = 0; c <= a; ++c)
-                    A[a * (a + 1) / 2 + c] = st.SD[(int64_t)(p.coll_index[a] * n + p.coll_index[c]) * S + s];
-            return chol_packed<D>(A, L);
-        };
         if (tid < F) {
             double L[NS2];
             if (mine) {
-                factor(L);
+                factor_chol<D>(st, p, s, L);
 #pragma unroll
                 for (int a = 0; a < D; ++a) par[tid * PS + a] = (R)st.mu[(int64_t)p.coll_index[a] * S + s];
             } else {
@@ -380,12 +524,9 @@ __global__ void __launch_bounds__((ExpectShape<R, D, P, F, KIND>::T))
 #pragma unroll
             for (int e = 0; e < NS2; ++e) par[tid * PS + D + e] = (R)L[e];
         }
-        R s0 = R(0), s1[D], S2[NS2], centre = R(0);
-#pragma unroll
-        for (int a = 0; a < D; ++a) s1[a] = R(0);
-#pragma unroll
-        for (int e = 0; e < NS2; ++e) S2[e] = R(0);
-        const int nf = min(F, hi - i0);  // factors of this round (those below lo are skipped)
+        Moments<R, D> m;
+        m.zero();
+        R centre = R(0);
 
         for (int ch = 0; ch < NCH; ++ch) {
             __syncthreads();
@@ -399,22 +540,16 @@ __global__ void __launch_bounds__((ExpectShape<R, D, P, F, KIND>::T))
                 const uint32_t f = (uint32_t)it / (uint32_t)CH;
                 const uint32_t jj = (uint32_t)it - f * (uint32_t)CH;
                 const uint32_t e = min((uint32_t)(ch * CH) + jj, (uint32_t)(NE - 1));
-                R xi[D];
+                R xi[D], W;
                 if (Sh::TAB) {
 #pragma unroll
-                    for (int a = 0; a < D; ++a) xi[a] = xtab[e * D + a];
+                    for (int a = 0; a < D; ++a) xi[a] = ntab[e * TS + a];
                 } else {
-                    point(xs, e, xi);
+                    rule_point<R, D, P, CENTRE>(xs, ws, e, xi, W);
                 }
                 const R* pf = par + f * PS;
                 R x[D];
-#pragma unroll
-                for (int a = 0; a < D; ++a) {
-                    R v = pf[a];
-#pragma unroll
-                    for (int c = 0; c <= a; ++c) v += pf[D + a * (a + 1) / 2 + c] * xi[c];
-                    x[a] = v;
-                }
+                node_point<R, D>(pf, pf + D, xi, x);
                 psi[f * CHS + jj] = cost(x);
             }
             __syncthreads();
@@ -430,91 +565,99 @@ __global__ void __launch_bounds__((ExpectShape<R, D, P, F, KIND>::T))
                         centre = v;
                         continue;
                     }
-                    int node = CENTRE ? e - 1 : e;
-                    R xi[D], W = R(1);
+                    R xi[D], W;
+                    if (Sh::TAB) {
 #pragma unroll
-                    for (int a = 0; a < D; ++a) {
-                        const int q = node % P;
-                        node /= P;
-                        xi[a] = xs[q];
-                        W *= ws[q];
+                        for (int a = 0; a < D; ++a) xi[a] = ntab[e * TS + a];
+                        W = ntab[e * TS + D];
+                    } else {
+                        rule_point<R, D, P, CENTRE>(xs, ws, (uint32_t)e, xi, W);
                     }
-                    const R wp = W * (v - centre);
-                    s0 += wp;
-                    int t = 0;
-#pragma unroll
-                    for (int a = 0; a < D; ++a) {
-                        const R wa = wp * xi[a];
-                        s1[a] += wa;
-#pragma unroll
-                        for (int c = a; c < D; ++c) S2[t++] += wa * xi[c];
-                    }
+                    m.add(v, centre, W, xi);
                 }
             }
         }
-        // FP64 epilogue: Li = L^-1 (lower), g = Li^T s1, H = Li^T (S2 - s0 I) Li
-        // (the factor is formed again: cheaper than holding it through B and C)
+        // the factor is formed again: cheaper than holding it through B and C
         if (mine) {
             double L[NS2];
-            if (!factor(L)) {
-                st.Ecol[s] = NAN;
-#pragma unroll
-                for (int a = 0; a < D; ++a) st.gcol[a * S + s] = NAN;
-#pragma unroll
-                for (int a = 0; a < D * D; ++a) st.Hcol[a * S + s] = NAN;
-            } else {
-                // Li packed by rows like L: Li[a(a+1)/2 + c], c <= a
-                double Li[NS2];
-#pragma unroll
-                for (int a = 0; a < D; ++a) {
-                    const double inv = 1.0 / L[a * (a + 1) / 2 + a];
-                    Li[a * (a + 1) / 2 + a] = inv;
-#pragma unroll
-                    for (int c = 0; c < a; ++c) {
-                        double v = 0.0;
-#pragma unroll
-                        for (int q = c; q < a; ++q) v = fma(L[a * (a + 1) / 2 + q], Li[q * (q + 1) / 2 + c], v);
-                        Li[a * (a + 1) / 2 + c] = -v * inv;
-                    }
-                }
-                const double e0 = (double)s0;
-                // M = S2 - s0 I from the upper-triangle accumulators
-                auto M = [&](int a, int c) {
-                    const int lo2 = a < c ? a : c, hi2 = a < c ? c : a;
-                    const int t = lo2 * D - lo2 * (lo2 - 1) / 2 + (hi2 - lo2);
-                    return (double)S2[t] - (a == c ? e0 : 0.0);
-                };
-                st.Ecol[s] = e0 + (double)centre;
-#pragma unroll
-                for (int a = 0; a < D; ++a) {
-                    double v = 0.0;
-#pragma unroll
-                    for (int q = a; q < D; ++q) v = fma(Li[q * (q + 1) / 2 + a], (double)s1[q], v);
-                    st.gcol[a * S + s] = v;
-                }
-                // row a of H: t = (Li^T M)_a = sum_q Li[q][a] M[q][.], then H_ac = t Li[.][c]
-#pragma unroll
-                for (int a = 0; a < D; ++a) {
-                    double t[D];
-#pragma unroll
-                    for (int r = 0; r < D; ++r) {
-                        double v = 0.0;
-#pragma unroll
-                        for (int q = a; q < D; ++q) v = fma(Li[q * (q + 1) / 2 + a], M(q, r), v);
-                        t[r] = v;
-                    }
-#pragma unroll
-                    for (int c = a; c < D; ++c) {
-                        double v = 0.0;
-#pragma unroll
-                        for (int r = c; r < D; ++r) v = fma(t[r], Li[r * (r + 1) / 2 + c], v);
-                        st.Hcol[(a * D + c) * S + s] = v;
-                        st.Hcol[(c * D + a) * S + s] = v;
-                    }
-                }
-            }
+            const bool ok = factor_chol<D>(st, p, s, L);
+            store_factor<R, D>(st, s, ok, L, m, centre);
         }
         __syncthreads();  // LDS rows are rewritten by the next round
+    }
+}
+
+// Large batches: one factor per thread, 256 per workgroup; every lane
+// walks the same evaluation at the same time (weights and points are
+// uniform LDS reads), and the moments stay in registers.  Node values,
+// their order and the moment updates are those of expect_kernel, so both
+// give the same bits.
+template <typename R, int D, int P, int KIND>
+__global__ void __launch_bounds__(256) expect_lane_kernel(DevState st, int plan_lo, int plan_hi, int tiles,
+                                                          int respect_budget) {
+    using Sh = ExpectShape<R, D, P, 256, KIND>;
+    constexpr int T = 256, NE = Sh::NE, TS = Sh::TS;
+    constexpr bool CENTRE = Sh::CENTRE;
+    constexpr int NS2 = Sh::NS2;
+    static_assert(Sh::TAB, "the lane kernel needs the rule table");
+    __shared__ R xs[P], ws[P];
+    __shared__ R ntab[NE * TS];
+
+    int pid, tile;
+    if (!expect_block_plan(st, plan_lo, plan_hi, tiles, respect_budget, KIND, P, pid, tile)) return;
+    const PlanDev& p = st.plans[pid];
+    const int tid = threadIdx.x;
+    const int N = p.N;
+    const int lo = p.coll_states == 1 ? 1 : 0;
+    const int hi = p.coll_states == 1 ? N - 1 : N;
+    const int64_t S = st.S;
+    if (tid < P) {
+        xs[tid] = Tab<R>::x(st)[P * kMaxGH + tid];
+        ws[tid] = Tab<R>::w(st)[P * kMaxGH + tid];
+    }
+    __syncthreads();
+    for (int e = tid; e < NE; e += T) rule_point<R, D, P, CENTRE>(xs, ws, (uint32_t)e, ntab + e * TS, ntab[e * TS + D]);
+    __syncthreads();
+    Cost<R, D, KIND> cost;
+    cost.init(p);
+
+    for (int i0 = tile * T; i0 < N; i0 += tiles * T) {
+        const int i = i0 + tid;
+        const bool mine = i >= lo && i < hi;
+        const int64_t s = p.off + i;
+        double L64[NS2];
+        bool ok = false;
+        R mu[D], L[NS2];
+        if (mine) {
+            ok = factor_chol<D>(st, p, s, L64);
+#pragma unroll
+            for (int a = 0; a < D; ++a) mu[a] = (R)st.mu[(int64_t)p.coll_index[a] * S + s];
+        } else {
+#pragma unroll
+            for (int e = 0; e < NS2; ++e) L64[e] = 0.0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) mu[a] = R(0);
+        }
+#pragma unroll
+        for (int e = 0; e < NS2; ++e) L[e] = (R)L64[e];
+        Moments<R, D> m;
+        m.zero();
+        R centre = R(0);
+        if (CENTRE) {
+            R x[D];
+            node_point<R, D>(mu, L, ntab, x);  // row 0: xi = 0
+            centre = cost(x);
+        }
+#pragma unroll 4
+        for (int e = CENTRE ? 1 : 0; e < NE; ++e) {
+            R xi[D];
+#pragma unroll
+            for (int a = 0; a < D; ++a) xi[a] = ntab[e * TS + a];
+            R x[D];
+            node_point<R, D>(mu, L, xi, x);
+            m.add(cost(x), centre, ntab[e * TS + D], xi);
+        }
+        if (mine) store_factor<R, D>(st, s, ok, L64, m, centre);
     }
 }
 
@@ -531,8 +674,12 @@ static hipError_t launch_one(const DevState& st, int plo, int phi, int maxN, int
     const int64_t blocks = slots * tiles * kNumXcd;
     if (blocks <= 0) return hipSuccess;
     if (blocks > INT32_MAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((expect_kernel<R, D, P, KIND, F>), dim3((unsigned)blocks),
-                       dim3(ExpectShape<R, D, P, F, KIND>::T), 0, s, st, plo, phi, tiles, respect);
+    if constexpr (F == 256 && ExpectShape<R, D, P, 256, KIND>::TAB)
+        hipLaunchKernelGGL((expect_lane_kernel<R, D, P, KIND>), dim3((unsigned)blocks), dim3(256), 0, s, st, plo,
+                           phi, tiles, respect);
+    else
+        hipLaunchKernelGGL((expect_kernel<R, D, P, KIND, F>), dim3((unsigned)blocks), dim3(256), 0, s, st, plo,
+                           phi, tiles, respect);
     return hipGetLastError();
 }
 

@@ -146,3 +146,23 @@ def test_mixed_rule_of_one_point_is_not_centred(pg):
     _, _, H, _ = pg.pgvimp_factor_expectations(ctx, 0)
     assert np.abs(H).max() > 0
     _check_plan(pg, ctx, 0, p, TOLMIX, "point2d p=1 mixed")
+
+
+@pytest.mark.parametrize("kind,p_gh", [("point2d", 3), ("point2d", 5), ("point2d", 10), ("point3d", 3)])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_workgroup_shapes_give_the_same_bits(pg, kind, p_gh, precision):
+    """The launch shape is chosen per launch from the batch: one factor per
+    thread (256 per workgroup) and the staged shapes (32-128 factors per
+    workgroup) must give bitwise identical results, so a plan's result does
+    not depend on the batch it runs in."""
+    make = workloads.point2d_problem if kind == "point2d" else workloads.point3d_problem
+    p = make(2, N=300, gh_points=p_gh)
+    print(f"shapes {kind} p={p_gh} precision={precision}", flush=True)
+    outs = []
+    for group in (256, 128, 64, 32):
+        ctx = pg.pgvimp_create([p], precision=precision, use_graph=False, expect_group=group)
+        outs.append(pg.pgvimp_factor_expectations(ctx, 0))
+        pg.pgvimp_destroy(ctx)
+    assert np.abs(outs[0][0]).max() > 0
+    for o in outs[1:]:
+        assert all(np.array_equal(u, v) for u, v in zip(outs[0], o))
