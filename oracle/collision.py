@@ -38,13 +38,10 @@ def collision_cost(prob, x):
         h = np.maximum(0.0, eps + prob["sphere_radius"][0] - dist)
         return w * h * h
     if kind == "arm3d":
-        out = np.zeros(x.shape[0])
-        for k in range(x.shape[0]):
-            c = fk.sphere_centres(x[k], prob["fk"])
-            dist = sdf.trilinear(prob["sdf"], prob["origin"], prob["cell"], c)
-            h = np.maximum(0.0, eps + prob["sphere_radius"] - dist)
-            out[k] = w * np.sum(h * h)
-        return out
+        c = fk.sphere_centres(x, prob["fk"])  # [K, S, 3]
+        dist = sdf.trilinear(prob["sdf"], prob["origin"], prob["cell"], c)
+        h = np.maximum(0.0, eps + prob["sphere_radius"][None, :] - dist)
+        return w * np.sum(h * h, axis=1)
     if kind == "none":
         return np.zeros(x.shape[0])
     raise ValueError(kind)
