@@ -1,0 +1,230 @@
+"""Step-by-step parity of the proximal iteration (Theorem 1, Alg. 1, App. C)
+and of Alg. 2's linearisation rounds, at the configurations' full sizes in
+the launch configuration the benchmark times (one context for the batch,
+iterations replayed as HIP graphs).
+
+At every iteration of every plan the oracle takes ONE step from the state
+the GPU holds (its mean, precision blocks and its own K^-1), and the GPU's
+next state is compared with the oracle's, block family by block family
+(mean, diagonal and super-diagonal precision blocks).  The bound is the
+measured floor: the same oracle step from that input perturbed by the
+backward error of a banded factorization (up to 2 n roundoffs per entry,
+see stepwise_oracle) moves the result by `floor`.  Per block family the
+ratio error / max(floor, f0) (f0 = eps in FP64, MIXED_FLOOR = 1e-6 for the
+FP32 quadrature of mixed mode) must have median <= 4 and 95th percentile
+<= FLOOR_MULT over all steps, and no step may exceed MAX_MULT.
+
+The step size must be the one the oracle chooses, except at a tie of the
+step rule (stepwise_oracle.decision_tie): there the state is compared at
+the GPU's step size.  At N = 750 the KL test is at the resolution of FP64
+in a sizeable share of steps: its trace term tr((K^-1 + H) Sigma') sums
+products of entries of order 1e4-1e8 to a result of order 1e3, and moves by
+several nats under the perturbation; at most MAX_TIES of the steps may be
+ties.
+"""
+import multiprocessing as mp
+import os
+
+import numpy as np
+import pytest
+
+import stepwise_oracle as so
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+EPS = float(np.finfo(float).eps)
+FLOOR_MULT = 32.0
+MAX_MULT = 4096.0
+MIXED_FLOOR = 1e-6
+MAX_TIES = 0.2
+REPORT = os.environ.get("PGVIMP_STEPWISE_REPORT") == "1"  # print the errors, assert nothing
+
+
+@pytest.fixture(scope="module")
+def pg():
+    import paper_2411_03416_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def pool():
+    # fresh interpreters (no GPU state), one BLAS thread each
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[k] = "1"
+    workers = max(1, min(16, os.cpu_count() or 1))
+    with mp.get_context("spawn").Pool(workers) as p:
+        yield p
+
+
+def _gpu_steps(pg, probs, precision, iters):
+    """Run `iters` single-iteration graph replays on all plans; per plan the
+    GPU's K^-1 and its state before every iteration and after the last."""
+    ctx = pg.pgvimp_create(probs, precision=precision, use_graph=True)
+    K = {k: pg.pgvimp_get_state(ctx, k) for k in range(len(probs))}
+    states = {k: [K[k]] for k in range(len(probs))}
+    stats = {k: [] for k in range(len(probs))}
+    for _ in range(iters):
+        st = pg.pgvimp_prox_step(ctx, 1)
+        for k in range(len(probs)):
+            states[k].append(pg.pgvimp_get_state(ctx, k))
+            stats[k].append(st[k])
+    pg.pgvimp_destroy(ctx)
+    return K, states, stats
+
+
+def _tasks(kind, seeds, K, states, stats, extra=None):
+    tasks, keys = [], []
+    for k, seed in enumerate(seeds):
+        for it in range(len(states[k]) - 1):
+            mu, D, U = states[k][it]
+            t = {"kind": kind, "seed": seed, "mu": mu, "D": D, "U": U, "KD": K[k][1], "KU": K[k][2],
+                 "rng": 1000 * k + it, "gpu_trials": stats[k][it]["trials"] if stats[k][it]["status"] == 0 else 0}
+            if extra:
+                t.update(extra[k])
+            tasks.append(t)
+            keys.append((k, it))
+    return tasks, keys
+
+
+def _check(label, keys, results, states, stats, precision, kinds, seeds):
+    """Compare every step; returns the per-step (family, ratio) records.
+
+    ratio = error / max(floor, f0): f0 = eps in FP64 and MIXED_FLOOR in
+    mixed mode (the FP32 quadrature's own effect on one step).  The bulk
+    must sit at the floor (median <= 4, 95th percentile <= FLOOR_MULT) and
+    no step may exceed MAX_MULT: a defect shows in every step, while
+    steps of an ill-conditioned iteration (floors up to order 1 at N = 750)
+    spread the tail."""
+    log = []
+    worst = {"mu": 0.0, "D": 0.0, "U": 0.0}
+    ratios = {"mu": [], "D": [], "U": []}
+    ties = 0
+    f0 = EPS if precision == 0 else MIXED_FLOOR
+    for (k, it), res in zip(keys, results):
+        ref, pert = res["ref"], res["pert"]
+        g = stats[k][it]
+        mu, D, U = states[k][it + 1]
+        if g["beta"] != ref["beta"] or g["trials"] != ref["trials"]:
+            bound = so.problem(kinds[k], seeds[k])["kl_bound"]
+            if not so.decision_tie(ref, pert, g["trials"], bound, precision == 1):
+                raise AssertionError(f"{label} plan {k} iteration {it}: step size {g['beta']} ({g['trials']} "
+                                     f"trials), oracle {ref['beta']} ({ref['trials']}); oracle trials "
+                                     f"{ref['trial_log']}; perturbed {pert['trial_log']}")
+            ties += 1  # the step rule is at a tie: either branch is right
+            log.append({"plan": k, "it": it, "tie": True, "gpu_trials": g["trials"], "trials": ref["trials"]})
+            if g["status"] != 0 or "forced" not in ref:
+                continue
+            # the state is still compared, at the GPU's step size
+            ref = dict(ref, **ref["forced"])
+            pert = dict(pert, **pert.get("forced", ref["forced"]))
+        e = so.errors({"mu": mu, "D": D, "U": U}, ref, pert)
+        log.append({"plan": k, "it": it, "beta": ref["beta"], "trials": ref["trials"], "err": e})
+        for fam, v in e.items():
+            worst[fam] = max(worst[fam], v["err"], v["err_blk"])
+            r = max(v["err"] / max(v["floor"], f0), v["err_blk"] / max(v["floor_blk"], f0))
+            ratios[fam].append(r)
+    stat = {fam: (float(np.median(r)), float(np.percentile(r, 95)), float(np.max(r)))
+            for fam, r in ratios.items() if r}
+    print(f"{label}: {len(keys)} steps, ties {ties}, worst error mu {worst['mu']:.2e} D {worst['D']:.2e} "
+          f"U {worst['U']:.2e}; error / floor median, p95, max: "
+          + ", ".join(f"{fam} {a:.2f} {b:.2f} {c:.3g}" for fam, (a, b, c) in stat.items()), flush=True)
+    if REPORT:
+        import json
+        os.makedirs("gpurun_out", exist_ok=True)
+        with open(os.path.join("gpurun_out", "stepwise_" + label.replace(" ", "_") + ".json"), "w") as f:
+            json.dump(log, f)
+        return stat
+    for fam, (med, p95, mx) in stat.items():
+        assert med <= 4.0 and p95 <= FLOOR_MULT and mx <= MAX_MULT, (label, fam, med, p95, mx)
+    assert ties <= max(1, int(MAX_TIES * len(keys))), f"{label}: {ties} ties"
+    return stat
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_config0_every_step(pg, pool, precision):
+    seeds = list(range(32))
+    probs = [workloads.config0_problem(seed=s) for s in seeds]
+    K, states, stats = _gpu_steps(pg, probs, precision, 20)
+    tasks, keys = _tasks("config0", seeds, K, states, stats)
+    _check(f"config 0 precision {precision}", keys, pool.map(so.one_step, tasks), states, stats, precision,
+           ["config0"] * 32, seeds)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_config1_every_step(pg, pool, precision):
+    """All 32 plans x 20 iterations of the benchmark workload."""
+    seeds = list(range(32))
+    probs = [workloads.config1_problem(seed=s) for s in seeds]
+    print(f"config 1 stepwise precision {precision}", flush=True)
+    K, states, stats = _gpu_steps(pg, probs, precision, 20)
+    tasks, keys = _tasks("config1", seeds, K, states, stats)
+    _check(f"config 1 precision {precision}", keys, pool.map(so.one_step, tasks, chunksize=4), states, stats,
+           precision, ["config1"] * 32, seeds)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_config2_arm_every_step(pg, pool, precision):
+    seeds = [0, 1]
+    probs = [workloads.config2_problem(seed=s) for s in seeds]
+    print(f"config 2 stepwise precision {precision}", flush=True)
+    K, states, stats = _gpu_steps(pg, probs, precision, 20)
+    tasks, keys = _tasks("config2", seeds, K, states, stats)
+    _check(f"config 2 precision {precision}", keys, pool.map(so.one_step, tasks), states, stats, precision,
+           ["config2"] * 2, seeds)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_config3_rounds_every_step(pg, pool, precision):
+    """Alg. 2 on four of the 64 quadrotor plans: 10 rounds x 15 iterations.
+    Each round's linearisation is checked against the oracle's regression
+    about the GPU's own marginals, and each iteration as above."""
+    seeds = [0, 3, 17, 42]
+    probs = [workloads.config3_problem(seed=s) for s in seeds]
+    print(f"config 3 stepwise precision {precision}, N = {[p['N'] for p in probs]}", flush=True)
+    ctx = pg.pgvimp_create(probs, precision=precision, use_graph=True)
+    n_rounds, iters = probs[0]["n_rounds"], probs[0]["n_iters"]
+    all_keys, all_res, all_states, all_stats, slr_err = [], [], {}, {}, 0.0
+    for r in range(n_rounds):
+        lin, K, states, stats, slr_tasks, gpu_lin = {}, {}, {}, {}, [], []
+        for k, p in enumerate(probs):
+            if r == 0:
+                mu_n, S_n = p["nominal_mean"], p["nominal_cov"]
+            else:
+                mu_n = pg.pgvimp_get_state(ctx, k)[0]
+                S_n = pg.pgvimp_marginals(ctx, k)[0]
+            A, a = (pg.ipgvimp_begin if r == 0 else pg.ipgvimp_next_round)(ctx, k, p)
+            slr_tasks.append({"kind": "config3", "seed": seeds[k], "mu": mu_n, "S": S_n, "rng": 100 * r + k})
+            gpu_lin.append((A, a))
+            lin[k] = {"A": A, "a": a}
+            K[k] = pg.pgvimp_get_state(ctx, k)
+            states[k] = [K[k]]
+            stats[k] = []
+        for (A, a), ((Ar, ar), (Ap, ap)), p in zip(gpu_lin, pool.map(so.slr_round, slr_tasks), probs):
+            # per state: error / max(floor, 4 eps), floor from the perturbed marginals
+            N = p["N"]
+            for X, Xr, Xp in ((A, Ar, Ap), (a, ar, ap)):
+                X, Xr, Xp = (np.asarray(y[:N - 1]).reshape(N - 1, -1) for y in (X, Xr, Xp))
+                nr = np.maximum(np.linalg.norm(Xr, axis=1), 1e-300)
+                err = np.linalg.norm(X - Xr, axis=1) / nr
+                fl = np.maximum(np.linalg.norm(Xp - Xr, axis=1) / nr, 4 * EPS)
+                slr_err = max(slr_err, float(err.max()))
+                assert (err / fl).max() <= 64.0, (r, float(err.max()), float((err / fl).max()))
+        for _ in range(iters):
+            st = pg.pgvimp_prox_step(ctx, 1)
+            for k in range(len(probs)):
+                states[k].append(pg.pgvimp_get_state(ctx, k))
+                stats[k].append(st[k])
+        tasks, keys = _tasks("config3", seeds, K, states, stats, extra=lin)
+        res = pool.map(so.one_step, tasks)
+        # (round, plan) pairs become the plans of one check over all rounds
+        P = len(probs)
+        all_keys += [(r * P + k, it) for k, it in keys]
+        all_res += res
+        for k in range(P):
+            all_states[r * P + k] = states[k]
+            all_stats[r * P + k] = stats[k]
+    pg.pgvimp_destroy(ctx)
+    print(f"config 3: linearisation error {slr_err:.2e}", flush=True)
+    _check(f"config 3 precision {precision}", all_keys, all_res, all_states, all_stats, precision,
+           ["config3"] * len(all_states), seeds * n_rounds)
