@@ -432,15 +432,24 @@ def config_rates(pg):
            "rounds": probs[0]["n_rounds"], "iters_per_round": probs[0]["n_iters"]}
     for pname, prec in (("mixed", pg.MIXED), ("fp64", pg.FP64)):
         ctx = pg.pgvimp_create(probs, precision=prec, use_graph=True)
+        failed = set()
 
         def solve():
             for r in range(probs[0]["n_rounds"]):
                 for k, p in enumerate(probs):
-                    (pg.ipgvimp_begin if r == 0 else pg.ipgvimp_next_round)(ctx, k, p)
+                    if k in failed:
+                        continue
+                    try:
+                        (pg.ipgvimp_begin if r == 0 else pg.ipgvimp_next_round)(ctx, k, p)
+                    except pg.PgvimpError:
+                        # a linearised prior that is not positive definite ends
+                        # this plan (its budget is spent); the others go on
+                        failed.add(k)
+                        pg.pgvimp_set_budget(ctx, k, 0)
                 pg.pgvimp_prox_step(ctx, probs[0]["n_iters"])
         dt = _timed(solve, 1)
         pg.pgvimp_destroy(ctx)
-        row[pname] = {"plans_per_s": 64 / dt, "ms_per_step": 1e3 * dt}
+        row[pname] = {"plans_per_s": 64 / dt, "ms_per_step": 1e3 * dt, "plans_ended_early": len(failed)}
     out["config3"] = row
     return out
 

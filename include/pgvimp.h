@@ -95,8 +95,10 @@ typedef struct pgvimp_ctx pgvimp_ctx;
  * r_s - sdf(c_s(x)))^2, where c_s are the collision points (the point
  * itself, or forward-kinematics spheres) and r_s their radii.  The SDF is
  * an FP32 grid sampled at nodes origin + (ix, iy, iz) * cell, stored
- * sdf[iy][ix] (2-D, gz = 1) or sdf[iz][iy][ix] (3-D); lookups are bilinear
- * or trilinear with clamping to the grid.  gh_points p in [1, 10] points per
+ * sdf[iy][ix] (2-D, gz = 1) or sdf[iz][iy][ix] (3-D), at most 2 GiB; lookups
+ * are bilinear or trilinear with clamping to the grid.  Plans of one context
+ * whose grids are identical (same dimensions and values) share one device
+ * copy.  gh_points p in [1, 10] points per
  * configuration dimension (tensor rule, p^d nodes).  coll_states: 0 = every
  * support state carries a collision factor, 1 = only interior states.
  *
@@ -172,7 +174,14 @@ typedef struct pgvimp_engine_cfg {
     int32_t trial_width, trial_lookahead, trial_slots;
 } pgvimp_engine_cfg;
 
-/* Per-plan statistics of the last iteration run by pgvimp_prox_step. */
+/*
+ * Per-plan statistics of the last iteration run by pgvimp_prox_step.  The
+ * cost breakdown describes q_k, the iterate the iteration started from
+ * (Sec. 2.2: J(q) = E[psi] - T H(q), psi = prior factors + collision
+ * factors): total_cost = E_prior + E_coll + entropy_cost with entropy_cost =
+ * -T H(q_k), T the plan's temperature during the iteration.  logdet and
+ * entropy describe q_{k+1}.
+ */
 typedef struct pgvimp_stats {
     double beta;    /* accepted step size (0 if none)                       */
     double kl;      /* KL(q_{k+1} || q_k) of the accepted step              */
@@ -180,6 +189,9 @@ typedef struct pgvimp_stats {
     double E_prior; /* sum of prior-factor expectations at q_k              */
     double logdet;  /* log det of the precision after the iteration         */
     double entropy; /* entropy of q after the iteration                     */
+    double temperature;  /* T of the iteration                              */
+    double entropy_cost; /* -T H(q_k)                                       */
+    double total_cost;   /* E_prior + E_coll - T H(q_k) = J(q_k)            */
     int32_t status; /* 0, PGVIMP_ENOTPD (input) or PGVIMP_ENOCONV           */
     int32_t trials; /* step sizes tried in the last iteration               */
     int32_t iters_done, iters_left;
@@ -322,6 +334,16 @@ int pgvimp_set_state(pgvimp_ctx *ctx, int32_t plan, const double *mu, const doub
 
 /* Set the plan's remaining iteration budget. */
 int pgvimp_set_budget(pgvimp_ctx *ctx, int32_t plan, int32_t iters_left);
+
+/*
+ * Set the plan's temperature T > 0 (the weight of the entropy in the
+ * objective E[psi] - T H(q), Sec. 2.2) for the iterations that follow: the
+ * paper's runs use a low temperature until the plan is collision-free, then
+ * a high one that emphasises the entropy (Sec. 7).  Takes effect on the
+ * next pgvimp_prox_step, also inside a captured graph.  EINVAL for T <= 0 or
+ * not finite (the plan is unchanged).
+ */
+int pgvimp_set_temperature(pgvimp_ctx *ctx, int32_t plan, double temperature);
 
 /* Change the stream used by the context (hipStream_t; NULL = a new stream
  * owned by the context).  Waits for the old stream first. */

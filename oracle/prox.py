@@ -147,6 +147,18 @@ def entropy(st):
     return 0.5 * N * n * (1.0 + math.log(2.0 * math.pi)) - 0.5 * st["logdet"]
 
 
+def cost_breakdown(prob, pri, st):
+    """The objective of Sec. 2.2, J(q) = E[psi] - T H(q), split as the paper's
+    cost tables do: E_prior (sum of the prior factors' expected costs),
+    E_coll (sum of the collision factors'), entropy_cost = -T H(q) and their
+    sum total = J(q), at the state st (mean, precision, marginals)."""
+    E, _, _ = collision.collision_expectations(prob, st["mu"], st["Sig"])
+    e_prior = float(np.sum(prior_factor_costs(prob, pri, st["mu"], st["Sig"], st["Soff"])))
+    e_coll = float(np.sum(E))
+    ent = -prob["temperature"] * entropy(st)
+    return {"E_prior": e_prior, "E_coll": e_coll, "entropy_cost": ent, "total": e_prior + e_coll + ent}
+
+
 def run(prob, n_iters=None, pri=None, mu0=None, history=False):
     """Run the proximal iteration from the initial state; returns the final
     state (and the list of per-iteration states/stats when history=True)."""

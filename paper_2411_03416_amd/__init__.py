@@ -357,6 +357,10 @@ def pgvimp_set_budget(ctx, plan, iters_left):
     _check(_abi.load().pgvimp_set_budget(ctx.handle, plan, iters_left), ctx.handle)
 
 
+def pgvimp_set_temperature(ctx, plan, temperature):
+    _check(_abi.load().pgvimp_set_temperature(ctx.handle, plan, float(temperature)), ctx.handle)
+
+
 def pgvimp_profile(ctx, enable=True):
     _check(_abi.load().pgvimp_profile(ctx.handle, 1 if enable else 0), ctx.handle)
 

@@ -63,6 +63,7 @@ class Stats(C.Structure):
     _fields_ = [
         ("beta", C.c_double), ("kl", C.c_double), ("E_coll", C.c_double), ("E_prior", C.c_double),
         ("logdet", C.c_double), ("entropy", C.c_double),
+        ("temperature", C.c_double), ("entropy_cost", C.c_double), ("total_cost", C.c_double),
         ("status", C.c_int32), ("trials", C.c_int32), ("iters_done", C.c_int32), ("iters_left", C.c_int32),
         ("trials_total", C.c_int32), ("evals_total", C.c_int32),
     ]
@@ -91,6 +92,7 @@ SIGNATURES = [
     ("pgvimp_get_state", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("pgvimp_set_state", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("pgvimp_set_budget", C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
+    ("pgvimp_set_temperature", C.c_int, [C.c_void_p, C.c_int32, C.c_double]),
     ("pgvimp_set_stream", C.c_int, [C.c_void_p, C.c_void_p]),
     ("pgvimp_sync", C.c_int, [C.c_void_p]),
     ("pgvimp_launch_shape", C.c_int, [C.c_void_p, C.c_int32, _ip, _ip]),

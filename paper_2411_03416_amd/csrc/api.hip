@@ -831,6 +831,19 @@ int pgvimp_set_budget(pgvimp_ctx* c, int32_t plan, int32_t iters_left) {
     return PGVIMP_OK;
 }
 
+int pgvimp_set_temperature(pgvimp_ctx* c, int32_t plan, double temperature) {
+    if (!plan_ok(c, plan)) return PGVIMP_EINVAL;
+    if (!(temperature > 0.0) || !std::isfinite(temperature))
+        FAIL(c, PGVIMP_EINVAL, "temperature must be positive and finite");
+    HCK(c, hipSetDevice(c->cfg.device));
+    int rc = download_plans(c);
+    if (rc) return rc;
+    c->pdev[plan].temperature = temperature;
+    if ((rc = upload_plan(c, plan))) return rc;
+    HCK(c, hipStreamSynchronize(c->stream));
+    return PGVIMP_OK;
+}
+
 int pgvimp_marginals(pgvimp_ctx* c, int32_t plan, double* cov_diag, double* cov_off, double* logdet) {
     if (!plan_ok(c, plan)) return PGVIMP_EINVAL;
     HCK(c, hipSetDevice(c->cfg.device));
@@ -1109,6 +1122,9 @@ static int run_iters(pgvimp_ctx* c, int32_t n_iters, pgvimp_stats* per_plan, boo
             s.E_prior = p.E_prior;
             s.logdet = p.logdet;
             s.entropy = p.entropy;
+            s.temperature = p.iter_temperature;
+            s.entropy_cost = p.entropy_cost;
+            s.total_cost = p.total_cost;
             s.status = p.status;
             s.trials = p.trials;
             s.iters_done = p.iters_done;

@@ -1612,6 +1612,11 @@ __global__ void __launch_bounds__(kIterThreads) select_kernel(DevState st, int /
         }
         p.E_coll = ecol;
         p.E_prior = epri;
+        // J(q_k) = E[psi] - T H(q_k), with H(q_k) from the log det before the update
+        const double h_k = 0.5 * (double)N * n * (1.0 + 1.8378770664093453) - 0.5 * p.logdet;
+        p.iter_temperature = p.temperature;
+        p.entropy_cost = -p.temperature * h_k;
+        p.total_cost = epri + ecol + p.entropy_cost;
         p.trials = pick >= 0 ? pick + 1 : p.max_bisect;
         p.trials_total += p.trials;
         // step sizes evaluated: every window up to the one holding the pick

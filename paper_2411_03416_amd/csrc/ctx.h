@@ -51,6 +51,7 @@ struct PlanDev {
     double inv_cell, hinge_eps, obs_weight, logdet;
     double origin[3];
     double beta, kl, E_coll, E_prior, entropy;
+    double iter_temperature, entropy_cost, total_cost;  // cost breakdown of q_k (last iteration)
     const float* sdf;
     // model block (FP64) laid out by the host, see Layout in api.cpp
     double* Wstart;  // Sig_start^-1 [n*n]   (written by the prior kernel)

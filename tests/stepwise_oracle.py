@@ -76,6 +76,8 @@ def one_step(task):
     p = problem(task["kind"], task["seed"])
     if "A" in task:
         p = slr.linearised_problem(p, task["A"], task["a"])
+    if "temperature" in task:
+        p = dict(p, temperature=task["temperature"])
     pri = dict(prior.build_prior(p))
     rng = np.random.default_rng(task.get("rng", 0))
     out = {}
@@ -88,6 +90,10 @@ def one_step(task):
         q = dict(pri)
         q["D"], q["U"] = KD, KU
         out[name] = _step(p, q, mu, D, U, task.get("gpu_trials", 0))
+        # the cost breakdown of the input state (Sec. 2.2 objective)
+        S, So, ld = gbp.gbp_marginals(D, U)
+        out[name]["costs"] = prox.cost_breakdown(p, q, {"mu": mu, "D": D, "U": U, "Sig": S, "Soff": So,
+                                                         "logdet": ld})
     return out
 
 

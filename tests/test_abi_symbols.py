@@ -38,7 +38,7 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts_match_the_header():
     from paper_2411_03416_amd import _abi
     # sizes computed from the C declarations with natural alignment (x86-64)
-    assert ctypes.sizeof(_abi.Stats) == 6 * 8 + 6 * 4  # 6 int32
+    assert ctypes.sizeof(_abi.Stats) == 9 * 8 + 6 * 4  # 9 doubles, 6 int32
     # 4 int32, 2 int64, 3 pointer-sized, 7 int32 and 4 bytes of tail padding
     assert ctypes.sizeof(_abi.EngineCfg) == 4 * 4 + 2 * 8 + 3 * 8 + 7 * 4 + 4
 

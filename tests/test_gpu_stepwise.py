@@ -12,7 +12,10 @@ backward error of a banded factorization (up to 2 n roundoffs per entry,
 see stepwise_oracle) moves the result by `floor`.  Per block family the
 ratio error / max(floor, f0) (f0 = eps in FP64, MIXED_FLOOR = 1e-6 for the
 FP32 quadrature of mixed mode) must have median <= 4 and 95th percentile
-<= FLOOR_MULT over all steps, and no step may exceed MAX_MULT.
+<= FLOOR_MULT over all steps, and no step may exceed MAX_MULT.  The cost
+breakdown of the objective at the step's starting state (E_prior, E_coll,
+-T H(q), J) is compared with the oracle's, relative to the objective's
+size, by the same median and 95th-percentile rule.
 
 The step size must be the one the oracle chooses, except at a tie of the
 step rule (stepwise_oracle.decision_tie): there the state is compared at
@@ -57,14 +60,19 @@ def pool():
         yield p
 
 
-def _gpu_steps(pg, probs, precision, iters):
+def _gpu_steps(pg, probs, precision, iters, schedule=None):
     """Run `iters` single-iteration graph replays on all plans; per plan the
-    GPU's K^-1 and its state before every iteration and after the last."""
+    GPU's K^-1 and its state before every iteration and after the last.
+    schedule[it], when given and not None, is the temperature set on every
+    plan before iteration it."""
     ctx = pg.pgvimp_create(probs, precision=precision, use_graph=True)
     K = {k: pg.pgvimp_get_state(ctx, k) for k in range(len(probs))}
     states = {k: [K[k]] for k in range(len(probs))}
     stats = {k: [] for k in range(len(probs))}
-    for _ in range(iters):
+    for it in range(iters):
+        if schedule is not None and schedule[it] is not None:
+            for k in range(len(probs)):
+                pg.pgvimp_set_temperature(ctx, k, schedule[it])
         st = pg.pgvimp_prox_step(ctx, 1)
         for k in range(len(probs)):
             states[k].append(pg.pgvimp_get_state(ctx, k))
@@ -79,7 +87,8 @@ def _tasks(kind, seeds, K, states, stats, extra=None):
         for it in range(len(states[k]) - 1):
             mu, D, U = states[k][it]
             t = {"kind": kind, "seed": seed, "mu": mu, "D": D, "U": U, "KD": K[k][1], "KU": K[k][2],
-                 "rng": 1000 * k + it, "gpu_trials": stats[k][it]["trials"] if stats[k][it]["status"] == 0 else 0}
+                 "rng": 1000 * k + it, "gpu_trials": stats[k][it]["trials"] if stats[k][it]["status"] == 0 else 0,
+                 "temperature": stats[k][it]["temperature"]}
             if extra:
                 t.update(extra[k])
             tasks.append(t)
@@ -97,14 +106,27 @@ def _check(label, keys, results, states, stats, precision, kinds, seeds):
     steps of an ill-conditioned iteration (floors up to order 1 at N = 750)
     spread the tail."""
     log = []
-    worst = {"mu": 0.0, "D": 0.0, "U": 0.0}
-    ratios = {"mu": [], "D": [], "U": []}
+    worst = {"mu": 0.0, "D": 0.0, "U": 0.0, "cost": 0.0}
+    ratios = {"mu": [], "D": [], "U": [], "cost": []}
     ties = 0
     f0 = EPS if precision == 0 else MIXED_FLOOR
     for (k, it), res in zip(keys, results):
         ref, pert = res["ref"], res["pert"]
         g = stats[k][it]
         mu, D, U = states[k][it + 1]
+        # cost breakdown of the state the iteration started from, each part
+        # relative to the size of the objective (|prior| + |collision| + |entropy|)
+        rc = ref["costs"]
+        scale = max(abs(rc["E_prior"]) + abs(rc["E_coll"]) + abs(rc["entropy_cost"]), 1e-300)
+        for name, gname in (("E_coll", "E_coll"), ("E_prior", "E_prior"), ("entropy_cost", "entropy_cost"),
+                            ("total", "total_cost")):
+            rv, pv = rc[name], pert["costs"][name]
+            r = (abs(g[gname] - rv) / scale) / max(abs(pv - rv) / scale, f0)
+            ratios["cost"].append(r)
+            if REPORT and r > FLOOR_MULT:
+                log.append({"plan": k, "it": it, "cost": name, "gpu": g[gname], "ref": rv, "pert": pv,
+                            "status": g["status"], "trials": g["trials"], "costs": rc})
+            worst["cost"] = max(worst["cost"], abs(g[gname] - rv) / scale)
         if g["beta"] != ref["beta"] or g["trials"] != ref["trials"]:
             bound = so.problem(kinds[k], seeds[k])["kl_bound"]
             if not so.decision_tie(ref, pert, g["trials"], bound, precision == 1):
@@ -127,7 +149,7 @@ def _check(label, keys, results, states, stats, precision, kinds, seeds):
     stat = {fam: (float(np.median(r)), float(np.percentile(r, 95)), float(np.max(r)))
             for fam, r in ratios.items() if r}
     print(f"{label}: {len(keys)} steps, ties {ties}, worst error mu {worst['mu']:.2e} D {worst['D']:.2e} "
-          f"U {worst['U']:.2e}; error / floor median, p95, max: "
+          f"U {worst['U']:.2e} costs {worst['cost']:.2e}; error / floor median, p95, max: "
           + ", ".join(f"{fam} {a:.2f} {b:.2f} {c:.3g}" for fam, (a, b, c) in stat.items()), flush=True)
     if REPORT:
         import json
@@ -136,7 +158,10 @@ def _check(label, keys, results, states, stats, precision, kinds, seeds):
             json.dump(log, f)
         return stat
     for fam, (med, p95, mx) in stat.items():
-        assert med <= 4.0 and p95 <= FLOOR_MULT and mx <= MAX_MULT, (label, fam, med, p95, mx)
+        # the costs of a state whose marginals are not resolved (precision
+        # condition 1e13 in the worst steps of configs 1 and 3) are not
+        # resolved either: their tail is not bounded, the bulk is
+        assert med <= 4.0 and p95 <= FLOOR_MULT and (fam == "cost" or mx <= MAX_MULT), (label, fam, med, p95, mx)
     assert ties <= max(1, int(MAX_TIES * len(keys))), f"{label}: {ties} ties"
     return stat
 
@@ -228,3 +253,19 @@ def test_config3_rounds_every_step(pg, pool, precision):
     print(f"config 3: linearisation error {slr_err:.2e}", flush=True)
     _check(f"config 3 precision {precision}", all_keys, all_res, all_states, all_stats, precision,
            ["config3"] * len(all_states), seeds * n_rounds)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_temperature_schedule_every_step(pg, pool, precision):
+    """Two-phase schedule of Sec. 7: low temperature until the plan is clear
+    of obstacles, then a high one that weights the entropy (T_low = 1,
+    T_high = 5, the quadrotor runs' values), 10 + 10 iterations on 8 config 0
+    plans; every step and the cost breakdown checked as above."""
+    seeds = list(range(8))
+    probs = [workloads.config0_problem(seed=s) for s in seeds]
+    schedule = [1.0] + [None] * 9 + [5.0] + [None] * 9
+    K, states, stats = _gpu_steps(pg, probs, precision, 20, schedule)
+    assert all(stats[k][12]["temperature"] == 5.0 and stats[k][3]["temperature"] == 1.0 for k in stats)
+    tasks, keys = _tasks("config0", seeds, K, states, stats)
+    _check(f"schedule precision {precision}", keys, pool.map(so.one_step, tasks), states, stats, precision,
+           ["config0"] * len(seeds), seeds)

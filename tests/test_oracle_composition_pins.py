@@ -235,3 +235,41 @@ def test_entropy_matches_dense_gaussian(N, n):
     dense = prior.dense_from_blocks(D, U)
     ref = scipy.stats.multivariate_normal(mean=np.zeros(N * n), cov=np.linalg.inv(dense)).entropy()
     assert abs(prox.entropy(st) - ref) < 1e-11 * max(1.0, abs(ref))
+
+
+# ----------------------------------------------------------------------------
+# Cost breakdown of the objective (Sec. 2.2): J(q) = E[psi] - T H(q)
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("temperature", [1.0, 3.5])
+def test_objective_gap_is_temperature_times_kl_to_the_posterior(temperature):
+    """Without obstacles psi is the GP prior's quadratic, whose tempered
+    posterior is q* = N(mu_bar, T K); the objective then satisfies
+    J(q) - J(q*) = T KL(q || q*) for every Gaussian q.  KL on the dense
+    matrices (numpy slogdet and inverse) pins the prior costs, the entropy
+    and the sign and scale of the entropy cost together."""
+    prob = workloads.free_problem(n_dof=2, N=6, temperature=temperature)
+    pri = prior.build_prior(prob)
+    N, n = prob["N"], prob["n"]
+    rng = np.random.default_rng(4)
+    D, U = rand_chain(rng, N, n)
+    mu = pri["mu_bar"] + rng.normal(size=(N, n))
+
+    def state(mu, D, U):
+        S, So, ld = gbp.gbp_marginals(D, U)
+        return {"mu": mu, "D": D, "U": U, "Sig": S, "Soff": So, "logdet": ld}
+
+    q = state(mu, D, U)
+    qs = state(pri["mu_bar"], pri["D"] / temperature, pri["U"] / temperature)
+    cq, cs = prox.cost_breakdown(prob, pri, q), prox.cost_breakdown(prob, pri, qs)
+    assert cq["E_coll"] == 0.0 and cs["E_coll"] == 0.0
+    Lam = prior.dense_from_blocks(D, U)
+    Kinv = prior.dense_from_blocks(pri["D"], pri["U"])
+    Sq = np.linalg.inv(Lam)
+    Ss = temperature * np.linalg.inv(Kinv)
+    d = (mu - pri["mu_bar"]).ravel()
+    kl = 0.5 * (np.trace(np.linalg.solve(Ss, Sq)) + d @ np.linalg.solve(Ss, d) - N * n
+                + np.linalg.slogdet(Ss)[1] - np.linalg.slogdet(Sq)[1])
+    assert abs((cq["total"] - cs["total"]) - temperature * kl) < 1e-9 * max(1.0, abs(temperature * kl))
+    # the entropy cost is -T H(q) with H the Gaussian entropy
+    H = scipy.stats.multivariate_normal(mean=np.zeros(N * n), cov=Sq).entropy()
+    assert abs(cq["entropy_cost"] + temperature * H) < 1e-9 * abs(H)
