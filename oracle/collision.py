@@ -56,7 +56,7 @@ def factor_expectation(prob, mu_c, Sig_c, p=None, cost=None):
     mu_c = np.asarray(mu_c, dtype=np.float64)
     d = mu_c.shape[0]
     L = np.linalg.cholesky(Sig_c)
-    pts, wts = gh.tensor_rule(p, d)
+    pts, wts = gh.rule(prob.get("quadrature", "tensor"), p, d)
     x = pts @ L.T + mu_c[None, :]
     psi = collision_cost(prob, x) if cost is None else cost(x)
     dx = x - mu_c[None, :]

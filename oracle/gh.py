@@ -9,9 +9,14 @@ Readings of the paper:
   * In the multi-dimensional rule the square root of P is the lower Cholesky
     factor L (P = L L^T), and the points are the tensor product of the
     one-dimensional points, the first coordinate varying fastest.
+  * Sparse grids (Sec. 4.3 Lemma 1): Smolyak's combination of tensor rules
+    built from the 1-D Gauss-Hermite rules, as in the cited Heiss-Winschel
+    construction: level k (the paper's precision degree k_q) is exact for
+    every polynomial of total degree <= 2k - 1.
 """
 from __future__ import annotations
 
+import itertools
 import math
 
 import numpy as np
@@ -66,3 +71,42 @@ def expect(phi, m, P, p: int):
     x = pts @ L.T + m[None, :]
     vals = np.asarray(phi(x), dtype=np.float64)
     return np.tensordot(wts, vals, axes=(0, 0))
+
+
+def smolyak_rule(k: int, d: int):
+    """Sparse-grid rule of level k in d dimensions: points [M, d], weights [M].
+
+    A(k, d) = sum over q = max(0, k - d) .. k - 1 of
+              (-1)^(k-1-q) C(d-1, k-1-q) sum over i in N^d, i_j >= 1,
+              |i| = d + q, of the tensor rule U_{i_1} x ... x U_{i_d},
+    U_i being the i-point Gauss-Hermite rule (exact to degree 2i - 1).
+    Points that several tensor rules share (only coordinates equal to the
+    exact zero of odd rules coincide) are merged by adding their weights.
+    Points are listed in the order they first appear; weights may be
+    negative."""
+    if k < 1 or d < 1:
+        raise ValueError("k and d must be >= 1")
+    acc = {}
+    order = []
+    for q in range(max(0, k - d), k):
+        coef = (-1) ** (k - 1 - q) * math.comb(d - 1, k - 1 - q)
+        for levels in itertools.product(range(1, q + 2), repeat=d):
+            if sum(levels) != d + q:
+                continue
+            rules = [gh_rule(i) for i in levels]
+            for combo in itertools.product(*[range(i) for i in levels]):
+                x = tuple(float(rules[a][0][combo[a]]) for a in range(d))
+                w = coef * math.prod(float(rules[a][1][combo[a]]) for a in range(d))
+                if x not in acc:
+                    acc[x] = 0.0
+                    order.append(x)
+                acc[x] += w
+    pts = np.array(order, dtype=np.float64).reshape(-1, d)
+    wts = np.array([acc[x] for x in order], dtype=np.float64)
+    return pts, wts
+
+
+def rule(kind: str, p: int, d: int):
+    """The d-dimensional rule of a problem: 'tensor' (p points per axis) or
+    'sparse' (Smolyak level p)."""
+    return smolyak_rule(p, d) if kind == "sparse" else tensor_rule(p, d)
