@@ -65,6 +65,11 @@ extern "C" {
 #define PGVIMP_COLL_ARM3D 3   /* 7 joint angles x[ci0..6] -> forward kinematics
                                  of a serial chain -> spheres, trilinear SDF  */
 
+/* quadrature rules of the collision expectations */
+#define PGVIMP_QUAD_TENSOR 0 /* tensor Gauss-Hermite, p points per axis       */
+#define PGVIMP_QUAD_SPARSE 1 /* Smolyak combination of Gauss-Hermite tensor
+                                rules of level k (at most 65536 nodes)       */
+
 /* nonlinear models for pgvimp_slr_linearize */
 #define PGVIMP_MODEL_QUAD2D 1 /* planar quadrotor drift of Sec. 7.3 eq.
                                  planar_quad with u = 0; state (x, z, phi,
@@ -131,6 +136,10 @@ typedef struct pgvimp_problem {
     int32_t segments;      /* chain segments for this plan (0 = context default) */
     int32_t expect_group;  /* factors per expectation workgroup: 32, 64, 128,
                               256 or 0 = chosen per launch (speed only)   */
+    int32_t quadrature;    /* PGVIMP_QUAD_TENSOR: gh_points = p points per
+                              axis (p^d nodes); PGVIMP_QUAD_SPARSE: Smolyak
+                              sparse grid of level k = gh_points (Sec. 4.3
+                              Lemma 1), exact to total degree 2k - 1      */
 } pgvimp_problem;
 
 /*
@@ -388,6 +397,14 @@ int64_t pgvimp_device_bytes(const pgvimp_ctx *ctx);
  * caller-provided arena, cfg->dev_arena), or a negative error code.
  */
 int64_t pgvimp_arena_bytes(const pgvimp_engine_cfg *cfg);
+
+/*
+ * Bytes of context heap (cfg->heap_bytes) one plan of this problem takes:
+ * its SDF grid (shared with live plans of the same grid in a context) and
+ * its model data (dynamics, factors, forward kinematics, sparse rule).
+ * Negative error code for an invalid problem.
+ */
+int64_t pgvimp_plan_heap_bytes(const pgvimp_problem *prob);
 
 /* Message of the last failure on this context (or of create if ctx NULL). */
 const char *pgvimp_last_error(const pgvimp_ctx *ctx);

@@ -110,6 +110,7 @@ def problem_struct(prob, mu_init=None):
         s.mu_init = _dptr(arr(np.asarray(mu_init).reshape(N, n)))
     s.segments = int(prob.get("segments", _tuned_segments(prob)))
     s.expect_group = int(prob.get("expect_group", 0))
+    s.quadrature = _abi.QUAD_SPARSE if prob.get("quadrature", "tensor") == "sparse" else _abi.QUAD_TENSOR
     return s, keep
 
 
@@ -162,11 +163,13 @@ def pgvimp_arena_bytes(n, max_plans, max_states, heap_bytes, trial_width=0, tria
 
 
 def _heap_need(probs):
+    """Context heap bytes for the problems (the library's per-plan sizing)."""
     total = 0
     for p in probs:
-        if p.get("coll_kind", "none") != "none":
-            total += int(np.asarray(p["sdf"]).size) * 4 + 256
-        total += 8 * (4 * p["n"] ** 2 + 2 * p["n"] + p["m"] ** 2 + max(p["N"] - 1, 1) * (p["n"] ** 2 + p["n"] + p["n"] * p["m"]) + 100) + 256
+        st, keep = problem_struct(p)
+        b = int(_abi.load().pgvimp_plan_heap_bytes(C.byref(st)))
+        _check(b if b < 0 else 0)
+        total += b
     return total
 
 

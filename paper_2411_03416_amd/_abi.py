@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(_HERE, "libpgvimp.so")
 OK, EINVAL, ENOMEM, ENOTPD, ENOCONV, EDEVICE, EBUSY = 0, -1, -2, -3, -4, -5, -6
 FP64, MIXED = 0, 1
 COLL_NONE, COLL_POINT2D, COLL_POINT3D, COLL_ARM3D = 0, 1, 2, 3
+QUAD_TENSOR, QUAD_SPARSE = 0, 1
 MODEL_QUAD2D = 1
 MAX_COLL_DIM, MAX_SPHERES, ARM_DOF = 8, 32, 7
 KERNEL_KINDS = ("expect", "prep", "trial", "select", "restart")
@@ -45,6 +46,7 @@ class Problem(C.Structure):
         ("fk_axes", _ip), ("fk_sphere_link", _ip),
         ("mu_init", _dp),
         ("segments", C.c_int32), ("expect_group", C.c_int32),
+        ("quadrature", C.c_int32),
     ]
 
 
@@ -100,6 +102,7 @@ SIGNATURES = [
     ("pgvimp_kernel_times", C.c_int, [C.c_void_p, C.c_int32, _dp, C.POINTER(C.c_int64)]),
     ("pgvimp_device_bytes", C.c_int64, [C.c_void_p]),
     ("pgvimp_arena_bytes", C.c_int64, [C.POINTER(EngineCfg)]),
+    ("pgvimp_plan_heap_bytes", C.c_int64, [C.POINTER(Problem)]),
     ("pgvimp_last_error", C.c_char_p, [C.c_void_p]),
 ]
 

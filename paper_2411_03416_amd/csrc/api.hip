@@ -20,6 +20,7 @@ namespace {
 constexpr int64_t kAlign = 256;
 constexpr int kDefaultTrialWidth = 8;
 constexpr int kMaxTrialWidth = 64;
+constexpr int kMaxSparseNodes = 65536;  // nodes of a sparse quadrature rule
 
 struct PlanHost {
     bool active = false;
@@ -28,7 +29,7 @@ struct PlanHost {
     int64_t coff = -1;  // chain-order range
     int64_t heap_off = -1;  // model block
     int64_t map_off = -1;   // SDF block (shared by plans with identical maps)
-    int coll_kind = 0, d = 0, p = 0;
+    int coll_kind = 0, d = 0, p = 0, quadrature = 0;
     double dt = 0.0;
     int group = 0;  // factors per expectation workgroup (0 = chosen per launch)
     int max_bisect = 0;
@@ -69,9 +70,9 @@ MapKey map_key(const float* sdf, int gx, int gy, int gz) {
 }
 
 struct ClassKey {
-    int kind, d, p, group;
+    int kind, d, p, group, quadrature;
     bool operator==(const ClassKey& o) const {
-        return kind == o.kind && d == o.d && p == o.p && group == o.group;
+        return kind == o.kind && d == o.d && p == o.p && group == o.group && quadrature == o.quadrature;
     }
 };
 
@@ -90,6 +91,7 @@ struct pgvimp_ctx {
     DevState st{};
     RangeAlloc states, cstates, heapalloc;  // states, chain-order ranges, heap
     std::map<MapKey, MapEntry> maps;        // live SDF grids on the heap
+    std::vector<double> ghX, ghW;            // 1-D Gauss-Hermite rules [kMaxGH+1][kMaxGH]
     std::vector<PlanHost> plans;
     std::vector<PlanDev> pdev;  // host mirror of the device plan table
     // staging for host I/O
@@ -196,6 +198,63 @@ void gh_tables(std::vector<double>& X, std::vector<double>& W) {
             }
             X[p * kMaxGH + i] = x;
             W[p * kMaxGH + i] = 1.0 / s;
+        }
+    }
+}
+
+// Smolyak sparse grid of level k in d dimensions (Sec. 4.3 Lemma 1):
+// A(k, d) = sum_{q = max(0, k-d)}^{k-1} (-1)^(k-1-q) C(d-1, k-1-q)
+//           sum_{levels l, l_j >= 1, |l| = d + q} U_{l_1} x ... x U_{l_d},
+// U_l the l-point Gauss-Hermite rule.  Points shared by several tensor
+// rules (coordinates equal to the exact zero of odd rules) are merged by
+// adding their weights; rows keep the order of first appearance.  Returns
+// rows (xi[0..d-1], W), or an empty vector past max_nodes.
+void sparse_rule(int k, int d, const std::vector<double>& X, const std::vector<double>& W, int max_nodes,
+                 std::vector<double>& rows) {
+    rows.clear();
+    std::map<std::vector<double>, size_t> index;
+    auto binom = [](int a, int b) {
+        double r = 1.0;
+        for (int i = 1; i <= b; ++i) r = r * (a - b + i) / i;
+        return r;
+    };
+    std::vector<int> lv(d), at(d);
+    for (int q = std::max(0, k - d); q < k; ++q) {
+        const double coef = (((k - 1 - q) % 2) ? -1.0 : 1.0) * binom(d - 1, k - 1 - q);
+        // every levels vector with entries 1..q+1 summing to d + q
+        std::fill(lv.begin(), lv.end(), 1);
+        while (true) {
+            int sum = 0;
+            for (int a = 0; a < d; ++a) sum += lv[a];
+            if (sum == d + q) {
+                std::fill(at.begin(), at.end(), 0);
+                while (true) {
+                    std::vector<double> x(d);
+                    double w = coef;
+                    for (int a = 0; a < d; ++a) {
+                        x[a] = X[lv[a] * kMaxGH + at[a]];
+                        w *= W[lv[a] * kMaxGH + at[a]];
+                    }
+                    auto it = index.find(x);
+                    if (it == index.end()) {
+                        if ((int)index.size() >= max_nodes) {
+                            rows.clear();
+                            return;
+                        }
+                        index.emplace(x, rows.size());
+                        rows.insert(rows.end(), x.begin(), x.end());
+                        rows.push_back(w);
+                    } else {
+                        rows[it->second + d] += w;
+                    }
+                    int a = 0;
+                    while (a < d && ++at[a] == lv[a]) at[a++] = 0;
+                    if (a == d) break;
+                }
+            }
+            int a = 0;
+            while (a < d && ++lv[a] > q + 1) lv[a++] = 1;
+            if (a == d) break;
         }
     }
 }
@@ -322,7 +381,9 @@ int validate_problem(pgvimp_ctx* c, const pgvimp_problem* p) {
     for (int k = 0; k < d; ++k)
         if (p->coll_index[k] < 0 || p->coll_index[k] >= n) FAIL(c, PGVIMP_EINVAL, "coll_index out of range");
     const int group = p->expect_group > 0 ? p->expect_group : c->cfg.expect_group;
-    if (!expect_supported(p->coll_kind, d, p->gh_points, group))
+    if (p->quadrature != PGVIMP_QUAD_TENSOR && p->quadrature != PGVIMP_QUAD_SPARSE)
+        FAIL(c, PGVIMP_EINVAL, "unknown quadrature %d", p->quadrature);
+    if (!expect_supported(p->coll_kind, d, p->gh_points, group, p->quadrature))
         FAIL(c, PGVIMP_EINVAL, "unsupported quadrature shape kind=%d d=%d p=%d group=%d", p->coll_kind, d,
              p->gh_points, group);
     const bool is3 = p->coll_kind != PGVIMP_COLL_POINT2D;
@@ -509,6 +570,8 @@ static int ctx_alloc(pgvimp_ctx* c) {
     // tables and empty plan slots
     std::vector<double> X, W;
     gh_tables(X, W);
+    c->ghX = X;
+    c->ghW = W;
     std::vector<float> Xf(X.begin(), X.end()), Wf(W.begin(), W.end());
     HCK(c, hipMemcpy((void*)st.gh_x64, X.data(), X.size() * 8, hipMemcpyHostToDevice));
     HCK(c, hipMemset(st.flags, 0, 16 * 4));
@@ -610,6 +673,33 @@ int pgvimp_sync(pgvimp_ctx* c) {
     return PGVIMP_OK;
 }
 
+// FP64 values of a plan's model block: start/goal factors, Qc, per-interval
+// dynamics, sphere radii, forward-kinematics data and the sparse rule
+// (FP64 rows, then FP32 rows two per slot).
+static int64_t model_count_of(int n, int m, int N, int ns, int64_t rule_vals) {
+    const int64_t nI = std::max(N - 1, 1);
+    const int64_t fk_count = 3 + PGVIMP_ARM_DOF + ns + PGVIMP_ARM_DOF + ns;
+    return 4 * (int64_t)n * n + 2 * n + (int64_t)m * m + nI * n * n + nI * n + nI * n * m + ns + fk_count +
+           rule_vals + (rule_vals + 1) / 2;
+}
+
+int64_t pgvimp_plan_heap_bytes(const pgvimp_problem* p) {
+    if (!p || p->n < 1 || p->m < 1 || p->N < 1) return PGVIMP_EINVAL;
+    const bool coll = p->coll_kind != PGVIMP_COLL_NONE;
+    const int ns = coll ? std::max(p->n_spheres, 1) : 1;
+    int64_t rule_vals = 0;
+    if (coll && p->quadrature == PGVIMP_QUAD_SPARSE) {
+        std::vector<double> X, W, rule;
+        gh_tables(X, W);
+        if (p->gh_points < 1 || p->gh_points > kMaxGH) return PGVIMP_EINVAL;
+        sparse_rule(p->gh_points, coll_dim_of(p->coll_kind), X, W, kMaxSparseNodes, rule);
+        if (rule.empty()) return PGVIMP_EINVAL;
+        rule_vals = (int64_t)rule.size();
+    }
+    const int64_t sdf = coll ? align_up((int64_t)p->gx * p->gy * p->gz * 4) : 0;
+    return sdf + align_up(model_count_of(p->n, p->m, p->N, ns, rule_vals) * 8);
+}
+
 int pgvimp_add_plan(pgvimp_ctx* c, const pgvimp_problem* p, int32_t* plan_out) {
     if (!c || !plan_out) return PGVIMP_EINVAL;
     int rc = validate_problem(c, p);
@@ -630,8 +720,17 @@ int pgvimp_add_plan(pgvimp_ctx* c, const pgvimp_problem* p, int32_t* plan_out) {
     // and the plan's FP64 model data
     const int64_t sdf_bytes = coll ? align_up((int64_t)p->gx * p->gy * p->gz * 4) : 0;
     const int64_t fk_count = 3 + PGVIMP_ARM_DOF + ns + PGVIMP_ARM_DOF + ns;
-    const int64_t model_count = 4 * (int64_t)n * n + 2 * n + (int64_t)m * m + (int64_t)nI * n * n + (int64_t)nI * n +
-                                (int64_t)nI * n * m + ns + fk_count;
+    // sparse quadrature rule of the collision expectations (rows xi, W), FP64
+    // then FP32 (packed two per double slot)
+    std::vector<double> rule;
+    const int dcol = coll ? coll_dim_of(p->coll_kind) : 0;
+    if (coll && p->quadrature == PGVIMP_QUAD_SPARSE) {
+        sparse_rule(p->gh_points, dcol, c->ghX, c->ghW, kMaxSparseNodes, rule);
+        if (rule.empty()) FAIL(c, PGVIMP_EINVAL, "sparse rule of level %d in %d dimensions exceeds %d nodes",
+                               p->gh_points, dcol, kMaxSparseNodes);
+    }
+    const int64_t rule_vals = (int64_t)rule.size();
+    const int64_t model_count = model_count_of(n, m, N, ns, rule_vals);
     const int64_t bytes = align_up(model_count * 8);
     MapKey mkey{};
     bool map_new = false;
@@ -680,6 +779,8 @@ int pgvimp_add_plan(pgvimp_ctx* c, const pgvimp_problem* p, int32_t* plan_out) {
     double* B = take((int64_t)nI * n * m);
     double* rad = take(ns);
     double* fk = take(fk_count);
+    double* rule64 = take(rule_vals);
+    float* rule32 = (float*)take((rule_vals + 1) / 2);
     auto hput = [&](double* dst, const double* src, int64_t cnt) { memcpy(&h[dst - model], src, cnt * 8); };
     hput(mus, p->mu_start, n);
     hput(mug, p->mu_goal, n);
@@ -691,6 +792,11 @@ int pgvimp_add_plan(pgvimp_ctx* c, const pgvimp_problem* p, int32_t* plan_out) {
         hput(A + (int64_t)i * n * n, p->A + (int64_t)src * n * n, n * n);
         hput(a + (int64_t)i * n, p->a + (int64_t)src * n, n);
         hput(B + (int64_t)i * n * m, p->B + (int64_t)src * n * m, n * m);
+    }
+    if (rule_vals > 0) {
+        hput(rule64, rule.data(), rule_vals);
+        float* r32 = (float*)&h[(double*)rule32 - model];
+        for (int64_t e = 0; e < rule_vals; ++e) r32[e] = (float)rule[e];
     }
     if (coll) {
         hput(rad, p->sphere_radius, ns);
@@ -720,6 +826,10 @@ int pgvimp_add_plan(pgvimp_ctx* c, const pgvimp_problem* p, int32_t* plan_out) {
     pd.coll_kind = p->coll_kind;
     pd.d = coll ? coll_dim_of(p->coll_kind) : 0;
     pd.gh_points = p->gh_points;
+    pd.quadrature = coll ? p->quadrature : PGVIMP_QUAD_TENSOR;
+    pd.rule_n = dcol > 0 ? (int32_t)(rule_vals / (dcol + 1)) : 0;
+    pd.rule64 = rule_vals > 0 ? rule64 : nullptr;
+    pd.rule32 = rule_vals > 0 ? rule32 : nullptr;
     pd.gx = p->gx;
     pd.gy = p->gy;
     pd.gz = p->gz;
@@ -767,6 +877,7 @@ int pgvimp_add_plan(pgvimp_ctx* c, const pgvimp_problem* p, int32_t* plan_out) {
     ph.coll_kind = p->coll_kind;
     ph.d = pd.d;
     ph.p = p->gh_points;
+    ph.quadrature = pd.quadrature;
     ph.dt = p->dt;
     ph.max_bisect = p->max_bisect;
     ph.group = !coll ? 0 : p->expect_group > 0 ? p->expect_group : c->cfg.expect_group;
@@ -865,7 +976,7 @@ int pgvimp_factor_expectations(pgvimp_ctx* c, int32_t plan, double* E_coll, doub
     const PlanHost& ph = c->plans[plan];
     const int N = ph.N, n = c->n;
     if (ph.coll_kind != PGVIMP_COLL_NONE)
-        HCK(c, launch_expect(c->st, ph.coll_kind, ph.d, ph.p, c->cfg.precision, ph.group, plan, plan + 1, N, 0,
+        HCK(c, launch_expect(c->st, ph.coll_kind, ph.d, ph.p, ph.quadrature, c->cfg.precision, ph.group, plan, plan + 1, N, 0,
                              c->stream));
     HCK(c, launch_prior_costs(c->st, plan, N, c->stream));
     int rc;
@@ -890,7 +1001,7 @@ int pgvimp_factor_expectations_noalloc(pgvimp_ctx* c, int32_t plan, double* E_co
     double* stage = nullptr;
     HCK(c, scratch_address(c->cfg.device, &stage));
     if (ph.coll_kind != PGVIMP_COLL_NONE)
-        HCK(c, launch_expect(c->st, ph.coll_kind, ph.d, ph.p, c->cfg.precision, ph.group, plan, plan + 1, N, 0,
+        HCK(c, launch_expect(c->st, ph.coll_kind, ph.d, ph.p, ph.quadrature, c->cfg.precision, ph.group, plan, plan + 1, N, 0,
                              c->stream));
     HCK(c, launch_prior_costs(c->st, plan, N, c->stream));
     int rc;
@@ -907,7 +1018,8 @@ static std::vector<ClassKey> live_classes(pgvimp_ctx* c) {
     std::vector<ClassKey> v;
     for (auto& ph : c->plans) {
         if (!ph.active || ph.coll_kind == PGVIMP_COLL_NONE) continue;
-        ClassKey k{ph.coll_kind, ph.d, ph.p, ph.group};
+        // sparse plans of every level share one launch: each reads its own rule
+        ClassKey k{ph.coll_kind, ph.d, ph.quadrature == PGVIMP_QUAD_SPARSE ? 0 : ph.p, ph.group, ph.quadrature};
         if (std::find(v.begin(), v.end(), k) == v.end()) v.push_back(k);
     }
     return v;
@@ -983,7 +1095,7 @@ static int enqueue_iters(pgvimp_ctx* c, int n_iters, const std::vector<ClassKey>
     for (int it = 0; it < n_iters; ++it) {
         for (auto& k : cls) {
             if ((rc = begin(PGVIMP_K_EXPECT))) return rc;
-            HCK(c, launch_expect(c->st, k.kind, k.d, k.p, c->cfg.precision, k.group, 0, phw, maxN, 1, c->stream));
+            HCK(c, launch_expect(c->st, k.kind, k.d, k.p, k.quadrature, c->cfg.precision, k.group, 0, phw, maxN, 1, c->stream));
             if ((rc = end())) return rc;
         }
         if ((rc = begin(PGVIMP_K_PREP))) return rc;
@@ -1038,7 +1150,7 @@ int pgvimp_expect_all(pgvimp_ctx* c, int32_t reps) {
                 c->ev_kind[c->ev_used] = PGVIMP_K_EXPECT;
                 HCK(c, hipEventRecord(c->ev[c->ev_used], c->stream));
             }
-            HCK(c, launch_expect(c->st, k.kind, k.d, k.p, c->cfg.precision, k.group, 0, (int)c->plans.size(),
+            HCK(c, launch_expect(c->st, k.kind, k.d, k.p, k.quadrature, c->cfg.precision, k.group, 0, (int)c->plans.size(),
                                  max_live_N(c), 1, c->stream));
             if (c->profile) {
                 HCK(c, hipEventRecord(c->ev[c->ev_used + 1], c->stream));

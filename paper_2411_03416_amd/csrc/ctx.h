@@ -47,6 +47,10 @@ struct PlanDev {
     int32_t phase;  // 0 = iteration pending, 1 = no iteration (budget spent)
     int32_t coff;   // start of the plan's chain-order range (capacity Sc)
     int32_t coll_index[PGVIMP_MAX_COLL_DIM];
+    int32_t quadrature;  // PGVIMP_QUAD_*
+    int32_t rule_n;      // sparse rule: nodes (rows of rule64 / rule32)
+    const double* rule64;  // sparse rule rows (xi[0..d-1], W), FP64
+    const float* rule32;   // the same rows in FP32
     double temperature, beta_max, kl_bound, cell, dt;
     double inv_cell, hinge_eps, obs_weight, logdet;
     double origin[3];
@@ -190,7 +194,8 @@ hipError_t launch_iteration(const DevState& st, int phw, int part, int round, hi
 // Window `round` of step sizes of the current iteration for plans [0, phw).
 hipError_t launch_window(const DevState& st, int phw, int round, hipStream_t s);
 // collision expectations of plans [plan_lo, plan_hi) of up to maxN states each
-hipError_t launch_expect(const DevState& st, int coll_kind, int d, int p, int precision, int group, int plan_lo,
+hipError_t launch_expect(const DevState& st, int coll_kind, int d, int p, int quadrature, int precision, int group,
+                         int plan_lo,
                          int plan_hi, int maxN, int respect_budget, hipStream_t s);
 hipError_t launch_prior_costs(const DevState& st, int plan, int N, hipStream_t s);
 hipError_t launch_gather(const DevState& st, int what, int plan, int N, double* out, hipStream_t s);
@@ -198,7 +203,7 @@ hipError_t launch_scatter(const DevState& st, int what, int plan, int N, const d
 hipError_t launch_slr_model(const DevState& st, int plan, int N, double gravity, int p, double* A_out,
                             double* a_out, int write_model, hipStream_t s);
 bool chain_supported(int n);
-bool expect_supported(int coll_kind, int d, int p, int group);
+bool expect_supported(int coll_kind, int d, int p, int group, int quadrature);
 // factors per expectation workgroup for a launch over `plans` plan slots of
 // at most maxN states (group 0 = chosen from the batch)
 int expect_group_for(int group, int plans, int maxN, int cus);

@@ -303,17 +303,19 @@ __device__ __forceinline__ bool chol_packed(const double* A, double* L) {
 template <typename R, int D, int P, int F, int KIND>
 struct ExpectShape {
     static constexpr int T = 256;
-    static constexpr int NODES = ipow(P, D);
-    static constexpr bool CENTRE = sizeof(R) == 4 && P >= 2;
+    // P = 0: the plan's sparse rule (Smolyak), whose size is known at run time
+    static constexpr bool SPARSE = P == 0;
+    static constexpr int NODES = SPARSE ? 0 : ipow(P, D);
+    static constexpr bool CENTRE = sizeof(R) == 4 && (SPARSE || P >= 2);
     static constexpr int NE = NODES + (CENTRE ? 1 : 0);
     static constexpr int NS2 = D * (D + 1) / 2;
     static constexpr int PS = D + NS2;  // mu, then L packed by rows
     static constexpr int CHMAX = ((expect_lds(KIND) / (int)sizeof(R)) / F - 1) | 1;  // odd, < budget
-    static constexpr int CH = cmin(NE, CHMAX);
+    static constexpr int CH = SPARSE ? CHMAX : cmin(NE, CHMAX);
     static constexpr int CHS = CH | 1;
     static constexpr int NCH = (NE + CH - 1) / CH;
     // rule points and weights of every evaluation in an LDS table when small
-    static constexpr bool TAB = NE * D <= 1024;
+    static constexpr bool TAB = !SPARSE && NE * D <= 1024;
     static constexpr int TS = D + 1;  // table row: xi[0..D-1], W
 };
 
@@ -332,6 +334,18 @@ __device__ __forceinline__ void rule_point(const R* x1, const R* w1, uint32_t e,
         W *= w1[q];
     }
 }
+
+// Rule point and weight of evaluation e of a sparse rule: the centre first
+// (when cen), then the plan's rows (xi[0..D-1], W).
+template <typename R, int D>
+__device__ __forceinline__ void sparse_point(const R* __restrict__ rows, bool cen, uint32_t e, R* xi, R& W) {
+    const uint32_t r = cen ? (e == 0 ? 0u : e - 1u) : e;
+#pragma unroll
+    for (int a = 0; a < D; ++a) xi[a] = (cen && e == 0) ? R(0) : rows[r * (D + 1) + a];
+    W = rows[r * (D + 1) + D];
+}
+__device__ __forceinline__ const double* rule_rows(const PlanDev& p, double) { return p.rule64; }
+__device__ __forceinline__ const float* rule_rows(const PlanDev& p, float) { return p.rule32; }
 
 // x = mu + L xi (L lower, packed by rows), with explicit FMAs
 template <typename R, int D>
@@ -461,13 +475,16 @@ __device__ __forceinline__ void store_factor(const DevState& st, int64_t s, bool
 // tiles; false if the block has nothing to do.
 __device__ __forceinline__ bool expect_block_plan(const DevState& st, int plan_lo, int plan_hi, int tiles,
                                                   int respect_budget, int kind, int gh, int& pid, int& tile) {
+    // gh = 0: plans with a sparse rule (any level); else tensor plans of gh points
     const int b = blockIdx.x;
     const int k = b / kNumXcd;
     pid = plan_lo + (k / tiles) * kNumXcd + b % kNumXcd;
     tile = k % tiles;
     if (pid >= plan_hi) return false;
     const PlanDev& p = st.plans[pid];
-    if (!p.active || p.coll_kind != kind || p.gh_points != gh) return false;
+    if (!p.active || p.coll_kind != kind) return false;
+    if (gh == 0 ? p.quadrature != PGVIMP_QUAD_SPARSE : (p.quadrature != PGVIMP_QUAD_TENSOR || p.gh_points != gh))
+        return false;
     return !(respect_budget && p.iters_left <= 0);
 }
 
@@ -477,13 +494,14 @@ template <typename R, int D, int P, int KIND, int F>
 __global__ void __launch_bounds__(256) expect_kernel(DevState st, int plan_lo, int plan_hi, int tiles,
                                                      int respect_budget) {
     using Sh = ExpectShape<R, D, P, F, KIND>;
-    constexpr int T = Sh::T, NE = Sh::NE, PS = Sh::PS, CH = Sh::CH, CHS = Sh::CHS, NCH = Sh::NCH, TS = Sh::TS;
-    constexpr bool CENTRE = Sh::CENTRE;
+    constexpr int T = Sh::T, PS = Sh::PS, CH = Sh::CH, CHS = Sh::CHS, TS = Sh::TS;
+    constexpr bool SPARSE = Sh::SPARSE;
     constexpr int NS2 = Sh::NS2;
+    constexpr int PX = P > 0 ? P : 1;
     __shared__ R psi[F * CHS];
     __shared__ R par[F * PS];
-    __shared__ R xs[P], ws[P];
-    __shared__ R ntab[Sh::TAB ? NE * TS : 1];  // row e: xi of evaluation e, then its weight
+    __shared__ R xs[PX], ws[PX];
+    __shared__ R ntab[Sh::TAB ? Sh::NE * TS : 1];  // row e: xi of evaluation e, then its weight
 
     int pid, tile;
     if (!expect_block_plan(st, plan_lo, plan_hi, tiles, respect_budget, KIND, P, pid, tile)) return;
@@ -493,13 +511,20 @@ __global__ void __launch_bounds__(256) expect_kernel(DevState st, int plan_lo, i
     const int lo = p.coll_states == 1 ? 1 : 0;
     const int hi = p.coll_states == 1 ? N - 1 : N;
     const int64_t S = st.S;
-    if (tid < P) {
+    // evaluations per factor (the centre first in mixed mode, when the rule
+    // integrates xi xi^T: a sparse rule of level k >= 2)
+    const bool CENTRE = SPARSE ? Sh::CENTRE && p.gh_points >= 2 : Sh::CENTRE;
+    const int NE = SPARSE ? p.rule_n + (CENTRE ? 1 : 0) : Sh::NE;
+    const int NCH = (NE + CH - 1) / CH;
+    const R* __restrict__ rows = rule_rows(p, R(0));
+    if (!SPARSE && tid < P) {
         xs[tid] = Tab<R>::x(st)[P * kMaxGH + tid];
         ws[tid] = Tab<R>::w(st)[P * kMaxGH + tid];
     }
     if (Sh::TAB) {
         __syncthreads();
-        for (int e = tid; e < NE; e += T) rule_point<R, D, P, CENTRE>(xs, ws, (uint32_t)e, ntab + e * TS, ntab[e * TS + D]);
+        for (int e = tid; e < NE; e += T)
+            rule_point<R, D, PX, Sh::CENTRE>(xs, ws, (uint32_t)e, ntab + e * TS, ntab[e * TS + D]);
     }
     Cost<R, D, KIND> cost;
     cost.init(p);
@@ -541,11 +566,13 @@ __global__ void __launch_bounds__(256) expect_kernel(DevState st, int plan_lo, i
                 const uint32_t jj = (uint32_t)it - f * (uint32_t)CH;
                 const uint32_t e = min((uint32_t)(ch * CH) + jj, (uint32_t)(NE - 1));
                 R xi[D], W;
-                if (Sh::TAB) {
+                if (SPARSE) {
+                    sparse_point<R, D>(rows, CENTRE, e, xi, W);
+                } else if (Sh::TAB) {
 #pragma unroll
                     for (int a = 0; a < D; ++a) xi[a] = ntab[e * TS + a];
                 } else {
-                    rule_point<R, D, P, CENTRE>(xs, ws, e, xi, W);
+                    rule_point<R, D, PX, Sh::CENTRE>(xs, ws, e, xi, W);
                 }
                 const R* pf = par + f * PS;
                 R x[D];
@@ -559,19 +586,21 @@ __global__ void __launch_bounds__(256) expect_kernel(DevState st, int plan_lo, i
 #pragma unroll 4
                 for (int jj = 0; jj < CH; ++jj) {
                     const int e = ch * CH + jj;
-                    if (NE % CH != 0 && e >= NE) break;
+                    if (e >= NE) break;
                     const R v = row[jj];
                     if (CENTRE && e == 0) {
                         centre = v;
                         continue;
                     }
                     R xi[D], W;
-                    if (Sh::TAB) {
+                    if (SPARSE) {
+                        sparse_point<R, D>(rows, CENTRE, (uint32_t)e, xi, W);
+                    } else if (Sh::TAB) {
 #pragma unroll
                         for (int a = 0; a < D; ++a) xi[a] = ntab[e * TS + a];
                         W = ntab[e * TS + D];
                     } else {
-                        rule_point<R, D, P, CENTRE>(xs, ws, (uint32_t)e, xi, W);
+                        rule_point<R, D, PX, Sh::CENTRE>(xs, ws, (uint32_t)e, xi, W);
                     }
                     m.add(v, centre, W, xi);
                 }
@@ -702,11 +731,13 @@ static int pick_group(int group, int plans, int maxN, int cus) {
         default: return launch_one<R, D, P, KIND, 32>(st, plo, phi, maxN, respect, s);      \
     }
 
+// P = 0 launches the plans' own sparse rules.
 template <typename R>
 static hipError_t dispatch(const DevState& st, int kind, int d, int p, int f, int plo, int phi, int maxN, int respect,
                            hipStream_t s) {
     if (kind == PGVIMP_COLL_POINT2D && d == 2) {
         switch (p) {
+            case 0: PG_GROUPS(R, 2, 0, PGVIMP_COLL_POINT2D);
             case 1: PG_GROUPS(R, 2, 1, PGVIMP_COLL_POINT2D);
             case 2: PG_GROUPS(R, 2, 2, PGVIMP_COLL_POINT2D);
             case 3: PG_GROUPS(R, 2, 3, PGVIMP_COLL_POINT2D);
@@ -721,6 +752,7 @@ static hipError_t dispatch(const DevState& st, int kind, int d, int p, int f, in
     }
     if (kind == PGVIMP_COLL_POINT3D && d == 3) {
         switch (p) {
+            case 0: PG_GROUPS(R, 3, 0, PGVIMP_COLL_POINT3D);
             case 2: PG_GROUPS(R, 3, 2, PGVIMP_COLL_POINT3D);
             case 3: PG_GROUPS(R, 3, 3, PGVIMP_COLL_POINT3D);
             case 4: PG_GROUPS(R, 3, 4, PGVIMP_COLL_POINT3D);
@@ -731,6 +763,7 @@ static hipError_t dispatch(const DevState& st, int kind, int d, int p, int f, in
     if (kind == PGVIMP_COLL_ARM3D && d == PGVIMP_ARM_DOF) {
         // the arm's nodes are costly and many: 32 factors per workgroup
         switch (p) {
+            case 0: return launch_one<R, PGVIMP_ARM_DOF, 0, PGVIMP_COLL_ARM3D, 32>(st, plo, phi, maxN, respect, s);
             case 2: return launch_one<R, PGVIMP_ARM_DOF, 2, PGVIMP_COLL_ARM3D, 32>(st, plo, phi, maxN, respect, s);
             case 3: return launch_one<R, PGVIMP_ARM_DOF, 3, PGVIMP_COLL_ARM3D, 32>(st, plo, phi, maxN, respect, s);
             default: return hipErrorInvalidValue;
@@ -742,20 +775,31 @@ static hipError_t dispatch(const DevState& st, int kind, int d, int p, int f, in
 
 int expect_group_for(int group, int plans, int maxN, int cus) { return pick_group(group, plans, maxN, cus); }
 
-bool expect_supported(int kind, int d, int p, int group) {
+// Sparse rules (p = level k) are built on the host from the 1-D rules of up
+// to k points, for any level the host accepts; tensor rules need a compiled
+// shape.
+bool expect_supported(int kind, int d, int p, int group, int quadrature) {
     if (group != 0 && group != 32 && group != 64 && group != 128 && group != 256) return false;
+    if (kind == PGVIMP_COLL_NONE) return true;
+    if (quadrature == PGVIMP_QUAD_SPARSE) {
+        const bool shape = (kind == PGVIMP_COLL_POINT2D && d == 2) || (kind == PGVIMP_COLL_POINT3D && d == 3) ||
+                           (kind == PGVIMP_COLL_ARM3D && d == PGVIMP_ARM_DOF);
+        return shape && p >= 1 && p <= kMaxGH;
+    }
+    if (quadrature != PGVIMP_QUAD_TENSOR) return false;
     if (kind == PGVIMP_COLL_POINT2D) return d == 2 && p >= 1 && p <= 10 && p != 9;
     if (kind == PGVIMP_COLL_POINT3D) return d == 3 && p >= 2 && p <= 5;
     if (kind == PGVIMP_COLL_ARM3D) return d == PGVIMP_ARM_DOF && (p == 2 || p == 3);
-    return kind == PGVIMP_COLL_NONE;
+    return false;
 }
 
-hipError_t launch_expect(const DevState& st, int kind, int d, int p, int precision, int group, int plo, int phi,
-                         int maxN, int respect, hipStream_t s) {
+hipError_t launch_expect(const DevState& st, int kind, int d, int p, int quadrature, int precision, int group, int plo,
+                         int phi, int maxN, int respect, hipStream_t s) {
     if (kind == PGVIMP_COLL_NONE) return hipSuccess;
     const int f = pick_group(group, phi - plo, maxN, st.wbudget);
-    if (precision == PGVIMP_MIXED) return dispatch<float>(st, kind, d, p, f, plo, phi, maxN, respect, s);
-    return dispatch<double>(st, kind, d, p, f, plo, phi, maxN, respect, s);
+    const int shape = quadrature == PGVIMP_QUAD_SPARSE ? 0 : p;
+    if (precision == PGVIMP_MIXED) return dispatch<float>(st, kind, d, shape, f, plo, phi, maxN, respect, s);
+    return dispatch<double>(st, kind, d, shape, f, plo, phi, maxN, respect, s);
 }
 
 }  // namespace pg

@@ -166,3 +166,94 @@ def test_workgroup_shapes_give_the_same_bits(pg, kind, p_gh, precision):
     assert np.abs(outs[0][0]).max() > 0
     for o in outs[1:]:
         assert all(np.array_equal(u, v) for u, v in zip(outs[0], o))
+
+
+def _sparse_factor_errors(p, mu, S, E, g, H, mixed):
+    """_factor_errors for a sparse rule, whose weights can be negative: the
+    sums are bounded by the rule with |W|, so E_ref becomes
+    E_abs = sum |W| psi and the node term M sqrt(w E) becomes
+    M sqrt(w sum|W| E_abs) (Cauchy-Schwarz with weights |W|).  In mixed mode
+    the rule is rounded to FP32 and the centring by c = psi(mu) relies on
+    sum W = 1 and sum W xi xi^T = I, which then hold to about u sum |W|;
+    c sum |W| joins the scale.  sum |W| is 19 and 181 for level 10 in 2 and
+    3 dimensions and 3653 for level 6 in 7: the FP32 sums of a high-level
+    rule cancel that much, which the normwise errors printed here show."""
+    ci = np.asarray(p["coll_index"])
+    pts, wts = gh.rule("sparse", p["gh_points"], ci.size)
+    wabs = np.abs(wts)
+    xmax = max(float(np.abs(pts).max()), 1.0)  # level 1 is the single node xi = 0
+    grid = np.asarray(p["sdf"], dtype=np.float64)
+    M = (np.abs(grid).max() + max(grid.shape) * p["cell"] + np.abs(p["origin"]).max()
+         + p["hinge_eps"] + np.abs(p["sphere_radius"]).max())
+    w = p["obs_weight"]
+    Er, gr, Hr = collision.collision_expectations(p, mu, S)
+    worst = np.zeros(3)
+    for i in collision.collision_states(p):
+        Sc = S[i][np.ix_(ci, ci)]
+        L = np.linalg.cholesky(Sc)
+        Li = np.linalg.inv(L)
+        nl = np.abs(Li).sum(axis=1).max()
+        mc = mu[i][ci]
+        Eabs = float(np.sum(wabs * collision.collision_cost(p, pts @ L.T + mc[None, :])))
+        e = Eabs + M * np.sqrt(w * wabs.sum() * Eabs)
+        if mixed:
+            e += abs(float(collision.collision_cost(p, mc[None, :])[0])) * wabs.sum()
+        e = max(e, 1e-300)
+        worst[0] = max(worst[0], abs(E[i] - Er[i]) / e)
+        worst[1] = max(worst[1], np.abs(g[i][ci] - gr[i][ci]).max() / (e * xmax * nl))
+        worst[2] = max(worst[2], np.abs(H[i][np.ix_(ci, ci)] - Hr[i][np.ix_(ci, ci)]).max()
+                       / (e * (xmax ** 2 + 1) * nl ** 2))
+    return worst, (Er, gr, Hr)
+
+
+# Smolyak levels of the paper's experiments (10 for the point robots, 6 for
+# the arm) and low levels (k = 1: the single node xi = 0, no centring)
+@pytest.mark.parametrize("kind,k,N", [("point2d", 1, 37), ("point2d", 3, 37), ("point2d", 10, 37),
+                                      ("point3d", 2, 29), ("point3d", 10, 29), ("arm", 3, 5), ("arm", 6, 3)])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_sparse_rules_identical_inputs(pg, kind, k, N, precision):
+    """Sec. 4.3 Lemma 1: the expectations with the Smolyak rule built on the
+    host (merged nodes, negative weights) against the oracle's own sparse
+    rule on the marginals the GPU reads."""
+    make = {"point2d": workloads.point2d_problem, "point3d": workloads.point3d_problem,
+            "arm": workloads.arm_problem}[kind]
+    p = make(2 if kind != "arm" else 0, N=N, gh_points=k)
+    p["quadrature"] = "sparse"
+    print(f"sparse {kind} k={k} precision={precision}", flush=True)
+    ctx = pg.pgvimp_create([p], precision=precision, use_graph=False)
+    mu, _, _ = pg.pgvimp_get_state(ctx, 0)
+    S, _, _ = pg.pgvimp_marginals(ctx, 0)
+    E, g, H, _ = pg.pgvimp_factor_expectations(ctx, 0)
+    worst, (Er, gr, Hr) = _sparse_factor_errors(p, mu, S, E, g, H, precision == 1)
+    norm = (rel(E, Er), rel(g, gr), rel(H, Hr))
+    print(f"  per-factor/bound {worst[0]:.2e} {worst[1]:.2e} {worst[2]:.2e}; "
+          f"normwise {norm[0]:.2e} {norm[1]:.2e} {norm[2]:.2e}", flush=True)
+    assert np.abs(Er).max() > 0, "the workload must activate hinge terms"
+    tol = TOL64 if precision == 0 else TOLMIX
+    assert worst.max() < tol, worst
+    pg.pgvimp_destroy(ctx)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_sparse_and_tensor_plans_in_one_batch(pg, precision):
+    """Plans with tensor rules and sparse rules of two levels share one
+    context and one solve; each plan's expectations equal those it gets
+    alone (the launch filters plans by rule, and sparse plans of every
+    level run in one launch)."""
+    probs = []
+    for k, quad in ((4, "tensor"), (10, "sparse"), (5, "sparse"), (10, "tensor")):
+        p = workloads.point2d_problem(3, N=60, gh_points=k)
+        p["quadrature"] = quad
+        probs.append(p)
+    ctx = pg.pgvimp_create(probs, precision=precision, use_graph=False)
+    both = [pg.pgvimp_factor_expectations(ctx, k) for k in range(len(probs))]
+    pg.pgvimp_solve(ctx, 2)
+    after = [pg.pgvimp_get_state(ctx, k)[0] for k in range(len(probs))]
+    pg.pgvimp_destroy(ctx)
+    for k, p in enumerate(probs):
+        c1 = pg.pgvimp_create([p], precision=precision, use_graph=False)
+        alone = pg.pgvimp_factor_expectations(c1, 0)
+        assert all(np.array_equal(u, v) for u, v in zip(both[k], alone)), k
+        pg.pgvimp_solve(c1, 2)
+        assert np.array_equal(pg.pgvimp_get_state(c1, 0)[0], after[k]), k
+        pg.pgvimp_destroy(c1)
