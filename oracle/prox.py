@@ -18,6 +18,17 @@ if no trial passes the state is left unchanged.  The paper prints neither
 the bound nor the bisection constants; halving from beta_max is the reading
 used.  The KL is evaluated in the rearranged form of kl_step.
 
+Natural-gradient variant (Sec. 3.1(d), eq. ngd_proximal; problem key
+"update" = "ngd"): the proximal term is the symmetric KL, whose second-order
+form is the Fisher metric, so the step is natural-gradient descent on
+J(q) = E[psi] - T H(q).  Read in the natural parameters (Lambda mu,
+-Lambda / 2), where the Fisher-preconditioned gradient is the gradient with
+respect to the mean parameters (mu, Sigma + mu mu^T):
+    Lambda' = Lambda_k + beta (K^-1 + H - T Lambda_k)
+    Lambda' mu' = Lambda_k mu_k - beta [(K^-1 mu_k - eta + g) - (K^-1 + H - T Lambda_k) mu_k]
+The step size follows the same halving rule (Lambda' positive definite and
+KL(q' || q_k) <= kl_bound), with the KL in its plain banded form.
+
 Initial state (not stated in the paper): mu_0 = mu_bar, Lambda_0 = K^-1.
 """
 from __future__ import annotations
@@ -64,7 +75,7 @@ def kl_banded(mu1, Sig1, Soff1, logdet1, mu0, D0, U0, logdet0):
 def kl_step(prob, pri, st, H, beta, mu1, Sig1, Soff1, logdet1):
     """KL(q_{k+1} || q_k) for the step of size beta, evaluated stably.
 
-    Same quantity as kl_banded.  Because Lambda_k = (beta T + 1) Lambda' -
+    Same quantity as kl_banded (which the natural-gradient step uses).  Because Lambda_k = (beta T + 1) Lambda' -
     beta (K^-1 + H) exactly and tr(Lambda' Sigma') = dim, the trace term is
     tr(Lambda_k Sigma') - dim = beta (T dim - tr((K^-1 + H) Sigma')); this
     avoids subtracting dim from a sum of terms many orders of magnitude
@@ -72,6 +83,9 @@ def kl_step(prob, pri, st, H, beta, mu1, Sig1, Soff1, logdet1):
     condition number near 1e10, which leaves the textbook form with an
     absolute error of several nats).
     """
+    if update_rule(prob) == "ngd":
+        # Lambda_k is not a combination of Lambda' and K^-1 + H at beta T = 1
+        return kl_banded(mu1, Sig1, Soff1, logdet1, st["mu"], st["D"], st["U"], st["logdet"])
     N, n = mu1.shape
     T = prob["temperature"]
     trKH = np.einsum("iab,iba->", pri["D"] + H, Sig1)
@@ -99,8 +113,37 @@ def init_state(prob, pri, mu0=None):
     return {"mu": mu, "D": D, "U": U, "Sig": Sig, "Soff": Soff, "logdet": logdet}
 
 
+def update_rule(prob):
+    """'prox' (Theorem 1, the default) or 'ngd' (Sec. 3.1(d))."""
+    rule = prob.get("update", "prox")
+    if rule not in ("prox", "ngd"):
+        raise ValueError(f"unknown update rule {rule!r}")
+    return rule
+
+
+def trial_ngd(prob, pri, st, g, H, beta):
+    """Precision and mean of the natural-gradient step for one step size
+    (Sec. 3.1(d)); returns the same tuple as trial, the mean system being
+    Lambda' mu' = rhs."""
+    T = prob["temperature"]
+    # dJ/dm2 = 1/2 (K^-1 + H) - T/2 Lambda_k, as blocks of 2 dJ/dm2
+    GD = pri["D"] + H - T * st["D"]
+    GU = pri["U"] - T * st["U"]
+    # dJ/dm1 = dJ/dmu - 2 dJ/dm2 mu_k
+    grad_mu = prior_mod.block_matvec(pri["D"], pri["U"], st["mu"]) - pri["eta"] + g
+    grad_m1 = grad_mu - prior_mod.block_matvec(GD, GU, st["mu"])
+    # natural parameters (Lambda mu, -Lambda / 2) step by -beta (dJ/dm1, dJ/dm2)
+    Dn = st["D"] + beta * GD
+    Un = st["U"] + beta * GU
+    rhs = prior_mod.block_matvec(st["D"], st["U"], st["mu"]) - beta * grad_m1
+    return Dn, Un, Dn, Un, rhs
+
+
 def trial(prob, pri, st, g, H, beta):
-    """Precision and mean of Theorem 1 for one step size."""
+    """Precision and mean of Theorem 1 for one step size (or of the
+    natural-gradient step when the problem asks for it)."""
+    if update_rule(prob) == "ngd":
+        return trial_ngd(prob, pri, st, g, H, beta)
     T = prob["temperature"]
     Dn = (beta * (pri["D"] + H) + st["D"]) / (beta * T + 1.0)
     Un = (beta * pri["U"] + st["U"]) / (beta * T + 1.0)
