@@ -27,7 +27,7 @@ respect to the mean parameters (mu, Sigma + mu mu^T):
     Lambda' = Lambda_k + beta (K^-1 + H - T Lambda_k)
     Lambda' mu' = Lambda_k mu_k - beta [(K^-1 mu_k - eta + g) - (K^-1 + H - T Lambda_k) mu_k]
 The step size follows the same halving rule (Lambda' positive definite and
-KL(q' || q_k) <= kl_bound), with the KL in its plain banded form.
+KL(q' || q_k) <= kl_bound); see kl_step for how its KL is evaluated.
 
 Initial state (not stated in the paper): mu_0 = mu_bar, Lambda_0 = K^-1.
 """
@@ -75,7 +75,7 @@ def kl_banded(mu1, Sig1, Soff1, logdet1, mu0, D0, U0, logdet0):
 def kl_step(prob, pri, st, H, beta, mu1, Sig1, Soff1, logdet1):
     """KL(q_{k+1} || q_k) for the step of size beta, evaluated stably.
 
-    Same quantity as kl_banded (which the natural-gradient step uses).  Because Lambda_k = (beta T + 1) Lambda' -
+    Same quantity as kl_banded.  Because Lambda_k = (beta T + 1) Lambda' -
     beta (K^-1 + H) exactly and tr(Lambda' Sigma') = dim, the trace term is
     tr(Lambda_k Sigma') - dim = beta (T dim - tr((K^-1 + H) Sigma')); this
     avoids subtracting dim from a sum of terms many orders of magnitude
@@ -83,17 +83,22 @@ def kl_step(prob, pri, st, H, beta, mu1, Sig1, Soff1, logdet1):
     condition number near 1e10, which leaves the textbook form with an
     absolute error of several nats).
     """
-    if update_rule(prob) == "ngd":
-        # Lambda_k is not a combination of Lambda' and K^-1 + H at beta T = 1
-        return kl_banded(mu1, Sig1, Soff1, logdet1, st["mu"], st["D"], st["U"], st["logdet"])
     N, n = mu1.shape
     T = prob["temperature"]
+    scale = 1.0
+    if update_rule(prob) == "ngd":
+        # natural-gradient step: Lambda_k = (Lambda' - beta (K^-1 + H)) / (1 - beta T),
+        # so the same trace term divided by 1 - beta T.  Near beta T = 1,
+        # Lambda' hardly involves Lambda_k and the plain form is used.
+        scale = 1.0 - beta * T
+        if abs(scale) < 0.25:
+            return kl_banded(mu1, Sig1, Soff1, logdet1, st["mu"], st["D"], st["U"], st["logdet"])
     trKH = np.einsum("iab,iba->", pri["D"] + H, Sig1)
     if N > 1:
         trKH += 2.0 * np.einsum("iab,iab->", pri["U"], Soff1)
     d = mu1 - st["mu"]
     quad = np.sum(d * prior_mod.block_matvec(st["D"], st["U"], d))
-    return 0.5 * (beta * (T * N * n - trKH) + quad + logdet1 - st["logdet"])
+    return 0.5 * (beta * (T * N * n - trKH) / scale + quad + logdet1 - st["logdet"])
 
 
 def kl_dense(mu1, S1, mu0, S0):

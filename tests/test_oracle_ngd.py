@@ -198,19 +198,37 @@ def test_ngd_and_theorem_1_share_the_fixed_point():
             assert np.abs(m1 - mu).max() < 1e-10 * max(1.0, np.abs(mu).max()), (rule, beta)
 
 
-def test_ngd_step_uses_the_plain_kl_and_rejects_unknown_rules():
+@pytest.mark.parametrize("temperature,beta", [(1.0, 0.4), (1.0, 1.0), (0.5, 1.9), (2.0, 0.9), (0.8, 3.0)])
+def test_ngd_step_kl_equals_the_dense_kl(temperature, beta):
+    """The step rule's KL (rearranged with Lambda_k = (Lambda' - beta (K^-1 +
+    H)) / (1 - beta T), plain near beta T = 1) against numpy's dense KL."""
+    prob = dict(workloads.free_problem(n_dof=2, N=5, temperature=temperature), update="ngd")
+    pri = prior.build_prior(prob)
+    N, n = prob["N"], prob["n"]
+    rng = np.random.default_rng(3)
+    Hc, g0 = _surrogate(rng, N, n)
+    D, U = rand_chain(rng, N, n)
+    mu = pri["mu_bar"] + 0.2 * rng.normal(size=(N, n))
+    S, So, ld = gbp.gbp_marginals(D, U)
+    st = {"mu": mu, "D": D, "U": U, "Sig": S, "Soff": So, "logdet": ld}
+    g = np.einsum("iab,ib->ia", Hc, mu) + g0
+    Dn, Un, MD, MU, rhs = prox.trial(prob, pri, st, g, Hc, beta)
+    Lam1 = prior.dense_from_blocks(Dn, Un)
+    assert np.linalg.eigvalsh(Lam1).min() > 0
+    S1, So1, ld1 = gbp.gbp_marginals(Dn, Un)
+    mu1 = prior.banded_solve(MD, MU, rhs)
+    kl = prox.kl_step(prob, pri, st, Hc, beta, mu1, S1, So1, ld1)
+    Sq = np.linalg.inv(Lam1)
+    Sk = np.linalg.inv(prior.dense_from_blocks(D, U))
+    dense = prox.kl_dense(mu1.ravel(), Sq, mu.ravel(), Sk)
+    assert abs(kl - dense) < 1e-8 * max(1.0, abs(dense)), (kl, dense)
+
+
+def test_unknown_update_rule_is_rejected():
     prob = workloads.free_problem(n_dof=2, N=5)
     pri = prior.build_prior(prob)
     st = prox.init_state(prob, pri, pri["mu_bar"] + 0.2)
     N, n = prob["N"], prob["n"]
     H = np.zeros((N, n, n))
-    Dn, Un, MD, MU, rhs = prox.trial(dict(prob, update="ngd"), pri, st, np.zeros((N, n)), H, 0.4)
-    S1, So1, ld1 = gbp.gbp_marginals(Dn, Un)
-    mu1 = prior.banded_solve(MD, MU, rhs)
-    kl = prox.kl_step(dict(prob, update="ngd"), pri, st, H, 0.4, mu1, S1, So1, ld1)
-    Sq = np.linalg.inv(prior.dense_from_blocks(Dn, Un))
-    Sk = np.linalg.inv(prior.dense_from_blocks(st["D"], st["U"]))
-    dense = prox.kl_dense(mu1.ravel(), Sq, st["mu"].ravel(), Sk)
-    assert abs(kl - dense) < 1e-9 * max(1.0, abs(dense))
     with pytest.raises(ValueError):
         prox.trial(dict(prob, update="sgd"), pri, st, np.zeros((N, n)), H, 0.4)
