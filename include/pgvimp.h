@@ -65,6 +65,15 @@ extern "C" {
 #define PGVIMP_COLL_ARM3D 3   /* 7 joint angles x[ci0..6] -> forward kinematics
                                  of a serial chain -> spheres, trilinear SDF  */
 
+/* update rules of one iteration */
+#define PGVIMP_UPDATE_PROX 0 /* KL-proximal step of Theorem 1 (eq.
+                                mu_Sigma_update)                             */
+#define PGVIMP_UPDATE_NGD 1  /* natural-gradient step (Sec. 3.1(d), eq.
+                                ngd_proximal): descent on J = E[psi] - T H(q)
+                                in the natural parameters,
+                                Lambda' = Lambda_k + beta (K^-1 + H - T Lambda_k),
+                                Lambda' (mu' - mu_k) = -beta (K^-1 mu_k - eta + g) */
+
 /* quadrature rules of the collision expectations */
 #define PGVIMP_QUAD_TENSOR 0 /* tensor Gauss-Hermite, p points per axis       */
 #define PGVIMP_QUAD_SPARSE 1 /* Smolyak combination of Gauss-Hermite tensor
@@ -140,6 +149,10 @@ typedef struct pgvimp_problem {
                               axis (p^d nodes); PGVIMP_QUAD_SPARSE: Smolyak
                               sparse grid of level k = gh_points (Sec. 4.3
                               Lemma 1), exact to total degree 2k - 1      */
+    int32_t update;        /* PGVIMP_UPDATE_PROX or PGVIMP_UPDATE_NGD; both
+                              use the same step-size rule (halving from
+                              beta_max until Lambda' is positive definite
+                              and KL(q' || q_k) <= kl_bound)              */
 } pgvimp_problem;
 
 /*

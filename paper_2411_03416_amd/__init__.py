@@ -110,7 +110,8 @@ def problem_struct(prob, mu_init=None):
         s.mu_init = _dptr(arr(np.asarray(mu_init).reshape(N, n)))
     s.segments = int(prob.get("segments", _tuned_segments(prob)))
     s.expect_group = int(prob.get("expect_group", 0))
-    s.quadrature = _abi.QUAD_SPARSE if prob.get("quadrature", "tensor") == "sparse" else _abi.QUAD_TENSOR
+    s.quadrature = {"tensor": _abi.QUAD_TENSOR, "sparse": _abi.QUAD_SPARSE}[prob.get("quadrature", "tensor")]
+    s.update = {"prox": _abi.UPDATE_PROX, "ngd": _abi.UPDATE_NGD}[prob.get("update", "prox")]
     return s, keep
 
 

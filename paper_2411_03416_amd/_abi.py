@@ -15,6 +15,7 @@ OK, EINVAL, ENOMEM, ENOTPD, ENOCONV, EDEVICE, EBUSY = 0, -1, -2, -3, -4, -5, -6
 FP64, MIXED = 0, 1
 COLL_NONE, COLL_POINT2D, COLL_POINT3D, COLL_ARM3D = 0, 1, 2, 3
 QUAD_TENSOR, QUAD_SPARSE = 0, 1
+UPDATE_PROX, UPDATE_NGD = 0, 1
 MODEL_QUAD2D = 1
 MAX_COLL_DIM, MAX_SPHERES, ARM_DOF = 8, 32, 7
 KERNEL_KINDS = ("expect", "prep", "trial", "select", "restart")
@@ -46,7 +47,7 @@ class Problem(C.Structure):
         ("fk_axes", _ip), ("fk_sphere_link", _ip),
         ("mu_init", _dp),
         ("segments", C.c_int32), ("expect_group", C.c_int32),
-        ("quadrature", C.c_int32),
+        ("quadrature", C.c_int32), ("update", C.c_int32),
     ]
 
 

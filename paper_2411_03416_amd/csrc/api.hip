@@ -381,6 +381,8 @@ int validate_problem(pgvimp_ctx* c, const pgvimp_problem* p) {
     for (int k = 0; k < d; ++k)
         if (p->coll_index[k] < 0 || p->coll_index[k] >= n) FAIL(c, PGVIMP_EINVAL, "coll_index out of range");
     const int group = p->expect_group > 0 ? p->expect_group : c->cfg.expect_group;
+    if (p->update != PGVIMP_UPDATE_PROX && p->update != PGVIMP_UPDATE_NGD)
+        FAIL(c, PGVIMP_EINVAL, "unknown update rule %d", p->update);
     if (p->quadrature != PGVIMP_QUAD_TENSOR && p->quadrature != PGVIMP_QUAD_SPARSE)
         FAIL(c, PGVIMP_EINVAL, "unknown quadrature %d", p->quadrature);
     if (!expect_supported(p->coll_kind, d, p->gh_points, group, p->quadrature))
@@ -827,6 +829,7 @@ int pgvimp_add_plan(pgvimp_ctx* c, const pgvimp_problem* p, int32_t* plan_out) {
     pd.d = coll ? coll_dim_of(p->coll_kind) : 0;
     pd.gh_points = p->gh_points;
     pd.quadrature = coll ? p->quadrature : PGVIMP_QUAD_TENSOR;
+    pd.update = p->update;
     pd.rule_n = dcol > 0 ? (int32_t)(rule_vals / (dcol + 1)) : 0;
     pd.rule64 = rule_vals > 0 ? rule64 : nullptr;
     pd.rule32 = rule_vals > 0 ? rule32 : nullptr;

@@ -33,7 +33,10 @@
 // trial back in state order.
 //
 // The same elimination with a right-hand side solves
-// (K^-1 + Lambda_k / beta) mu' = eta - g + Lambda_k mu_k / beta.
+// (K^-1 + Lambda_k / beta) mu' = eta - g + Lambda_k mu_k / beta, or for the
+// natural-gradient step (Sec. 3.1(d)) Lambda' mu' / beta =
+// eta - g + H mu_k + (1 / beta - T) Lambda_k mu_k with
+// Lambda' / beta = K^-1 + H + (1 / beta - T) Lambda_k.
 //
 // Step-size selection.  Halving from beta_max accepts the first trial step
 // that passes (Alg. 1, App. C), so the trials are independent of each
@@ -1299,7 +1302,8 @@ __device__ __forceinline__ double block_sum(double v, double* sh) { return wg_su
 
 // One proximal iteration (Alg. 1), part 1: per-state quantities shared by all
 // trial step sizes, written in chain order -- KH = K^-1 + H (collision
-// Hessians on the diagonal blocks), rb = eta - g, Lmu = Lambda_k mu_k, and
+// Hessians on the diagonal blocks), rb = eta - g (eta - g + H mu_k for the
+// natural-gradient step), Lmu = Lambda_k mu_k, and
 // copies of K^-1, Lambda_k and mu_k -- and the expected costs (per-block
 // partial sums; the select kernel adds them in block order).
 // Grid (plans, iter_blocks), kIterThreads threads, grid-stride over states.
@@ -1376,6 +1380,22 @@ PG_UNROLL
         PG_VEC(acc, lt);
         ld_soa<n>(st.LD, S, s, Dm);
         ld_vec<n>(st.mu, S, s, m);
+        if (p.update == PGVIMP_UPDATE_NGD && act) {
+            // natural-gradient step: H mu_k on the collision coordinates
+            for (int a = 0; a < d; ++a) {
+                double h = 0.0;
+                for (int b = 0; b < d; ++b) {
+                    const int cb = p.coll_index[b];
+                    double mb = 0.0;
+PG_UNROLL
+                    for (int e = 0; e < n; ++e) mb = e == cb ? m[e] : mb;
+                    h = fma(st.Hcol[(a * d + b) * S + s], mb, h);
+                }
+                const int ca = p.coll_index[a];
+PG_UNROLL
+                for (int e = 0; e < n; ++e) r[e] += e == ca ? h : 0.0;
+            }
+        }
         if (notlast) {
             ld_soa<n>(st.LU, S, s, Um);
             ld_vec<n>(st.mu, S, s + 1, mn);
@@ -1440,13 +1460,19 @@ PG_UNROLL
 // so a plan's trials share one or two L2s.  In the uniform window, plan q
 // runs on XCD q mod 8 (live plans spread over the XCDs even when they hold
 // neighbouring slots of a larger context).
-// For that step size:
+// For that step size (Theorem 1):
 //   Lambda' = (beta (K^-1 + H) + Lambda_k) / (beta T + 1)  -> marginals, log det, PD
 //   (K^-1 + Lambda_k / beta) mu' = eta - g + Lambda_k mu_k / beta
 //   KL(q' || q_k) = 1/2 [beta (T dim - tr((K^-1 + H) Sigma')) + dmu^T Lambda_k dmu
 //                        + log det Lambda' - log det Lambda_k]
 // (the trace term uses Lambda_k = (beta T + 1) Lambda' - beta (K^-1 + H) and
-// tr(Lambda' Sigma') = dim).  Results go to the trial slot (chain order) and
+// tr(Lambda' Sigma') = dim).  The natural-gradient step (Sec. 3.1(d)) takes
+//   Lambda' = (1 - beta T) Lambda_k + beta (K^-1 + H)
+//   (K^-1 + H + (1 / beta - T) Lambda_k) mu' = eta - g + H mu_k + (1 / beta - T) Lambda_k mu_k
+// and the trace term beta (T dim - tr((K^-1 + H) Sigma')) / (1 - beta T)
+// (Lambda_k = (Lambda' - beta (K^-1 + H)) / (1 - beta T)), or where
+// |1 - beta T| < 1/4 the plain tr(Lambda_k Sigma') - dim, Lambda' then
+// hardly involving Lambda_k.  Results go to the trial slot (chain order) and
 // st.tres (passed, KL, log det, slot).  PAD: see the node scratch below.
 template <int n, bool PAD>
 __global__ void __launch_bounds__(kTrialThreads) trial_kernel(DevState st, int phw) {
@@ -1493,6 +1519,9 @@ __global__ void __launch_bounds__(kTrialThreads) trial_kernel(DevState st, int p
     const double beta = ldexp(p.beta_max, -tt);
     const double T = p.temperature;
     const double c = 1.0 / fma(beta, T, 1.0);
+    const bool ngd = p.update == PGVIMP_UPDATE_NGD;
+    const double omt = fma(-beta, T, 1.0);  // 1 - beta T
+    const bool plain = ngd && fabs(omt) < 0.25;
     // views of the plan's inputs and of this trial slot's outputs
     const double *kh = st.cKH + coff * NN, *kd = st.cKD + coff * NN, *lD = st.cLD + coff * NN;
     const double *ku = st.cKU + coff * NN, *lU = st.cLU + coff * NN;
@@ -1507,10 +1536,15 @@ __global__ void __launch_bounds__(kTrialThreads) trial_kernel(DevState st, int p
     double* sh_t = NodeLds<n>::value ? sg_lds : sh_t_own;
     double part = 0.0, ld_trial = 0.0;
     if (half == 0) {
-        BlockSrc MT{kh, lD, ku, lU, kh, lD, c * beta, c};
+        // the trace term reads the first source: K^-1 + H, or Lambda_k for
+        // the plain form
+        const BlockSrc MT = plain ? BlockSrc{lD, kh, lU, ku, lD, kh, omt, beta}
+                            : ngd ? BlockSrc{kh, lD, ku, lU, kh, lD, beta, omt}
+                                  : BlockSrc{kh, lD, ku, lU, kh, lD, c * beta, c};
         wg_gbp<n, true>(MT, ws, lane, N, nseg, sg, tsd, tsu, &ld_trial, sh_d, sh_i, &part, ts);
     } else {
-        BlockSrc MM{kd, lD, ku, lU, rb, lmu, 1.0, 1.0 / beta};
+        const BlockSrc MM = ngd ? BlockSrc{kh, lD, ku, lU, rb, lmu, 1.0, 1.0 / beta - T}
+                                : BlockSrc{kd, lD, ku, lU, rb, lmu, 1.0, 1.0 / beta};
         wg_solve<n, true>(MM, ws, lane, N, nseg, sg, tmu, sh_j, cmu, &part, ts);
     }
     sh_t[tid] = part;
@@ -1529,7 +1563,9 @@ __global__ void __launch_bounds__(kTrialThreads) trial_kernel(DevState st, int p
             for (int k = 0; k < kChainThreads; ++k) trKH += sh_t[k];
             for (int k = 0; k < kChainThreads; ++k) quad += sh_t[kChainThreads + k];
             res[0] = 1.0;
-            res[1] = 0.5 * (beta * (T * (double)N * n - trKH) + quad + ld_trial - p.logdet);
+            const double tk = beta * (T * (double)N * n - trKH);
+            const double trace = plain ? trKH - (double)N * n : ngd ? tk / omt : tk;
+            res[1] = 0.5 * (trace + quad + ld_trial - p.logdet);
             res[2] = ld_trial;
             res[3] = t;
             if (res[1] <= p.kl_bound) atomicMin(&st.plans[pid].firstpass, tt);
@@ -1566,8 +1602,12 @@ __global__ void __launch_bounds__(kIterThreads) select_kernel(DevState st, int /
         beta = ldexp(p.beta_max, -pick);
         kl = res[1];
         ld = res[2];
+        // the trial's precision, with the same operations as the trial kernel
+        const bool ngd = p.update == PGVIMP_UPDATE_NGD;
         const double c = 1.0 / fma(beta, p.temperature, 1.0);
-        const double a0 = c * beta, a1 = c;
+        const double omt = fma(-beta, p.temperature, 1.0);
+        const bool plain = ngd && fabs(omt) < 0.25;
+        const double a0 = plain ? omt : ngd ? beta : c * beta, a1 = plain ? beta : ngd ? omt : c;
         for (int i = y * kIterThreads + tid; i < N; i += nb * kIterThreads) {
             const int64_t s = off + i, qs = coff + chain_pos(N, nseg, i), q = (int64_t)slot * st.Sc + qs;
             const bool notlast = i < N - 1;
@@ -1589,10 +1629,10 @@ __global__ void __launch_bounds__(kIterThreads) select_kernel(DevState st, int /
                 for (int k = 0; k < CH; ++k) {
                     const int e = e0 + k;
                     if (e >= NN) break;
-                    st.LD[e * S + s] = lin2(a0, kh[k], a1, ld[k]);
+                    st.LD[e * S + s] = plain ? lin2(a0, ld[k], a1, kh[k]) : lin2(a0, kh[k], a1, ld[k]);
                     st.SD[e * S + s] = sd[k];
                     if (notlast) {
-                        st.LU[e * S + s] = lin2(a0, ku[k], a1, lu[k]);
+                        st.LU[e * S + s] = plain ? lin2(a0, lu[k], a1, ku[k]) : lin2(a0, ku[k], a1, lu[k]);
                         st.SU[e * S + s] = su[k];
                     }
                 }

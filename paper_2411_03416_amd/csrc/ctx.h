@@ -48,6 +48,7 @@ struct PlanDev {
     int32_t coff;   // start of the plan's chain-order range (capacity Sc)
     int32_t coll_index[PGVIMP_MAX_COLL_DIM];
     int32_t quadrature;  // PGVIMP_QUAD_*
+    int32_t update;      // PGVIMP_UPDATE_*
     int32_t rule_n;      // sparse rule: nodes (rows of rule64 / rule32)
     const double* rule64;  // sparse rule rows (xi[0..d-1], W), FP64
     const float* rule32;   // the same rows in FP32

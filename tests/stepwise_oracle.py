@@ -24,8 +24,14 @@ from oracle import collision, gbp, prior, prox, slr
 
 @functools.lru_cache(maxsize=8)
 def problem(kind, seed):
-    return {"config0": workloads.config0_problem, "config1": workloads.config1_problem,
-            "config2": workloads.config2_problem, "config3": workloads.config3_problem}[kind](seed=seed)
+    """The configuration's problem; kind "<config>_ngd" takes the
+    natural-gradient step (Sec. 3.1(d)) instead of Theorem 1's."""
+    base, _, rule = kind.partition("_")
+    p = {"config0": workloads.config0_problem, "config1": workloads.config1_problem,
+         "config2": workloads.config2_problem, "config3": workloads.config3_problem}[base](seed=seed)
+    if rule:
+        p = dict(p, update=rule)
+    return p
 
 
 def _perturb(rng, x, n, sym=False):

@@ -255,6 +255,21 @@ def test_config3_rounds_every_step(pg, pool, precision):
            ["config3"] * len(all_states), seeds * n_rounds)
 
 
+@pytest.mark.parametrize("config,plans", [("config0", 32), ("config1", 8)])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_natural_gradient_every_step(pg, pool, config, plans, precision):
+    """The natural-gradient step (Sec. 3.1(d)) under the same step-size rule:
+    every step of 20 iterations checked as above (configs 0 and 1)."""
+    seeds = list(range(plans))
+    kind = config + "_ngd"
+    probs = [so.problem(kind, s) for s in seeds]
+    print(f"{kind} stepwise precision {precision}", flush=True)
+    K, states, stats = _gpu_steps(pg, probs, precision, 20)
+    tasks, keys = _tasks(kind, seeds, K, states, stats)
+    _check(f"{kind} precision {precision}", keys, pool.map(so.one_step, tasks, chunksize=2), states, stats,
+           precision, [kind] * plans, seeds)
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_temperature_schedule_every_step(pg, pool, precision):
     """Two-phase schedule of Sec. 7: low temperature until the plan is clear
