@@ -58,6 +58,9 @@ def parse():
                     help="--expect-sweep: plans k and k+32 share a map, or every plan has its own copy")
     ap.add_argument("--expect-sweep", action="store_true",
                     help="time the expectation kernel alone over a batch sweep (32 plans, growing N)")
+    ap.add_argument("--paper-tables", action="store_true",
+                    help="the shapes of the paper's efficiency tables (Sec. 7.1) instead of the headline line")
+    ap.add_argument("--tables-iters", type=int, default=20, help="iterations of the whole-optimisation table")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a 512 MiB copy kernel once (known traffic, to scale memory counters)")
     return ap.parse_args()
@@ -245,6 +248,168 @@ print(time.perf_counter() - t0)
 """
 
 
+_TABLE_CPU = """
+import json, sys, time
+sys.path.insert(0, {root!r})
+import numpy as np
+import workloads
+from oracle import collision, gbp, prior, prox
+p = workloads.{make}
+p["quadrature"] = "sparse"
+p["gh_points"] = {level}
+pri = prior.build_prior(p)
+out = {{}}
+t0 = time.perf_counter()
+st = prox.init_state(p, pri)
+out["gbp_s"] = time.perf_counter() - t0
+# every stride-th factor, scaled to all of them (the arm's take ~0.5 s each)
+ci = np.asarray(p["coll_index"])
+every = collision.collision_states(p)
+sample = every[::{stride}]
+t0 = time.perf_counter()
+for i in sample:
+    collision.factor_expectation(p, st["mu"][i][ci], st["Sig"][i][np.ix_(ci, ci)])
+out["expect_s"] = (time.perf_counter() - t0) * len(every) / len(sample)
+out["expect_sampled"] = int(len(sample))
+if {iteration}:
+    t0 = time.perf_counter()
+    prox.prox_iteration(p, pri, st)
+    out["iteration_s"] = time.perf_counter() - t0
+print(json.dumps(out))
+"""
+
+
+def paper_tables(args, pg):
+    """The shapes of the paper's efficiency tables (Sec. 7.1) on one MI355X,
+    on synthetic maps and a synthetic 7-joint chain (the paper's maps and
+    WAM model are not available), one trajectory per row:
+      expected collision cost (Table cost_time_comparison): N = 750, Smolyak
+        level 10 on the 2-D and 3-D point robots' positions, level 6 on the
+        arm's 7 joints; GPU = one expectation launch (kernel time from HIP
+        events), FP64 and mixed; CPU = the oracle's expectations of the same
+        marginals, one thread (serial);
+      marginal covariances (Table Inverse_comparison): precisions of
+        dimension 5000 (n = 4, N = 1250), 4998 (n = 6, N = 833) and 4998
+        (n = 14, N = 357), the GP prior's K^-1; GPU GBP = pgvimp_marginals
+        with no outputs (chain kernel and plan bookkeeping, wall clock);
+        brute force = the dense inverse of the same matrix: torch.linalg.inv
+        (LU) and the Cholesky inverse on the GPU (FP64, hipSOLVER) and
+        numpy.linalg.inv on the host (all threads), and the oracle's serial
+        GBP;
+      whole optimisation (Table total_cost_time_comparison): the expected
+        cost rows' problems, prior build + initial marginals + `tables_iters`
+        iterations (the paper does not print its count) with pgvimp_solve,
+        FP64 and mixed; CPU = the oracle's time for one iteration, times the
+        iteration count (a full serial run takes minutes per row); for the
+        arm, whose oracle expectations take ~0.5 s per factor, the
+        expectations of every 38th factor scaled to all, and the whole run
+        bounded below by the expectations alone."""
+    import numpy as np
+    import torch
+    import workloads
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+
+    def cpu_leg(make, iteration, level=2, stride=1):
+        if args.no_cpu:
+            return None
+        print(f"tables: oracle leg {make}", flush=True)
+        r = subprocess.run([sys.executable, "-c", _TABLE_CPU.format(root=ROOT, make=make, iteration=iteration,
+                                                                    level=level, stride=stride)],
+                           capture_output=True, text=True, env=env, timeout=900)
+        if r.returncode != 0:
+            return {"error": r.stderr[-400:]}
+        return json.loads(r.stdout.strip().splitlines()[-1])
+
+    # (problem, Smolyak level, oracle sampling stride, oracle iteration timed)
+    rows = {"point2d": ("config1_problem(seed=0, N=750)", 10, 1, True),
+            "point3d": ("point3d_problem(0, N=750)", 10, 3, True),
+            "arm": ("arm_problem(0, N=750)", 6, 38, False)}
+    t1, t3 = {}, {}
+    for name, (make, level, stride, whole) in rows.items():
+        prob = eval("workloads." + make)
+        prob.update(quadrature="sparse", gh_points=level, n_iters=args.tables_iters)
+        print(f"tables: {name} level {level}", flush=True)
+        r1 = {"N": prob["N"], "rule": f"Smolyak level {level}"}
+        r3 = {"N": prob["N"], "iters": args.tables_iters}
+        for pname, prec in (("mixed", pg.MIXED), ("fp64", pg.FP64)):
+            ctx = pg.pgvimp_create([prob], precision=prec, use_graph=False)
+            pg.pgvimp_expect_all(ctx, 2)
+            pg.pgvimp_profile(ctx, True)
+            pg.pgvimp_kernel_times(ctx, reset=True)
+            pg.pgvimp_expect_all(ctx, 10)
+            r1[pname + "_ms"] = pg.pgvimp_kernel_times(ctx, reset=True)["expect"][0]
+            print(f"tables: {name} {pname} expectations {r1[pname + '_ms']:.3f} ms", flush=True)
+            pg.pgvimp_profile(ctx, False)
+            # one solve, kernels launched directly (a graph would be captured
+            # for this single run); every kernel has run once already
+            # (prior build and marginals at creation, expectations above)
+            res = {}
+            dt = _timed(lambda: res.update(pg.pgvimp_solve(ctx, args.tables_iters)), 1)
+            r3[pname + "_s"] = dt
+            r3[pname + "_status"] = res[0]["status"]
+            r3[pname + "_E_coll"] = res[0]["E_coll"]
+            print(f"tables: {name} {pname} solve {dt:.3f} s", flush=True)
+            pg.pgvimp_destroy(ctx)
+        cpu = cpu_leg(make, whole, level, stride)
+        if cpu is not None and "error" not in cpu:
+            r1["cpu_oracle_ms"] = 1e3 * cpu["expect_s"]
+            r1["cpu_oracle_sample"] = f"{cpu['expect_sampled']} of {prob['N']} factors, scaled"
+            if whole:
+                r3["cpu_oracle_s_per_iteration"] = cpu["iteration_s"]
+                r3["cpu_oracle_s_estimate"] = cpu["iteration_s"] * args.tables_iters
+            else:
+                # the expectations alone: a lower bound of the serial run
+                r3["cpu_oracle_s_lower_bound"] = cpu["expect_s"] * args.tables_iters
+        elif cpu is not None:
+            r1["cpu_error"] = cpu["error"]
+        t1[name], t3[name] = r1, r3
+    t2 = {}
+    for name, make in (("point2d", "config1_problem(seed=0, N=1250)"), ("point3d", "point3d_problem(0, N=833)"),
+                       ("arm", "arm_problem(0, N=357)")):
+        prob = eval("workloads." + make)
+        print(f"tables: marginals {name}", flush=True)
+        ctx = pg.pgvimp_create([prob], precision=pg.FP64, use_graph=False)
+        lib = pg._abi.load()
+
+        def gbp():
+            pg._check(lib.pgvimp_marginals(ctx.handle, 0, None, None, None), ctx.handle)
+
+        gbp()
+        row = {"dim": prob["N"] * prob["n"], "n": prob["n"], "N": prob["N"], "gpu_gbp_ms": 1e3 * _timed(gbp, 20)}
+        _, D, U = pg.pgvimp_get_state(ctx, 0)
+        pg.pgvimp_destroy(ctx)
+        n, N = prob["n"], prob["N"]
+        L = np.zeros((N * n, N * n))
+        for i in range(N):
+            L[i * n:(i + 1) * n, i * n:(i + 1) * n] = D[i]
+            if i < N - 1:
+                L[i * n:(i + 1) * n, (i + 1) * n:(i + 2) * n] = U[i]
+                L[(i + 1) * n:(i + 2) * n, i * n:(i + 1) * n] = U[i].T
+        Lg = torch.from_numpy(L).cuda()
+        # the default linear-algebra backend's triangular solves fail to get
+        # their workspace at this size on this stack; hipSOLVER's do not
+        torch.backends.cuda.preferred_linalg_library("cusolver")
+        torch.linalg.inv(Lg)
+        row["gpu_dense_inverse_ms"] = 1e3 * _timed(lambda: torch.linalg.inv(Lg), 5)
+        torch.cholesky_inverse(torch.linalg.cholesky(Lg))
+        row["gpu_dense_cholesky_inverse_ms"] = 1e3 * _timed(lambda: torch.cholesky_inverse(torch.linalg.cholesky(Lg)),
+                                                            5)
+        del Lg
+        t0 = time.perf_counter()
+        np.linalg.inv(L)
+        row["cpu_dense_inverse_ms"] = 1e3 * (time.perf_counter() - t0)
+        cpu = cpu_leg(make, False)
+        if cpu is not None and "error" not in cpu:
+            row["cpu_oracle_gbp_ms"] = 1e3 * cpu["gbp_s"]
+        t2[name] = row
+    out = {"metric": "paper-shape tables (Sec. 7.1)", "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": "one trajectory per row; Smolyak levels 10/10/6; N = 750; precisions of "
+                                  "dimension 5000/4998/4998"},
+           "expected_collision_cost": t1, "marginal_covariances": t2, "whole_optimisation": t3,
+           "cpu_model": _cpu_model(), "nproc": os.cpu_count()}
+    print(json.dumps(out), flush=True)
+
+
 def _cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -313,6 +478,9 @@ def main():
         return
     if args.expect_sweep:
         expect_sweep(args, pg)
+        return
+    if args.paper_tables:
+        paper_tables(args, pg)
         return
 
     probs = make_batch(args.plans, args.N, args.iters)
