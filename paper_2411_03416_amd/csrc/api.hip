@@ -742,7 +742,9 @@ int pgvimp_add_plan(pgvimp_ctx* c, const pgvimp_problem* p, int32_t* plan_out) {
     }
     const int64_t soff = c->states.alloc(N);
     if (soff < 0) FAIL(c, PGVIMP_ENOMEM, "no room for %d states", N);
-    const int nseg = choose_segments(c, N, p->segments);
+    // n >= 6: the chain kernels sweep the whole plan from both ends (one
+    // wavefront per sweep), state order is chain order
+    const int nseg = c->n >= 6 ? 1 : choose_segments(c, N, p->segments);
     const int64_t clen = ((int64_t)((N + nseg - 1) / nseg) * nseg + 31) / 32 * 32;
     const int64_t coff = c->cstates.alloc(clen, 32);
     if (coff < 0) {

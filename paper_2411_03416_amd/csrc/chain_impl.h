@@ -1141,6 +1141,10 @@ __device__ __forceinline__ TS thread_ws(const DevState& st, int pid, int t) {
     double* base = st.tws + (((int64_t)pid * st.W + t) * kTrialThreads + threadIdx.x) * st.tws_stride;
     return TS{base, base + st.tws_stride, st.flags};
 }
+}  // namespace pg
+#include "coop.h"
+namespace pg {
+
 // Block temporaries of the chain and trial kernels in LDS (n = 6, plans of
 // at most kLdsWsSegments segments): a slice of STRIDE doubles per lane of
 // both halves, the stride odd so that the lanes of a wave spread over the
@@ -1148,7 +1152,7 @@ __device__ __forceinline__ TS thread_ws(const DevState& st, int pid, int t) {
 // work) and plans of more segments keep their workspace slices in HBM.
 template <int n>
 struct LdsWs {
-    static constexpr bool value = n == 6;
+    static constexpr bool value = n == 6 && !Coop<n>::value;
     static constexpr int STRIDE = (kTwsBlocks * n * n + kTwsVecs * n) | 1;
     static constexpr int size = value ? 2 * kLdsWsSegments * STRIDE : 1;
 };
@@ -1181,7 +1185,8 @@ __device__ __forceinline__ Ws sweep_ws(const DevState& st, int half, int64_t c0)
 // wave 0 computes the marginals while wave 1 solves for the mean; the other
 // modes run with one.
 template <int n>
-__global__ void __launch_bounds__(kTrialThreads) chain_kernel(DevState st, int mode, int plan_lo) {
+__global__ void __launch_bounds__(Coop<n>::value ? Coop<n>::THREADS : kTrialThreads)
+    chain_kernel(DevState st, int mode, int plan_lo) {
     __shared__ double sh_d[kChainThreads + 1];
     __shared__ int sh_i[kChainThreads + 1];
     __shared__ int sh_j[kChainThreads + 1];
@@ -1242,7 +1247,22 @@ __global__ void __launch_bounds__(kTrialThreads) chain_kernel(DevState st, int m
         }
     }
     __syncthreads();
-    if (half == 0) {
+    if constexpr (Coop<n>::value) {
+        // one wavefront per matrix: marginals on wave 0, the mean on wave 1
+        __shared__ double c_lds[2 * Coop<n>::WAVE_LDS];
+        __shared__ double c_sh[Coop<n>::THREADS + 4];
+        const double *d = cD + coff * NN, *u = cU + coff * NN;
+        const BlockSrc MT{d, d, u, u, d, d, 1.0, 0.0};
+        const double *kd = st.cKD + coff * NN, *ku = st.cKU + coff * NN, *r = st.crb + coff * n;
+        const BlockSrc MM{kd, kd, ku, ku, r, r, 1.0, 0.0};
+        coop_chain<n>(MT, MM, mode == CHAIN_INIT, N, sweep_ws<n>(st, 0, coff), sweep_ws<n>(st, 1, coff),
+                      st.TSD + coff * NN, st.TSU + coff * NN, st.Tmu + coff * n, nullptr, nullptr, nullptr, c_lds,
+                      c_sh);
+        if (tid == 0) {
+            sh_d[kChainThreads] = c_sh[0];
+            sh_i[kChainThreads] = c_sh[1] != 0.0 ? 1 : 0;
+        }
+    } else if (half == 0) {
         const double *d = cD + coff * NN, *u = cU + coff * NN;
         BlockSrc M{d, d, u, u, d, d, 1.0, 0.0};
         double ld = 0.0;
@@ -1475,7 +1495,8 @@ PG_UNROLL
 // hardly involving Lambda_k.  Results go to the trial slot (chain order) and
 // st.tres (passed, KL, log det, slot).  PAD: see the node scratch below.
 template <int n, bool PAD>
-__global__ void __launch_bounds__(kTrialThreads) trial_kernel(DevState st, int phw) {
+__global__ void __launch_bounds__(Coop<n>::value ? Coop<n>::THREADS : kTrialThreads)
+    trial_kernel(DevState st, int phw) {
     // work list, or (wlist[0] = -w) the uniform first window of width w
     const int head = st.wlist[0];
     const int kx = (int)blockIdx.x / kNumXcd, x = (int)blockIdx.x % kNumXcd;
@@ -1493,28 +1514,14 @@ __global__ void __launch_bounds__(kTrialThreads) trial_kernel(DevState st, int p
         if (kx >= chunk || j >= items) return;
         item = st.wlist[1 + j];
     }
-    __shared__ double sh_d[kChainThreads + 1];
-    __shared__ int sh_i[kChainThreads + 1];
-    __shared__ int sh_j[kChainThreads + 1];
     constexpr int NN = n * n;
     const int pid = item >> 6, t = item & 63;
     const PlanDev& p = st.plans[pid];
     if (!p.active || p.phase != 0 || t >= p.wwidth) return;
     const int tt = p.wstart + t;
     const int tid = threadIdx.x;
-    const int half = tid / kChainThreads, lane = tid % kChainThreads;
     const int N = p.N, nseg = p.nseg;
     const int64_t coff = p.coff, c0 = (int64_t)t * st.Sc + coff;
-    // With LDS node scratch a trial workgroup takes just under half a CU's
-    // LDS; with PAD, kTrialLdsPad unused bytes keep it to one workgroup per
-    // CU.  Two per CU run each other ~1.5x slower, and the dispatcher pairs
-    // them up even in windows smaller than the chip; only windows of more
-    // workgroups than CUs gain from pairs (1.12x the throughput).
-    __shared__ double sg_lds[NodeLds<n>::size + (NodeLds<n>::value && PAD ? kTrialLdsPad / 8 : 0)];
-    double* sg = NodeLds<n>::value ? sg_lds + half * kMaxSeg * SegLayout<n, false>::STRIDE : seg_scratch<n>(st, pid, t, half);
-    const Ws ws = sweep_ws<n>(st, half, c0);
-    __shared__ double ws_lds[LdsWs<n>::size];
-    TS ts = chain_ws<n>(st, ws_lds, pid, t, half, lane, nseg);
     double* res = st.tres + ((int64_t)pid * kMaxBisect + tt) * 4;
     const double beta = ldexp(p.beta_max, -tt);
     const double T = p.temperature;
@@ -1527,41 +1534,71 @@ __global__ void __launch_bounds__(kTrialThreads) trial_kernel(DevState st, int p
     const double *ku = st.cKU + coff * NN, *lU = st.cLU + coff * NN;
     const double *rb = st.crb + coff * n, *lmu = st.cLmu + coff * n, *cmu = st.cmu + coff * n;
     double *tsd = st.TSD + c0 * NN, *tsu = st.TSU + c0 * NN, *tmu = st.Tmu + c0 * n;
-    // wave 0: marginals and PD test of the trial precision, with the trace
-    // term; wave 1: trial mean, with the quadratic term.  Both helpers pass
-    // the same workgroup barriers.
-    // per-lane KL partial sums; with LDS node scratch they reuse it (both
-    // helpers end with a barrier after their last scratch access)
-    __shared__ double sh_t_own[NodeLds<n>::value ? 1 : kTrialThreads];
-    double* sh_t = NodeLds<n>::value ? sg_lds : sh_t_own;
-    double part = 0.0, ld_trial = 0.0;
-    if (half == 0) {
-        // the trace term reads the first source: K^-1 + H, or Lambda_k for
-        // the plain form
-        const BlockSrc MT = plain ? BlockSrc{lD, kh, lU, ku, lD, kh, omt, beta}
-                            : ngd ? BlockSrc{kh, lD, ku, lU, kh, lD, beta, omt}
-                                  : BlockSrc{kh, lD, ku, lU, kh, lD, c * beta, c};
-        wg_gbp<n, true>(MT, ws, lane, N, nseg, sg, tsd, tsu, &ld_trial, sh_d, sh_i, &part, ts);
+    // the trial precision (its trace term reads the first source: K^-1 + H,
+    // or Lambda_k for the plain form) and the mean system
+    const BlockSrc MT = plain ? BlockSrc{lD, kh, lU, ku, lD, kh, omt, beta}
+                        : ngd ? BlockSrc{kh, lD, ku, lU, kh, lD, beta, omt}
+                              : BlockSrc{kh, lD, ku, lU, kh, lD, c * beta, c};
+    const BlockSrc MM = ngd ? BlockSrc{kh, lD, ku, lU, rb, lmu, 1.0, 1.0 / beta - T}
+                            : BlockSrc{kd, lD, ku, lU, rb, lmu, 1.0, 1.0 / beta};
+    bool pd;
+    double ld_trial, trKH, quad;
+    if constexpr (Coop<n>::value) {
+        __shared__ double c_lds[2 * Coop<n>::WAVE_LDS];
+        __shared__ double c_sh[Coop<n>::THREADS + 4];
+        coop_chain<n>(MT, MM, true, N, sweep_ws<n>(st, 0, c0), sweep_ws<n>(st, 1, c0), tsd, tsu, tmu, cmu, MT.D0,
+                      MT.U0, c_lds, c_sh);
+        pd = c_sh[1] != 0.0;
+        ld_trial = c_sh[0];
+        trKH = c_sh[2];
+        quad = c_sh[3];
     } else {
-        const BlockSrc MM = ngd ? BlockSrc{kh, lD, ku, lU, rb, lmu, 1.0, 1.0 / beta - T}
-                                : BlockSrc{kd, lD, ku, lU, rb, lmu, 1.0, 1.0 / beta};
-        wg_solve<n, true>(MM, ws, lane, N, nseg, sg, tmu, sh_j, cmu, &part, ts);
-    }
-    sh_t[tid] = part;
-    __syncthreads();
-    if (tid == 0) {
-        const bool pd = sh_i[kChainThreads] != 0;
+        __shared__ double sh_d[kChainThreads + 1];
+        __shared__ int sh_i[kChainThreads + 1];
+        __shared__ int sh_j[kChainThreads + 1];
+        const int half = tid / kChainThreads, lane = tid % kChainThreads;
+        // With LDS node scratch a trial workgroup takes just under half a CU's
+        // LDS; with PAD, kTrialLdsPad unused bytes keep it to one workgroup per
+        // CU.  Two per CU run each other ~1.5x slower, and the dispatcher pairs
+        // them up even in windows smaller than the chip; only windows of more
+        // workgroups than CUs gain from pairs (1.12x the throughput).
+        __shared__ double sg_lds[NodeLds<n>::size + (NodeLds<n>::value && PAD ? kTrialLdsPad / 8 : 0)];
+        double* sg = NodeLds<n>::value ? sg_lds + half * kMaxSeg * SegLayout<n, false>::STRIDE
+                                       : seg_scratch<n>(st, pid, t, half);
+        const Ws ws = sweep_ws<n>(st, half, c0);
+        __shared__ double ws_lds[LdsWs<n>::size];
+        TS ts = chain_ws<n>(st, ws_lds, pid, t, half, lane, nseg);
+        // wave 0: marginals and PD test of the trial precision, with the trace
+        // term; wave 1: trial mean, with the quadratic term.  Both helpers pass
+        // the same workgroup barriers.
+        // per-lane KL partial sums; with LDS node scratch they reuse it (both
+        // helpers end with a barrier after their last scratch access)
+        __shared__ double sh_t_own[NodeLds<n>::value ? 1 : kTrialThreads];
+        double* sh_t = NodeLds<n>::value ? sg_lds : sh_t_own;
+        double part = 0.0, ld = 0.0;
+        if (half == 0)
+            wg_gbp<n, true>(MT, ws, lane, N, nseg, sg, tsd, tsu, &ld, sh_d, sh_i, &part, ts);
+        else
+            wg_solve<n, true>(MM, ws, lane, N, nseg, sg, tmu, sh_j, cmu, &part, ts);
+        sh_t[tid] = part;
+        __syncthreads();
+        pd = sh_i[kChainThreads] != 0;
         ld_trial = sh_d[kChainThreads];
+        // partial sums in lane order: trace from wave 0, quadratic from wave 1
+        trKH = 0.0;
+        quad = 0.0;
+        if (tid == 0) {
+            for (int k = 0; k < kChainThreads; ++k) trKH += sh_t[k];
+            for (int k = 0; k < kChainThreads; ++k) quad += sh_t[kChainThreads + k];
+        }
+    }
+    if (tid == 0) {
         if (!pd) {
             res[0] = 0.0;
             res[1] = NAN;
             res[2] = NAN;
             res[3] = t;
         } else {
-            // partial sums in lane order: trace from wave 0, quadratic from wave 1
-            double trKH = 0.0, quad = 0.0;
-            for (int k = 0; k < kChainThreads; ++k) trKH += sh_t[k];
-            for (int k = 0; k < kChainThreads; ++k) quad += sh_t[kChainThreads + k];
             res[0] = 1.0;
             const double tk = beta * (T * (double)N * n - trKH);
             const double trace = plain ? trKH - (double)N * n : ngd ? tk / omt : tk;
@@ -1693,7 +1730,7 @@ __global__ void __launch_bounds__(kChainThreads) prior_cost_kernel(DevState st, 
 template <int n>
 hipError_t launch_chain_n(const DevState& st, int mode, int lo, int hi, hipStream_t s) {
     if (hi <= lo) return hipSuccess;
-    const int threads = mode == CHAIN_INIT ? kTrialThreads : kChainThreads;
+    const int threads = Coop<n>::value ? Coop<n>::THREADS : mode == CHAIN_INIT ? kTrialThreads : kChainThreads;
     hipLaunchKernelGGL(chain_kernel<n>, dim3(hi - lo), dim3(threads), 0, s, st, mode, lo);
     return hipGetLastError();
 }
@@ -1708,10 +1745,11 @@ hipError_t launch_iteration_n(const DevState& st, int phw, int part, int round, 
     if (part == 1 || part == 5) {
         // covers a list of up to phw * W items and the uniform window
         const int64_t blocks = (int64_t)((phw + kNumXcd - 1) / kNumXcd) * kNumXcd * st.W;
+        const int threads = Coop<n>::value ? Coop<n>::THREADS : kTrialThreads;
         if (part == 5 && NodeLds<n>::value)
-            hipLaunchKernelGGL((trial_kernel<n, false>), dim3((unsigned)blocks), dim3(kTrialThreads), 0, s, st, phw);
+            hipLaunchKernelGGL((trial_kernel<n, false>), dim3((unsigned)blocks), dim3(threads), 0, s, st, phw);
         else
-            hipLaunchKernelGGL((trial_kernel<n, true>), dim3((unsigned)blocks), dim3(kTrialThreads), 0, s, st, phw);
+            hipLaunchKernelGGL((trial_kernel<n, true>), dim3((unsigned)blocks), dim3(threads), 0, s, st, phw);
     }
     if (part == 2) hipLaunchKernelGGL(select_kernel<n>, it, dim3(kIterThreads), 0, s, st, round);
     return hipGetLastError();

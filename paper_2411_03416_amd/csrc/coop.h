@@ -1,0 +1,465 @@
+// Chain factorizations for larger blocks (n >= 6), one wavefront per matrix.
+//
+// The marginals of a block-tridiagonal precision (Sec. 5.1: GBP on the
+// chain, equal to the selected inverse) are computed by a forward
+// elimination and a backward recursion:
+//   P_0 = D_0,  G_i = P_i^-1 U_i,  P_{i+1} = D_{i+1} - U_i^T G_i,
+//   Sigma_{N-1} = P_{N-1}^-1,
+//   Sigma_{i,i+1} = -G_i Sigma_{i+1},  Sigma_i = P_i^-1 - Sigma_{i,i+1} G_i^T.
+// log det Lambda is the sum of log det P_i, and Lambda is positive definite
+// iff every P_i is.  A linear system (D, U) x = r takes the same forward
+// elimination with y_0 = r_0, w_i = P_i^-1 y_i, y_{i+1} = r_{i+1} - U_i^T w_i,
+// and back substitution x_{N-1} = w_{N-1}, x_i = w_i - G_i x_{i+1}.  The
+// backward passes need products only, no inversion.  (GBP's two-sided
+// form, Sigma_ii = (P_i + Q_i - D_i)^-1 with the right Schur complements
+// Q_i, halves the depth but subtracts blocks far larger than the marginal
+// precision on stiff chains; this form does not.)
+//
+// Within a wavefront the 64 lanes share every block operation.  A block is
+// padded to NP x NP (NP = 8 for n = 6, else 16; a spare column carries a
+// right-hand side) and held in registers: lane l holds column l % NP of rows
+// l / NP + RSTEP t, t < EPL.  Products and factorizations exchange blocks
+// through a per-wavefront LDS area; the lanes of one wavefront execute in
+// lock step and LDS serves a wavefront's accesses in order, so a
+// wavefront-scope fence (no barrier) orders the exchanges.
+//
+// Included by chain_impl.h after its chain-order helpers (BlockSrc, Ws,
+// tiled offsets, lin2).
+#pragma once
+#include "blockmath.h"
+#include "ctx.h"
+
+namespace pg {
+
+template <int n>
+struct Coop {
+    static constexpr bool value = n >= 6;
+    static constexpr int NP = n <= 6 ? 8 : 16;    // padded block (one spare column at least)
+    static constexpr int EPL = NP * NP / 64;       // entries per lane
+    static constexpr int RSTEP = 64 / NP;          // rows between a lane's entries
+    static constexpr int LS = NP + 1;              // LDS row stride in doubles
+    static constexpr int BUF = NP * LS;            // one LDS block
+    static constexpr int WAVE_LDS = 3 * BUF + 2 * NP;  // three blocks and two vectors per wavefront
+    static constexpr int THREADS = 128;                // two wavefronts
+};
+
+// A block in registers: entry t of the lane is (row0 + RSTEP t, col).
+template <int n>
+struct DM {
+    double v[Coop<n>::EPL];
+};
+
+// Orders the LDS accesses of a wavefront before and after this point.
+__device__ __forceinline__ void wsync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int n>
+struct Lane {
+    int row0, col;
+    __device__ __forceinline__ explicit Lane(int lane) : row0(lane / Coop<n>::NP), col(lane % Coop<n>::NP) {}
+    __device__ __forceinline__ int row(int t) const { return row0 + Coop<n>::RSTEP * t; }
+};
+
+template <int n>
+__device__ __forceinline__ void dm_zero(DM<n>& X) {
+#pragma unroll
+    for (int t = 0; t < Coop<n>::EPL; ++t) X.v[t] = 0.0;
+}
+
+// Block at byte offset off of a tiled chain-order array (entry e = r n + c);
+// zero outside the n x n block.
+template <int n>
+__device__ __forceinline__ void dm_ld(const double* base, uint32_t off, const Lane<n>& L, DM<n>& X) {
+#pragma unroll
+    for (int t = 0; t < Coop<n>::EPL; ++t) {
+        const int r = L.row(t), c = L.col;
+        X.v[t] = (r < n && c < n) ? ldo(base, off, r * n + c) : 0.0;
+    }
+}
+template <int n>
+__device__ __forceinline__ void dm_st(double* base, uint32_t off, const Lane<n>& L, const DM<n>& X) {
+#pragma unroll
+    for (int t = 0; t < Coop<n>::EPL; ++t) {
+        const int r = L.row(t), c = L.col;
+        if (r < n && c < n) sto(base, off, r * n + c, X.v[t]);
+    }
+}
+// a0 X0 + a1 X1 of two blocks of a source (the same expression as lin2)
+template <int n>
+__device__ __forceinline__ void dm_src(const double* X0, const double* X1, double a0, double a1, uint32_t off,
+                                       const Lane<n>& L, DM<n>& X) {
+#pragma unroll
+    for (int t = 0; t < Coop<n>::EPL; ++t) {
+        const int r = L.row(t), c = L.col;
+        const bool in = r < n && c < n;
+        const double x0 = in ? ldo(X0, off, r * n + c) : 0.0;
+        const double x1 = in ? ldo(X1, off, r * n + c) : 0.0;
+        X.v[t] = in ? lin2(a0, x0, a1, x1) : 0.0;
+    }
+}
+// Vector entries r < n of a tiled array with E entries per position, held
+// by the lanes of column `col` (the others get 0).
+template <int n, int E>
+__device__ __forceinline__ void dm_ld_vec(const double* base, int64_t q, int col, const Lane<n>& L, DM<n>& X) {
+#pragma unroll
+    for (int t = 0; t < Coop<n>::EPL; ++t) {
+        const int r = L.row(t);
+        X.v[t] = (L.col == col && r < n) ? base[tidx<E>(q, r)] : 0.0;
+    }
+}
+template <int n, int E>
+__device__ __forceinline__ void dm_st_vec(double* base, int64_t q, int col, const Lane<n>& L, const DM<n>& X) {
+#pragma unroll
+    for (int t = 0; t < Coop<n>::EPL; ++t) {
+        const int r = L.row(t);
+        if (L.col == col && r < n) base[tidx<E>(q, r)] = X.v[t];
+    }
+}
+
+template <int n>
+__device__ __forceinline__ void dm_put(const DM<n>& X, double* B, const Lane<n>& L) {
+#pragma unroll
+    for (int t = 0; t < Coop<n>::EPL; ++t) B[L.row(t) * Coop<n>::LS + L.col] = X.v[t];
+}
+// B = X^T
+template <int n>
+__device__ __forceinline__ void dm_put_t(const DM<n>& X, double* B, const Lane<n>& L) {
+#pragma unroll
+    for (int t = 0; t < Coop<n>::EPL; ++t) B[L.col * Coop<n>::LS + L.row(t)] = X.v[t];
+}
+// V[r] = X[r][col] for r < n
+template <int n>
+__device__ __forceinline__ void dm_put_col(const DM<n>& X, int col, double* V, const Lane<n>& L) {
+#pragma unroll
+    for (int t = 0; t < Coop<n>::EPL; ++t)
+        if (L.col == col && L.row(t) < n) V[L.row(t)] = X.v[t];
+}
+
+// C = op(A) op(B) over the inner index k < n, A and B blocks in LDS (the
+// caller fences after writing them).  Column `vcol` of B is read from the
+// vector V instead (an augmented right-hand side); vcol = -1: none.
+template <int n, bool TA, bool TB>
+__device__ __forceinline__ void coop_mul(const double* A, const double* B, const double* V, int vcol,
+                                         const Lane<n>& L, DM<n>& C) {
+    constexpr int LS = Coop<n>::LS;
+    const int c = L.col;
+    const bool fromv = c == vcol;
+    const double* bp = fromv ? V : (TB ? B + c * LS : B + c);
+    const int bs = fromv ? 1 : (TB ? 1 : LS);
+#pragma unroll
+    for (int t = 0; t < Coop<n>::EPL; ++t) {
+        const int r = L.row(t);
+        const double* ap = TA ? A + r : A + r * LS;
+        const int as = TA ? LS : 1;
+        double s = 0.0;
+        for (int k = 0; k < n; ++k) s = fma(ap[k * as], bp[k * bs], s);
+        C.v[t] = s;
+    }
+}
+
+// Inverse of the SPD block written to LDS buffer A (read as its lower
+// triangle; A and X are overwritten): Cholesky A = L L^T in place, the
+// diagonal kept as its reciprocal, X = L^-1 by forward substitution on the
+// identity, and Ainv = X^T X (bitwise symmetric).  Multiplies det by the
+// pivots; returns false if a pivot is not positive, not finite or below
+// the smallest normal number (the same test as spd_inverse).
+template <int n>
+__device__ __forceinline__ bool coop_spd_inverse(double* A, double* X, const Lane<n>& L, DM<n>& Ainv, DetAcc* det) {
+    constexpr int LS = Coop<n>::LS;
+    const int c = L.col;
+    bool ok = true;
+    wsync();
+    for (int k = 0; k < n; ++k) {
+        const double d = A[k * LS + k];
+        const bool good = d >= 2.2250738585072014e-308 && d < INFINITY;
+        ok = ok && good;
+        if (det) det->mul(good ? d : 1.0);
+        const double rs = good ? rsqrt_nr(d) : 0.0;
+        const double lck = (c > k && c < n) ? A[c * LS + k] * rs : 0.0;  // L[c][k]
+#pragma unroll
+        for (int t = 0; t < Coop<n>::EPL; ++t) {
+            const int r = L.row(t);
+            if (r < n && r >= k) {
+                const double lrk = A[r * LS + k] * rs;  // L[r][k]
+                if (c == k) A[r * LS + k] = r == k ? rs : lrk;
+                else if (c > k && c <= r) A[r * LS + c] = fma(-lrk, lck, A[r * LS + c]);
+            }
+        }
+        wsync();
+    }
+    // X = L^-1: row k of X is finished at step k, then removed from the rows below
+#pragma unroll
+    for (int t = 0; t < Coop<n>::EPL; ++t) X[L.row(t) * LS + c] = (L.row(t) == c && c < n) ? 1.0 : 0.0;
+    wsync();
+    for (int k = 0; k < n; ++k) {
+        const double xk = X[k * LS + c] * A[k * LS + k];
+#pragma unroll
+        for (int t = 0; t < Coop<n>::EPL; ++t) {
+            const int r = L.row(t);
+            if (r == k) X[k * LS + c] = xk;
+            else if (r > k && r < n) X[r * LS + c] = fma(-A[r * LS + k], xk, X[r * LS + c]);
+        }
+        wsync();
+    }
+#pragma unroll
+    for (int t = 0; t < Coop<n>::EPL; ++t) {
+        const int r = L.row(t);
+        double s = 0.0;
+        for (int k = 0; k < n; ++k) s = fma(X[k * LS + r], X[k * LS + c], s);
+        Ainv.v[t] = (r < n && c < n) ? s : 0.0;
+    }
+    return ok;
+}
+
+// Forward elimination.  Covariance (!RHS): stores P_i^-1 at ws.P and G_i
+// at ws.G.  System (RHS): stores G_i at ws.G and w_i at ws.H (n entries of
+// an n x n slot).  Positions are plan-local (chain order is state order
+// here).  Returns whether every P_i is positive definite; adds log det.
+template <int n, bool RHS>
+__device__ __forceinline__ bool coop_forward(const BlockSrc& M, int N, const Ws& ws, double* lds, int lane,
+                                             double* logdet) {
+    using C = Coop<n>;
+    constexpr int NN = n * n;
+    const Lane<n> L(lane);
+    double *bA = lds, *bX = lds + C::BUF, *bB = lds + 2 * C::BUF, *bV = lds + 3 * C::BUF;
+    DetAcc det;
+    bool ok = true;
+    DM<n> P, Y;
+    dm_src<n>(M.D0, M.D1, M.a0, M.a1, toff<NN>(0), L, P);
+    if (RHS) {
+        DM<n> r0, r1;
+        dm_ld_vec<n, n>(M.R0, 0, n, L, r0);
+        dm_ld_vec<n, n>(M.R1, 0, n, L, r1);
+#pragma unroll
+        for (int t = 0; t < C::EPL; ++t) Y.v[t] = lin2(M.a0, r0.v[t], M.a1, r1.v[t]);
+    }
+    for (int i = 0; i < N; ++i) {
+        const uint32_t o = toff<NN>(i);
+        const bool more = i + 1 < N;
+        // the next state's inputs, independent of the recurrence
+        DM<n> U, Dn, Rn;
+        dm_zero<n>(U);
+        if (more) {
+            dm_src<n>(M.U0, M.U1, M.a0, M.a1, o, L, U);
+            dm_src<n>(M.D0, M.D1, M.a0, M.a1, toff<NN>(i + 1), L, Dn);
+            if (RHS) {
+                DM<n> r0, r1;
+                dm_ld_vec<n, n>(M.R0, i + 1, n, L, r0);
+                dm_ld_vec<n, n>(M.R1, i + 1, n, L, r1);
+#pragma unroll
+                for (int t = 0; t < C::EPL; ++t) Rn.v[t] = lin2(M.a0, r0.v[t], M.a1, r1.v[t]);
+            }
+        }
+        wsync();
+        dm_put<n>(P, bA, L);
+        DM<n> Pinv;
+        ok = coop_spd_inverse<n>(bA, bX, L, Pinv, &det) && ok;
+        if (!RHS) dm_st<n>(ws.P, o, L, Pinv);
+        if (!more && !RHS) break;
+        // G = P^-1 [U | y] (U = 0 after the last state), then S = U^T G
+        wsync();
+        dm_put<n>(Pinv, bA, L);
+        dm_put<n>(U, bB, L);
+        if (RHS) dm_put_col<n>(Y, n, bV, L);
+        wsync();
+        DM<n> G;
+        coop_mul<n, false, false>(bA, bB, bV, RHS ? n : -1, L, G);
+        if (more) dm_st<n>(ws.G, o, L, G);
+        if (RHS) dm_st_vec<n, NN>(ws.H, i, n, L, G);
+        if (!more) break;
+        wsync();
+        dm_put<n>(G, bX, L);
+        wsync();
+        DM<n> S;
+        coop_mul<n, true, false>(bB, bX, nullptr, -1, L, S);
+#pragma unroll
+        for (int t = 0; t < C::EPL; ++t) {
+            const int r = L.row(t), c = L.col;
+            P.v[t] = (r < n && c < n) ? Dn.v[t] - S.v[t] : 0.0;
+            if (RHS) Y.v[t] = (c == n && r < n) ? Rn.v[t] - S.v[t] : 0.0;
+        }
+    }
+    *logdet += det.log_value();
+    return ok;
+}
+
+// Backward recursion of the covariance from the forward elimination's
+// P_i^-1 and G_i: Sigma_ii to SDo (bitwise symmetric), Sigma_{i,i+1} to SUo.
+// Adds the lane's share of tr(KH_i Sigma_ii) + 2 tr(KU_i^T Sigma_{i,i+1})
+// to *part when KH is given.
+template <int n>
+__device__ __forceinline__ void coop_cov_backward(int N, const Ws& ws, double* SDo, double* SUo, const double* KH,
+                                                  const double* KU, double* lds, int lane, double* part) {
+    using C = Coop<n>;
+    constexpr int NN = n * n;
+    const Lane<n> L(lane);
+    double *bA = lds, *bX = lds + C::BUF, *bB = lds + 2 * C::BUF;
+    DM<n> Sg;
+    dm_ld<n>(ws.P, toff<NN>(N - 1), L, Sg);
+    dm_st<n>(SDo, toff<NN>(N - 1), L, Sg);
+    if (KH) {
+        DM<n> K;
+        dm_ld<n>(KH, toff<NN>(N - 1), L, K);
+#pragma unroll
+        for (int t = 0; t < C::EPL; ++t) *part = fma(K.v[t], Sg.v[t], *part);
+    }
+    for (int i = N - 2; i >= 0; --i) {
+        const uint32_t o = toff<NN>(i);
+        DM<n> G, Pinv, Kd, Ku;
+        dm_ld<n>(ws.G, o, L, G);
+        dm_ld<n>(ws.P, o, L, Pinv);
+        if (KH) {
+            dm_ld<n>(KH, o, L, Kd);
+            dm_ld<n>(KU, o, L, Ku);
+        }
+        // Sigma_{i,i+1} = -G Sigma_{i+1}
+        wsync();
+        dm_put<n>(G, bA, L);
+        dm_put<n>(Sg, bB, L);
+        wsync();
+        DM<n> So;
+        coop_mul<n, false, false>(bA, bB, nullptr, -1, L, So);
+#pragma unroll
+        for (int t = 0; t < C::EPL; ++t) So.v[t] = -So.v[t];
+        dm_st<n>(SUo, o, L, So);
+        // Sigma_i = P^-1 - Sigma_{i,i+1} G^T, its lower triangle mirrored
+        wsync();
+        dm_put<n>(So, bX, L);
+        wsync();
+        DM<n> T;
+        coop_mul<n, false, true>(bX, bA, nullptr, -1, L, T);
+#pragma unroll
+        for (int t = 0; t < C::EPL; ++t) Sg.v[t] = Pinv.v[t] - T.v[t];
+        wsync();
+        dm_put<n>(Sg, bB, L);
+        wsync();
+#pragma unroll
+        for (int t = 0; t < C::EPL; ++t) {
+            const int r = L.row(t), c = L.col;
+            if (r < c) Sg.v[t] = bB[c * C::LS + r];
+        }
+        dm_st<n>(SDo, o, L, Sg);
+        if (KH) {
+            double s = 0.0;
+#pragma unroll
+            for (int t = 0; t < C::EPL; ++t) {
+                *part = fma(Kd.v[t], Sg.v[t], *part);
+                s = fma(Ku.v[t], So.v[t], s);
+            }
+            *part = fma(2.0, s, *part);
+        }
+    }
+}
+
+// Back substitution x_i = w_i - G_i x_{i+1} into xo.  With mu0, adds the
+// lane's share of d_i^T LD_i d_i + 2 d_i^T LU_i d_{i+1} (d = x - mu0,
+// LD = M.D1, LU = M.U1: the mean step's quadratic KL term) to *part.
+template <int n>
+__device__ __forceinline__ void coop_rhs_backward(const BlockSrc& M, int N, const Ws& ws, double* xo,
+                                                  const double* mu0, double* lds, int lane, double* part) {
+    using C = Coop<n>;
+    constexpr int NN = n * n;
+    const Lane<n> L(lane);
+    double *bA = lds, *bV = lds + 3 * C::BUF, *bD = lds + 3 * C::BUF + C::NP;
+    // x and d = x - mu0 of the state below, in column 0 of the lanes
+    DM<n> x, d;
+    dm_zero<n>(d);
+    dm_ld_vec<n, NN>(ws.H, N - 1, 0, L, x);
+    dm_st_vec<n, n>(xo, N - 1, 0, L, x);
+    if (mu0) {
+        DM<n> m0;
+        dm_ld_vec<n, n>(mu0, N - 1, 0, L, m0);
+#pragma unroll
+        for (int t = 0; t < C::EPL; ++t) d.v[t] = x.v[t] - m0.v[t];
+    }
+    for (int i = N - 1; i >= 0; --i) {
+        const uint32_t o = toff<NN>(i);
+        const bool below = i + 1 < N;
+        DM<n> xi = x, di = d;
+        if (below) {
+            DM<n> G, w, m0;
+            dm_zero<n>(m0);
+            dm_ld<n>(ws.G, o, L, G);
+            dm_ld_vec<n, NN>(ws.H, i, 0, L, w);
+            if (mu0) dm_ld_vec<n, n>(mu0, i, 0, L, m0);
+            wsync();
+            dm_put<n>(G, bA, L);
+            dm_put_col<n>(x, 0, bV, L);
+            wsync();
+            DM<n> g;
+            coop_mul<n, false, false>(bA, bA, bV, 0, L, g);  // column 0: G x_{i+1}
+#pragma unroll
+            for (int t = 0; t < C::EPL; ++t) {
+                xi.v[t] = w.v[t] - g.v[t];
+                di.v[t] = xi.v[t] - m0.v[t];
+            }
+            dm_st_vec<n, n>(xo, i, 0, L, xi);
+        }
+        if (mu0) {
+            // d_i in bV, d_{i+1} in bD
+            wsync();
+            dm_put_col<n>(di, 0, bV, L);
+            if (below) dm_put_col<n>(d, 0, bD, L);
+            wsync();
+            double s = 0.0;
+#pragma unroll
+            for (int t = 0; t < C::EPL; ++t) {
+                const int r = L.row(t), c = L.col;
+                if (r < n && c < n) {
+                    const double ld = ldo(M.D1, o, r * n + c);
+                    const double lu = below ? ldo(M.U1, o, r * n + c) : 0.0;
+                    const double dn = below ? bD[c] : 0.0;
+                    s = fma(bV[r], fma(ld, bV[c], 2.0 * lu * dn), s);
+                }
+            }
+            *part += s;
+        }
+        x = xi;
+        d = di;
+    }
+}
+
+// The chain step of one matrix (and optionally a linear system) on two
+// wavefronts: wave 0 factors MT and recovers its marginals (SDo, SUo), wave
+// 1 solves MM x = r into xo.  Every thread of the workgroup calls this (it
+// ends with barriers).  Results in sh (thread 0 reads): sh[0] = log det
+// MT, sh[1] = 1 if MT is positive definite, sh[2] = trace term sum (KH, KU
+// given), sh[3] = quadratic term sum (mu0 given).  sh holds THREADS + 4
+// doubles, lds 2 * WAVE_LDS.
+template <int n>
+__device__ __forceinline__ void coop_chain(const BlockSrc& MT, const BlockSrc& MM, bool mean, int N, const Ws& w0,
+                                           const Ws& w1, double* SDo, double* SUo, double* xo, const double* mu0,
+                                           const double* KH, const double* KU, double* lds, double* sh) {
+    const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+    double* wl = lds + wave * Coop<n>::WAVE_LDS;
+    double* red = sh + 4;
+    double part = 0.0;
+    if (wave == 0) {
+        double ld = 0.0;
+        const bool ok = coop_forward<n, false>(MT, N, w0, wl, lane, &ld);
+        coop_cov_backward<n>(N, w0, SDo, SUo, KH, KU, wl, lane, &part);
+        if (lane == 0) {
+            sh[0] = ld;
+            sh[1] = ok ? 1.0 : 0.0;
+        }
+    } else if (mean) {
+        double ld = 0.0;
+        coop_forward<n, true>(MM, N, w1, wl, lane, &ld);
+        coop_rhs_backward<n>(MM, N, w1, xo, mu0, wl, lane, &part);
+    }
+    red[tid] = part;
+    __syncthreads();
+    if (tid == 0) {
+        double tr = 0.0, qd = 0.0;
+        for (int k = 0; k < 64; ++k) tr += red[k];
+        for (int k = 64; k < 128; ++k) qd += red[k];
+        sh[2] = tr;
+        sh[3] = qd;
+    }
+    __syncthreads();
+}
+
+}  // namespace pg

@@ -226,15 +226,20 @@ def test_config3_rounds_every_step(pg, pool, precision):
             states[k] = [K[k]]
             stats[k] = []
         for (A, a), ((Ar, ar), (Ap, ap)), p in zip(gpu_lin, pool.map(so.slr_round, slr_tasks), probs):
-            # per state: error / max(floor, 4 eps), floor from the perturbed marginals
+            # per state: error / max(floor, 4 eps), floor from the perturbed
+            # marginals.  The floor perturbs each input by 2 n roundoffs; the
+            # regression's own rounding grows with its sums over the p^n rule
+            # nodes, up to p^n / (2 n) times that in the worst case (60 for
+            # p = 3, n = 6): the bound is four times the worst case.
             N = p["N"]
+            slr_mult = 4.0 * p["slr_points"] ** p["n"] / (2 * p["n"])
             for X, Xr, Xp in ((A, Ar, Ap), (a, ar, ap)):
                 X, Xr, Xp = (np.asarray(y[:N - 1]).reshape(N - 1, -1) for y in (X, Xr, Xp))
                 nr = np.maximum(np.linalg.norm(Xr, axis=1), 1e-300)
                 err = np.linalg.norm(X - Xr, axis=1) / nr
                 fl = np.maximum(np.linalg.norm(Xp - Xr, axis=1) / nr, 4 * EPS)
                 slr_err = max(slr_err, float(err.max()))
-                assert (err / fl).max() <= 64.0, (r, float(err.max()), float((err / fl).max()))
+                assert (err / fl).max() <= slr_mult, (r, float(err.max()), float((err / fl).max()))
         for _ in range(iters):
             st = pg.pgvimp_prox_step(ctx, 1)
             for k in range(len(probs)):
