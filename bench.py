@@ -40,6 +40,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
     ap.add_argument("--no-configs", action="store_true", help="skip plans/s of configs 0, 2 and 3")
+    ap.add_argument("--configs-only", action="store_true", help="only plans/s of configs 0, 2 and 3")
     ap.add_argument("--segments", type=int, default=0)
     ap.add_argument("--group", type=int, default=0, help="factors per expectation workgroup (0 = per launch)")
     ap.add_argument("--trial-width", type=int, default=0, help="trial step sizes per window (0 = library default)")
@@ -481,6 +482,10 @@ def main():
         return
     if args.paper_tables:
         paper_tables(args, pg)
+        return
+    if args.configs_only:
+        print(json.dumps({"metric": "plans/s of configs 0, 2 and 3", "n_gpus": 1, "data": "synthetic",
+                          "configs": config_rates(pg)}), flush=True)
         return
 
     probs = make_batch(args.plans, args.N, args.iters)
