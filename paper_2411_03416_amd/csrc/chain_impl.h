@@ -1320,6 +1320,78 @@ __global__ void __launch_bounds__(Coop<n>::value ? Coop<n>::THREADS : kTrialThre
 // Sum over the block in a fixed order (sh holds blockDim.x + 1 doubles).
 __device__ __forceinline__ double block_sum(double v, double* sh) { return wg_sum(v, sh); }
 
+// prep_kernel's per-state right-hand side for n >= 6: rb = eta - g (+ H mu_k
+// for the natural-gradient step), mu_k and Lambda_k mu_k to chain position
+// q, vectors in registers and blocks read straight from memory.
+template <int n>
+__device__ __forceinline__ void prep_rhs_direct(const DevState& st, const PlanDev& p, int i, int64_t s, int64_t q,
+                                                bool act) {
+    const int64_t S = st.S;
+    const int N = p.N, d = p.d;
+    double r[n], m[n], acc[n];
+#pragma unroll
+    for (int e = 0; e < n; ++e) {
+        r[e] = st.eta[e * S + s];
+        m[e] = st.mu[e * S + s];
+    }
+    if (act) {
+        for (int a = 0; a < d; ++a) {
+            const double ga = st.gcol[a * S + s];
+            const int ca = p.coll_index[a];
+            double h = 0.0;
+            if (p.update == PGVIMP_UPDATE_NGD) {
+                for (int b = 0; b < d; ++b) {
+                    const int cb = p.coll_index[b];
+                    double mb = 0.0;
+#pragma unroll
+                    for (int e = 0; e < n; ++e) mb = e == cb ? m[e] : mb;
+                    h = fma(st.Hcol[(a * d + b) * S + s], mb, h);
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < n; ++e) r[e] += e == ca ? h - ga : 0.0;
+        }
+    }
+    // Lambda_k mu_k = D_i mu_i + U_i mu_{i+1} + U_{i-1}^T mu_{i-1}
+#pragma unroll
+    for (int e = 0; e < n; ++e) {
+        double t = 0.0;
+#pragma unroll
+        for (int c = 0; c < n; ++c) t = fma(st.LD[(e * n + c) * S + s], m[c], t);
+        acc[e] = t;
+    }
+    if (i < N - 1) {
+        double mn[n];
+#pragma unroll
+        for (int c = 0; c < n; ++c) mn[c] = st.mu[c * S + s + 1];
+#pragma unroll
+        for (int e = 0; e < n; ++e) {
+            double t = 0.0;
+#pragma unroll
+            for (int c = 0; c < n; ++c) t = fma(st.LU[(e * n + c) * S + s], mn[c], t);
+            acc[e] += t;
+        }
+    }
+    if (i > 0) {
+        double mp[n];
+#pragma unroll
+        for (int c = 0; c < n; ++c) mp[c] = st.mu[c * S + s - 1];
+#pragma unroll
+        for (int e = 0; e < n; ++e) {
+            double t = 0.0;
+#pragma unroll
+            for (int c = 0; c < n; ++c) t = fma(st.LU[(c * n + e) * S + s - 1], mp[c], t);
+            acc[e] += t;
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < n; ++e) {
+        st.crb[tidx<n>(q, e)] = r[e];
+        st.cmu[tidx<n>(q, e)] = m[e];
+        st.cLmu[tidx<n>(q, e)] = acc[e];
+    }
+}
+
 // One proximal iteration (Alg. 1), part 1: per-state quantities shared by all
 // trial step sizes, written in chain order -- KH = K^-1 + H (collision
 // Hessians on the diagonal blocks), rb = eta - g (eta - g + H mu_k for the
@@ -1378,6 +1450,12 @@ __global__ void __launch_bounds__(kIterThreads) prep_kernel(DevState st) {
                 st.cLD[qe] = ld[k];
                 st.cLU[qe] = lu[k];
             }
+        }
+        if constexpr (Coop<n>::value) {
+            // n >= 6: the right-hand side and Lambda_k mu_k in registers,
+            // the blocks read straight from memory
+            prep_rhs_direct<n>(st, p, i, s, q, act);
+            continue;
         }
         PG_VEC(r, lt);
         ld_vec<n>(st.eta, S, s, r);
@@ -1444,6 +1522,18 @@ PG_UNROLL
             st.cLmu[tidx<n>(q, e)] = acc[e];
         }
         epri += prior_cost_state<n>(st, p, i, nullptr, nullptr, nullptr, lt);
+    }
+    if constexpr (Coop<n>::value) {
+        // n >= 6: collision costs per thread, prior costs one wavefront per state
+        for (int i = y * kIterThreads + tid; i < N; i += nb * kIterThreads)
+            if (coll_active<n>(p, i)) ecol += st.Ecol[off + i];
+        __shared__ double p_lds[(kIterThreads / 64) * Coop<n>::WAVE_LDS];
+        const int wave = tid / 64, lane = tid % 64;
+        for (int i = y * (kIterThreads / 64) + wave; i < N; i += nb * (kIterThreads / 64)) {
+            double o[3];
+            coop_prior_cost<n>(st, p, i, p_lds + wave * Coop<n>::WAVE_LDS, lane, o);
+            if (lane == 0) epri += o[0] + o[1] + o[2];
+        }
     }
     ecol = block_sum(ecol, sh_d);
     epri = block_sum(epri, sh_d);
@@ -1717,6 +1807,21 @@ __global__ void __launch_bounds__(kIterThreads) select_kernel(DevState st, int /
 template <int n>
 __global__ void __launch_bounds__(kChainThreads) prior_cost_kernel(DevState st, int plan) {
     const PlanDev& p = st.plans[plan];
+    if constexpr (Coop<n>::value) {
+        // n >= 6: one wavefront, state by state
+        __shared__ double lds[Coop<n>::WAVE_LDS];
+        const int lane = threadIdx.x;
+        for (int i = 0; i < p.N; ++i) {
+            double o[3];
+            coop_prior_cost<n>(st, p, i, lds, lane, o);
+            if (lane == 0) {
+                if (i < p.N - 1) st.Epri[p.off + i] = o[0];
+                if (i == p.N - 1) st.Epri[p.off + i] = o[2];
+                if (i == 0) st.Epri[st.S + plan] = o[1];
+            }
+        }
+        return;
+    }
     const TS ts = thread_ws<n>(st, plan, 0);
     for (int i = threadIdx.x; i < p.N; i += kChainThreads) {
         double tr = 0.0, s0 = 0.0, g0 = 0.0;

@@ -422,6 +422,121 @@ __device__ __forceinline__ void coop_rhs_backward(const BlockSrc& M, int N, cons
     }
 }
 
+// Block of state s from a state-major array (entry e of state s at
+// X[e S + s]); zero outside n x n.
+template <int n>
+__device__ __forceinline__ void dm_ld_soa(const double* X, int64_t S, int64_t s, const Lane<n>& L, DM<n>& M) {
+#pragma unroll
+    for (int t = 0; t < Coop<n>::EPL; ++t) {
+        const int r = L.row(t), c = L.col;
+        M.v[t] = (r < n && c < n) ? X[(int64_t)(r * n + c) * S + s] : 0.0;
+    }
+}
+
+// Sum over the 64 lanes of a wavefront in lane order (LDS scratch of 64
+// doubles); every lane gets the sum.
+__device__ __forceinline__ double wave_sum(double v, double* sh, int lane) {
+    wsync();
+    sh[lane] = v;
+    wsync();
+    double s = 0.0;
+    for (int k = 0; k < 64; ++k) s += sh[k];
+    return s;
+}
+
+// Expected prior factor costs touching state i (Sec. 2.2): the transition
+// i -> i+1 (i < N-1), 1/2 [tr(W C) + rbar^T W rbar] with W = Q_i^-1,
+// C = Cov(x_{i+1} - Phi x_i) = S_{i+1} - Sx^T Phi^T - Phi Sx + Phi S_i Phi^T
+// and rbar = mu_{i+1} - Phi mu_i - abar; the start (i = 0) and goal
+// (i = N-1) factors 1/2 [tr(W S_i) + r^T W r].  out = (transition, start,
+// goal), the same on every lane.  lds: one wavefront's area.
+template <int n>
+__device__ __forceinline__ void coop_prior_cost(const DevState& st, const PlanDev& p, int i, double* lds, int lane,
+                                                double out[3]) {
+    using C = Coop<n>;
+    constexpr int LS = C::LS;
+    const Lane<n> L(lane);
+    const int c = L.col;
+    double *bA = lds, *bX = lds + C::BUF, *bB = lds + 2 * C::BUF, *bV = lds + 3 * C::BUF,
+           *bR = lds + 3 * C::BUF + C::NP;
+    const int64_t S = st.S, s = p.off + i;
+    double tr_part = 0.0, st_part = 0.0, gl_part = 0.0;
+    const bool trans = i < p.N - 1;
+    if (trans) {
+        DM<n> Phi, Wq, Si, Sn, Sx;
+        dm_ld_soa<n>(st.Phi, S, s, L, Phi);
+        dm_ld_soa<n>(st.Qinv, S, s, L, Wq);
+        dm_ld_soa<n>(st.SD, S, s, L, Si);
+        dm_ld_soa<n>(st.SD, S, s + 1, L, Sn);
+        dm_ld_soa<n>(st.SU, S, s, L, Sx);
+        // rbar = mu_{i+1} - Phi mu_i - abar, in bR
+        wsync();
+        dm_put<n>(Phi, bA, L);
+        if (lane < n) bV[lane] = st.mu[(int64_t)lane * S + s];
+        wsync();
+        if (lane < n) {
+            double pm = 0.0;
+            for (int k = 0; k < n; ++k) pm = fma(bA[lane * LS + k], bV[k], pm);
+            bR[lane] = st.mu[(int64_t)lane * S + s + 1] - pm - st.abar[(int64_t)lane * S + s];
+        }
+        // PS = Phi Sx and T = Phi S_i
+        dm_put<n>(Sx, bB, L);
+        dm_put<n>(Si, bX, L);
+        wsync();
+        DM<n> PS, T;
+        coop_mul<n, false, false>(bA, bB, nullptr, -1, L, PS);
+        coop_mul<n, false, false>(bA, bX, nullptr, -1, L, T);
+        // C = T Phi^T + Sn - PS - PS^T
+        wsync();
+        dm_put<n>(T, bX, L);
+        dm_put<n>(PS, bB, L);
+        wsync();
+        DM<n> Cm;
+        coop_mul<n, false, true>(bX, bA, nullptr, -1, L, Cm);
+#pragma unroll
+        for (int t = 0; t < C::EPL; ++t) {
+            const int r = L.row(t);
+            Cm.v[t] += Sn.v[t] - PS.v[t] - ((r < n && c < n) ? bB[c * LS + r] : 0.0);
+        }
+        // tr(W C) = sum W[r][c] C[c][r]; rbar^T W rbar
+        wsync();
+        dm_put<n>(Cm, bX, L);
+        wsync();
+#pragma unroll
+        for (int t = 0; t < C::EPL; ++t) {
+            const int r = L.row(t);
+            if (r < n && c < n) {
+                tr_part = fma(Wq.v[t], bX[c * LS + r], tr_part);
+                tr_part = fma(bR[r] * Wq.v[t], bR[c], tr_part);
+            }
+        }
+    }
+    for (int endf = 0; endf < 2; ++endf) {
+        if ((endf == 0 && i != 0) || (endf == 1 && i != p.N - 1)) continue;
+        const double* Wm = endf == 0 ? p.Wstart : p.Wgoal;
+        const double* m0 = endf == 0 ? p.mu_start : p.mu_goal;
+        double v = 0.0;
+#pragma unroll
+        for (int t = 0; t < C::EPL; ++t) {
+            const int a = L.row(t);
+            if (a < n && c < n) {
+                const double w = Wm[a * n + c];
+                const double ra = st.mu[(int64_t)a * S + s] - m0[a];
+                const double rc = st.mu[(int64_t)c * S + s] - m0[c];
+                v = fma(w, st.SD[(int64_t)(c * n + a) * S + s], v);
+                v = fma(ra * w, rc, v);
+            }
+        }
+        if (endf == 0) st_part = v;
+        else gl_part = v;
+    }
+    // (bX, NP (NP + 1) >= 64 doubles, is the reduction's scratch)
+    out[0] = trans ? 0.5 * wave_sum(tr_part, bX, lane) : 0.0;
+    out[1] = i == 0 ? 0.5 * wave_sum(st_part, bX, lane) : 0.0;
+    out[2] = i == p.N - 1 ? 0.5 * wave_sum(gl_part, bX, lane) : 0.0;
+    wsync();
+}
+
 // The chain step of one matrix (and optionally a linear system) on two
 // wavefronts: wave 0 factors MT and recovers its marginals (SDo, SUo), wave
 // 1 solves MM x = r into xo.  Every thread of the workgroup calls this (it
