@@ -609,16 +609,21 @@ def config_rates(pg):
 
         def solve():
             for r in range(probs[0]["n_rounds"]):
-                for k, p in enumerate(probs):
-                    if k in failed:
-                        continue
-                    try:
-                        (pg.ipgvimp_begin if r == 0 else pg.ipgvimp_next_round)(ctx, k, p)
-                    except pg.PgvimpError:
-                        # a linearised prior that is not positive definite ends
-                        # this plan (its budget is spent); the others go on
-                        failed.add(k)
-                        pg.pgvimp_set_budget(ctx, k, 0)
+                if r == 0:
+                    for k, p in enumerate(probs):
+                        try:
+                            pg.ipgvimp_begin(ctx, k, p)
+                        except pg.PgvimpError:
+                            # a linearised prior that is not positive definite
+                            # ends this plan (its budget is spent); the others go on
+                            failed.add(k)
+                            pg.pgvimp_set_budget(ctx, k, 0)
+                else:
+                    # later rounds: every live plan in shared launches
+                    live = [k for k in range(len(probs)) if k not in failed]
+                    for k, code in zip(live, pg.ipgvimp_next_round_many(ctx, live, probs[0])):
+                        if code != pg.OK:
+                            failed.add(k)
                 pg.pgvimp_prox_step(ctx, probs[0]["n_iters"])
         dt = _timed(solve, 1)
         pg.pgvimp_destroy(ctx)

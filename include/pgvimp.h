@@ -343,6 +343,23 @@ int pgvimp_slr_round(pgvimp_ctx *ctx, int32_t plan, int32_t model, const double 
                      int32_t gh_points, const double *nominal_mean, const double *nominal_cov,
                      int32_t n_iters, double *A_out, double *a_out);
 
+/*
+ * A later round of Alg. 2 for n_plans plans at once (plans [n_plans],
+ * distinct live plan indices): for each, the drift's statistical
+ * linearisation about its current marginals (Sec. 6.2), then the LTV
+ * priors of all of them are rebuilt, their precisions restart from the new
+ * K^-1 (means kept) and their marginals are recomputed in shared launches;
+ * each plan's budget becomes n_iters.  The other live plans are untouched.
+ * status [n_plans] (host, may be NULL) receives PGVIMP_OK or PGVIMP_ENOTPD
+ * per plan: a plan whose linearised prior is not positive definite gets a
+ * budget of 0 instead of failing the call.  The same results as
+ * pgvimp_slr_round on each plan in turn.  Errors: EINVAL (bad arguments:
+ * a plan listed twice or not live, n_iters < 0, a model the context's n
+ * does not fit; nothing is changed), EDEVICE.
+ */
+int pgvimp_slr_round_many(pgvimp_ctx *ctx, int32_t n_plans, const int32_t *plans, int32_t model,
+                          const double *model_params, int32_t gh_points, int32_t n_iters, int32_t *status);
+
 /* Read the plan's mean [N][n] and precision blocks D [N][n][n], U [N-1][n][n]. */
 int pgvimp_get_state(pgvimp_ctx *ctx, int32_t plan, double *mu, double *prec_diag, double *prec_off);
 

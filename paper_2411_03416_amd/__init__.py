@@ -326,6 +326,24 @@ def pgvimp_slr_round(ctx, plan, gravity=9.81, gh_points=3, n_iters=0, nominal_me
     return A, a
 
 
+def pgvimp_slr_round_many(ctx, plans, gravity=9.81, gh_points=3, n_iters=0):
+    """A later round of Alg. 2 for several plans at once (see
+    pgvimp_slr_round_many in include/pgvimp.h); returns the per-plan status
+    codes (OK or ENOTPD)."""
+    pl = np.ascontiguousarray(plans, dtype=np.int32)
+    st = np.zeros(pl.size, dtype=np.int32)
+    prm = np.array([gravity], dtype=np.float64)
+    _check(_abi.load().pgvimp_slr_round_many(ctx.handle, int(pl.size), pl.ctypes.data, _abi.MODEL_QUAD2D,
+                                             _dptr(prm), gh_points, int(n_iters), st.ctypes.data), ctx.handle)
+    return st
+
+
+def ipgvimp_next_round_many(ctx, plans, prob):
+    """Later rounds of Alg. 2 for several plans sharing prob's model."""
+    return pgvimp_slr_round_many(ctx, plans, gravity=prob["quad"]["gravity"], gh_points=prob.get("slr_points", 3),
+                                 n_iters=int(prob["n_iters"]))
+
+
 def ipgvimp_begin(ctx, plan, prob):
     """First round of Alg. 2 for a nonlinear plan: pgvimp_slr_round about the
     nominal trajectory (prob['nominal_mean'], prob['nominal_cov'])."""

@@ -90,6 +90,8 @@ SIGNATURES = [
     ("pgvimp_solve", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Stats)]),
     ("pgvimp_slr_linearize", C.c_int, [C.c_void_p, C.c_int32, C.c_int32, _dp, C.c_int32, C.c_int32,
                                        C.c_void_p, C.c_void_p]),
+    ("pgvimp_slr_round_many", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, _dp, C.c_int32, C.c_int32,
+                                        C.c_void_p]),
     ("pgvimp_slr_round", C.c_int, [C.c_void_p, C.c_int32, C.c_int32, _dp, C.c_int32, C.c_void_p, C.c_void_p,
                                    C.c_int32, C.c_void_p, C.c_void_p]),
     ("pgvimp_get_state", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),

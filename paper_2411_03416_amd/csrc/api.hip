@@ -1380,6 +1380,57 @@ int pgvimp_slr_round(pgvimp_ctx* c, int32_t plan, int32_t model, const double* m
     return PGVIMP_OK;
 }
 
+int pgvimp_slr_round_many(pgvimp_ctx* c, int32_t n_plans, const int32_t* plans, int32_t model,
+                          const double* model_params, int32_t gh_points, int32_t n_iters, int32_t* status) {
+    if (!c || n_plans < 1 || !plans) return PGVIMP_EINVAL;
+    if (n_iters < 0) FAIL(c, PGVIMP_EINVAL, "negative iteration budget");
+    if (model != PGVIMP_MODEL_QUAD2D || c->n != 6) FAIL(c, PGVIMP_EINVAL, "model %d needs a 6-dim state", model);
+    if (gh_points < 1 || gh_points > kMaxGH) FAIL(c, PGVIMP_EINVAL, "gh_points out of range");
+    const double g = model_params ? model_params[0] : 9.81;
+    if (!std::isfinite(g)) FAIL(c, PGVIMP_EINVAL, "non-finite model parameter");
+    std::vector<char> listed(c->plans.size(), 0);
+    int lo = (int)c->plans.size(), hi = 0, maxN = 1;
+    for (int k = 0; k < n_plans; ++k) {
+        const int pl = plans[k];
+        if (!plan_ok(c, pl) || listed[pl]) FAIL(c, PGVIMP_EINVAL, "plan %d is not live or listed twice", pl);
+        listed[pl] = 1;
+        lo = std::min(lo, pl);
+        hi = std::max(hi, pl + 1);
+        maxN = std::max(maxN, c->plans[pl].N);
+    }
+    HCK(c, hipSetDevice(c->cfg.device));
+    for (int k = 0; k < n_plans; ++k)
+        HCK(c, launch_slr_model(c->st, plans[k], c->plans[plans[k]].N, g, gh_points, nullptr, nullptr, 1, c->stream));
+    // the rebuild runs over [lo, hi) with the unlisted live plans hidden
+    int rc = download_plans(c);
+    if (rc) return rc;
+    std::vector<int> hidden;
+    for (int i = lo; i < hi; ++i)
+        if (c->pdev[i].active && !listed[i]) {
+            c->pdev[i].active = 0;
+            hidden.push_back(i);
+        }
+    for (int i : hidden)
+        if ((rc = upload_plan(c, i))) return rc;
+    HCK(c, launch_prior_build(c->st, lo, hi, maxN, c->stream));
+    HCK(c, launch_prior_assemble(c->st, lo, hi, maxN, c->stream));
+    HCK(c, launch_chain(c->st, CHAIN_REINIT, lo, hi, c->stream));
+    if ((rc = download_plans(c))) return rc;
+    for (int i : hidden) {
+        c->pdev[i].active = 1;
+        if ((rc = upload_plan(c, i))) return rc;
+    }
+    for (int k = 0; k < n_plans; ++k) {
+        PlanDev& pd = c->pdev[plans[k]];
+        const bool bad = pd.status == PGVIMP_ENOTPD;
+        if (status) status[k] = bad ? PGVIMP_ENOTPD : PGVIMP_OK;
+        pd.iters_left = bad ? 0 : n_iters;
+        if ((rc = upload_plan(c, plans[k]))) return rc;
+    }
+    HCK(c, hipStreamSynchronize(c->stream));
+    return PGVIMP_OK;
+}
+
 int pgvimp_launch_shape(pgvimp_ctx* c, int32_t N, int32_t* segments, int32_t* group) {
     if (!c || N < 1) return PGVIMP_EINVAL;
     if (segments) {

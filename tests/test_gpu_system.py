@@ -141,3 +141,40 @@ def test_plans_with_one_map_share_it_and_keep_their_results():
     e_new = pg.pgvimp_factor_expectations(ctx, pid)
     e_ref = pg.pgvimp_factor_expectations(pg.pgvimp_create([a], precision=pg.FP64, use_graph=False), 0)
     assert all(np.array_equal(u, v) for u, v in zip(e_new, e_ref))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_round_for_many_plans_equals_rounds_one_by_one(pg, precision):
+    """pgvimp_slr_round_many (a later Alg. 2 round of several plans in shared
+    launches) gives the bits of pgvimp_slr_round on each plan in turn, and
+    leaves the unlisted plans untouched."""
+    probs = [workloads.config3_problem(seed=s) for s in (1, 5, 8, 13, 21)]
+    for p in probs:
+        p["n_iters"] = 3
+    ctxs = [pg.pgvimp_create(probs, precision=precision, use_graph=False) for _ in range(2)]
+    for ctx in ctxs:
+        for k, p in enumerate(probs):
+            pg.ipgvimp_begin(ctx, k, p)
+        pg.pgvimp_prox_step(ctx, 3)
+    listed = [1, 2, 4]
+    before = {k: pg.pgvimp_get_state(ctxs[0], k) for k in range(len(probs))}
+    codes = pg.ipgvimp_next_round_many(ctxs[0], listed, probs[0])
+    for k in listed:
+        pg.ipgvimp_next_round(ctxs[1], k, probs[k])
+    assert all(c == pg.OK for c in codes)
+    for k in range(len(probs)):
+        a, b = pg.pgvimp_get_state(ctxs[0], k), pg.pgvimp_get_state(ctxs[1], k)
+        assert all(np.array_equal(u, v) for u, v in zip(a, b)), k
+        if k not in listed:
+            assert all(np.array_equal(u, v) for u, v in zip(a, before[k])), k
+        else:
+            assert not np.array_equal(a[1], before[k][1]), k  # the precision restarted from the new K^-1
+    for ctx in ctxs:
+        pg.pgvimp_prox_step(ctx, 3)
+    for k in range(len(probs)):
+        a, b = pg.pgvimp_get_state(ctxs[0], k), pg.pgvimp_get_state(ctxs[1], k)
+        assert all(np.array_equal(u, v) for u, v in zip(a, b)), k
+    with pytest.raises(pg.PgvimpError):
+        pg.ipgvimp_next_round_many(ctxs[0], [1, 1], probs[0])
+    for ctx in ctxs:
+        pg.pgvimp_destroy(ctx)
