@@ -21,6 +21,8 @@ import subprocess
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -49,8 +51,13 @@ def parse():
                     help="first window = previous trial count + this (0 = full first window)")
     ap.add_argument("--serve", action="store_true",
                     help="run the serving mix (Poisson arrivals of configs 0-3) instead of the batch solve")
-    ap.add_argument("--qps", type=float, default=20.0)
-    ap.add_argument("--requests", type=int, default=60)
+    ap.add_argument("--qps-list", type=float, nargs="*", default=None, help="offered loads of --serve's sweep")
+    ap.add_argument("--requests", type=int, default=2000, help="measured requests of --serve")
+    ap.add_argument("--warmup-requests", type=int, default=200)
+    ap.add_argument("--hbm-budget-gib", type=float, default=16.0, help="--serve's admission budget")
+    ap.add_argument("--serve-max-n", type=int, default=1000)
+    ap.add_argument("--serial-sample", type=int, default=100, help="requests of the serial FP64 baseline")
+    ap.add_argument("--serve-timeout", type=float, default=300.0)
     ap.add_argument("--sweep-plans", type=int, nargs="*", default=None, help="plan counts of --expect-sweep")
     ap.add_argument("--sweep-prec", choices=("mixed", "fp64", "both"), default="both",
                     help="precisions of --expect-sweep")
@@ -68,24 +75,65 @@ def parse():
 
 
 def serve(args, pg):
-    """Serving mix: Poisson arrivals, each request a config 0-3 shape with
-    N ~ U{50..max}; continuous batching vs one plan at a time (FP64)."""
+    """Serving mix (config 4): Poisson arrivals of requests drawn from
+    configs 0-3 with N ~ U{50..max_N} (state dimensions 4, 6, 14), up to 256
+    plans live, admission by an HBM budget; warm-up requests first, the
+    measured ones after.  The offered load is swept upward until the served
+    plans/s fall below 90 % of it (saturation); then mixed and FP64 are
+    served at 70 % of the saturated rate, and the serial FP64 baseline (one
+    plan at a time, back to back) is timed on a sample of the same stream."""
     import workloads
     from paper_2411_03416_amd.serve import ServingEngine
-    reqs = workloads.serving_mix(seed=0, count=args.requests, qps=args.qps, n_range=(50, args.N))
-    for _, p in reqs:
+    warm, count = args.warmup_requests, args.requests
+    budget = int(args.hbm_budget_gib * (1 << 30))
+    base = workloads.serving_mix(seed=0, count=warm + count, qps=1.0, n_range=(50, args.serve_max_n), map_pool=16)
+    for _, p in base:
         p["n_iters"] = min(p["n_iters"], args.iters)
-    out = {"metric": METRIC + " (serving mix)", "unit": "plans/s", "n_gpus": 1, "higher_is_better": True,
-           "data": "synthetic", "scaling": "weak", "vs_baseline": None,
-           "config": {"workload": f"serving mix: {args.requests} Poisson requests at {args.qps} QPS, configs 0-3, "
-                                  f"N ~ U{{50..{args.N}}}", "qps": args.qps}}
-    for name, prec, serial in (("mixed", pg.MIXED, False), ("fp64", pg.FP64, False), ("serial_fp64", pg.FP64, True)):
-        eng = ServingEngine(precision=prec, hbm_budget=24 << 30, max_plans=64, chunk=2, max_N=args.N, serial=serial)
-        m, _ = eng.run(reqs, timeout_s=240)
+
+    def at(qps):
+        return [(t / qps, p) for t, p in base]
+
+    def run(qps, prec):
+        eng = ServingEngine(precision=prec, hbm_budget=budget, max_concurrent=256, chunk=2,
+                            max_N=args.serve_max_n)
+        m, _ = eng.run(at(qps), timeout_s=args.serve_timeout, measured_from=warm)
         eng.close()
-        out[name] = m
-    out["value"] = out["mixed"]["plans_per_s"]
-    out["dtype"] = "fp32 quadrature + fp64"
+        m["qps"] = qps
+        print(f"serve: {qps:.1f} QPS {'mixed' if prec == pg.MIXED else 'fp64'}: {m['plans_per_s']:.1f} plans/s, "
+              f"p50 {m['p50_ms']} ms, p99 {m['p99_ms']} ms, completed {m['completed']}/{m['requests']}", flush=True)
+        return m
+
+    sweep, sat = [], None
+    for q in (args.qps_list or [25.0, 50.0, 100.0, 200.0, 400.0, 800.0]):
+        m = run(q, pg.MIXED)
+        sweep.append(m)
+        if m["completed"] < m["requests"] or m["plans_per_s"] < 0.9 * q:
+            sat = m["plans_per_s"]
+            break
+    if sat is None:
+        sat = max(m["plans_per_s"] for m in sweep)
+    q70 = 0.7 * sat
+    mixed = run(q70, pg.MIXED)
+    fp64 = run(q70, pg.FP64)
+    # serial FP64: one plan at a time, back to back, on the first requests
+    sample = [(0.0, p) for _, p in base[warm:warm + args.serial_sample]]
+    eng = ServingEngine(precision=pg.FP64, hbm_budget=budget, serial=True, max_N=args.serve_max_n)
+    t0 = time.perf_counter()
+    _, recs = eng.run(sample, timeout_s=args.serve_timeout)
+    wall = time.perf_counter() - t0
+    eng.close()
+    svc = np.array([r["done"] - r.get("admitted", r["done"]) for r in recs if "done" in r and "error" not in r])
+    serial = {"plans_per_s": len(svc) / wall if wall > 0 else 0.0, "sample": len(sample),
+              "service_p50_ms": float(np.percentile(svc, 50) * 1e3) if svc.size else None,
+              "service_p99_ms": float(np.percentile(svc, 99) * 1e3) if svc.size else None}
+    print(f"serve: serial FP64 {serial['plans_per_s']:.2f} plans/s on {len(sample)} requests", flush=True)
+    out = {"metric": METRIC + " (serving mix)", "value": mixed["plans_per_s"], "unit": "plans/s", "n_gpus": 1,
+           "higher_is_better": True, "data": "synthetic", "scaling": "weak", "vs_baseline": None,
+           "dtype": "fp32 quadrature + fp64",
+           "config": {"workload": f"serving mix: Poisson arrivals, configs 0-3, N ~ U{{50..{args.serve_max_n}}}, "
+                                  f"{warm} warm-up + {count} measured requests, 256 concurrent, HBM budget "
+                                  f"{args.hbm_budget_gib} GiB", "qps": q70},
+           "saturation_plans_per_s": sat, "sweep": sweep, "mixed": mixed, "fp64": fp64, "serial_fp64": serial}
     print(json.dumps(out), flush=True)
 
 

@@ -508,9 +508,12 @@ static int64_t carve(pgvimp_ctx* c, const pgvimp_engine_cfg* cfg, DevState& st, 
     take(&st.Hcol, S * dmax * dmax * 8);
     take(&st.Epri, (S + P) * 8);
     take(&st.ws, 2 * W * Sc * ws_stride * 8);
-    // reduced-chain node scratch: in LDS for n <= 4, in the arena otherwise
-    take(&st.seg, n > 4 ? P * W * 2 * kMaxSeg * (int64_t)seg_stride * 8 : 0);
-    const int64_t tws_stride = n > 4 ? (int64_t)kTwsBlocks * n * n + (int64_t)kTwsVecs * n : 0;
+    // reduced-chain node scratch and per-thread block workspace of the
+    // segmented sweeps: in LDS or registers for n <= 4; n >= 6 takes the
+    // wavefront-per-matrix path, which needs neither
+    const bool seg_ws = n > 4 && n < 6;
+    take(&st.seg, seg_ws ? P * W * 2 * kMaxSeg * (int64_t)seg_stride * 8 : 0);
+    const int64_t tws_stride = seg_ws ? (int64_t)kTwsBlocks * n * n + (int64_t)kTwsVecs * n : 0;
     take(&st.tws, P * W * kTrialThreads * tws_stride * 8);
     take(&st.flags, 16 * 4);
     take(&st.gh_x64, (kMaxGH + 1) * kMaxGH * 8);

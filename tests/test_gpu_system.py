@@ -52,11 +52,11 @@ def test_ipgvimp_rounds_match_oracle(pg):
         assert err_D < max(p["n_iters"] * (r + 1) * tol, 100 * self_D), r
 
 
-def test_serving_matches_plans_solved_alone(pg):
-    from paper_2411_03416_amd.serve import ServingEngine
+def _serving_requests(spacing=0.002):
     reqs = []
     t = 0.0
-    for k, (kind, N) in enumerate([(0, 60), (1, 120), (0, 45), (2, 30), (3, 50), (1, 80), (0, 70), (3, 40)]):
+    for k, (kind, N) in enumerate([(0, 60), (1, 120), (2, 150), (0, 45), (2, 200), (3, 50), (1, 80), (0, 70),
+                                   (3, 40), (2, 180), (1, 150)]):
         seed = 100 + k
         if kind == 0:
             prob = workloads.point2d_problem(seed, N=N)
@@ -69,16 +69,38 @@ def test_serving_matches_plans_solved_alone(pg):
             prob["n_rounds"], prob["n_iters"] = 2, 5
         prob["n_iters"] = prob.get("n_iters", 20) if kind == 3 else 6
         reqs.append((t, prob))
-        t += 0.002
-    eng = ServingEngine(precision=pg.FP64, hbm_budget=3 << 30, max_plans=8, chunk=2, max_N=200)
+        t += spacing
+    return reqs
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("budget_mib", [4096, 64])
+def test_serving_matches_plans_solved_alone(pg, precision, budget_mib):
+    """Continuous batching with admission by an HBM budget: every request is
+    served, and each result equals the same plan served alone, bitwise in
+    both precisions (no kernel's result depends on the batch).  A 64 MiB
+    budget holds only a few plans at once: requests queue for admission
+    and are admitted as plans leave."""
+    from paper_2411_03416_amd.serve import ServingEngine, plan_bytes
+    reqs = _serving_requests()
+    budget = budget_mib << 20
+    eng = ServingEngine(precision=precision, hbm_budget=budget, max_concurrent=8, chunk=2, max_N=200,
+                        trial_width=8, trial_slots=8)
     metrics, recs = eng.run(reqs, timeout_s=120)
     eng.close()
-    print("serving metrics", metrics)
-    assert metrics["completed"] == len(reqs)
-    # each result equals the same plan served alone (bitwise in FP64)
+    print("serving metrics", metrics, flush=True)
+    assert metrics["completed"] == len(reqs) and metrics["errors"] == 0
+    sizes = [plan_bytes(p, 8, 8) for _, p in reqs]
+    if budget_mib == 64:
+        # the budget held: never more live bytes than the budget, unless a
+        # single plan larger than it ran alone
+        assert metrics["peak_bytes"] <= max(budget, max(sizes))
+        assert sum(sizes) > budget  # the stream does not fit at once ...
+        assert metrics["admission_wait_p99_ms"] > 0.0  # ... so requests waited
+        assert metrics["peak_live"] < len(reqs)
     for rec in recs:
-        alone = ServingEngine(precision=pg.FP64, hbm_budget=1 << 30, max_plans=1, chunk=2,
-                              dims=(rec["prob"]["n"],), max_N=200)
+        alone = ServingEngine(precision=precision, hbm_budget=1 << 30, max_concurrent=1, chunk=2,
+                              dims=(rec["prob"]["n"],), max_N=200, trial_width=8, trial_slots=8)
         _, r2 = alone.run([(0.0, rec["prob"])], timeout_s=60)
         alone.close()
         assert np.array_equal(rec["result"]["mu"], r2[0]["result"]["mu"]), rec["id"]

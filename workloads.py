@@ -476,20 +476,30 @@ def arm_affine_problem(slope=(0.25, -0.125, 0.5), offset=2.0, N=6, kappa_eps=10.
     return p
 
 
-def serving_mix(seed=0, count=100, qps=50.0, n_range=(50, 1000)):
-    """Request stream: Poisson arrivals, each drawing a config 0..3 shape.
+def serving_mix(seed=0, count=100, qps=50.0, n_range=(50, 1000), map_pool=None):
+    """Request stream: Poisson arrivals, each drawing a config 0..3 shape
+    and N ~ U{n_range}.
 
+    With map_pool = P, the point-robot and arm requests draw their map (and
+    with it their start and goal) from P seeded maps per kind, so that long
+    streams are generated quickly and share device copies of their maps;
+    the quadrotor's nominal trajectory depends on N, so it is drawn anew.
     Returns a list of (arrival_time_s, problem) sorted by arrival.
     """
     rng = _rng(seed)
     t = 0.0
     out = []
+    cache = {}
     for k in range(count):
         t += float(rng.exponential(1.0 / qps))
         kind = int(rng.integers(0, 4))
         N = int(rng.integers(n_range[0], n_range[1] + 1))
         s = int(rng.integers(0, 1 << 30))
-        if kind == 0:
+        if map_pool and kind < 3:
+            s = s % map_pool
+        if kind < 3 and map_pool and (kind, s) in cache:
+            prob = dict(cache[(kind, s)], N=N)
+        elif kind == 0:
             prob = point2d_problem(s, N=N)
         elif kind == 1:
             prob = point2d_problem(s, N=N, grid=500, cell=0.1, n_shapes=40, boxes=True,
@@ -498,6 +508,8 @@ def serving_mix(seed=0, count=100, qps=50.0, n_range=(50, 1000)):
             prob = arm_problem(s, N=N)
         else:
             prob = quadrotor_problem(s, N=N)
+        if kind < 3 and map_pool:
+            cache.setdefault((kind, s), prob)
         prob["mix_kind"] = kind
         out.append((t, prob))
     return out
