@@ -89,6 +89,7 @@ def serve(args, pg):
     base = workloads.serving_mix(seed=0, count=warm + count, qps=1.0, n_range=(50, args.serve_max_n), map_pool=16)
     for _, p in base:
         p["n_iters"] = min(p["n_iters"], args.iters)
+    print(f"serve: {len(base)} requests generated", flush=True)
 
     def at(qps):
         return [(t / qps, p) for t, p in base]
@@ -107,7 +108,10 @@ def serve(args, pg):
     for q in (args.qps_list or [25.0, 50.0, 100.0, 200.0, 400.0, 800.0]):
         m = run(q, pg.MIXED)
         sweep.append(m)
-        if m["completed"] < m["requests"] or m["plans_per_s"] < 0.9 * q:
+        # saturated: requests left unanswered at the time limit, or the
+        # served rate below 90 % of the offered one (a request the library
+        # rejects is answered, with its error)
+        if m["completed"] + m["errors"] < m["requests"] or m["plans_per_s"] < 0.9 * q:
             sat = m["plans_per_s"]
             break
     if sat is None:
