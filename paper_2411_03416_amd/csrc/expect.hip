@@ -68,12 +68,25 @@ __device__ __forceinline__ float clamp_axis(float u, float top) { return fminf(f
 // clamped to [0, g-1]; the cell is min(floor(u), g-2) and t = u - cell.
 // fmax/fmin return the non-NaN operand, so a NaN coordinate lands on the
 // grid's first node instead of producing an undefined index.
-template <typename R>
-__device__ __forceinline__ void axis_cell(R x, R o_ic, R inv_cell, R top, R last, uint32_t& i, R& t) {
-    const R u = clamp_axis(x * inv_cell - o_ic, top);
-    const R k = fmin(floor(u), last);
+__device__ __forceinline__ void axis_cell(double x, double o_ic, double inv_cell, double top, double last,
+                                          uint32_t& i, double& t) {
+    const double u = clamp_axis(x * inv_cell - o_ic, top);
+    const double k = fmin(floor(u), last);
     i = (uint32_t)(int)k;
     t = u - k;
+}
+// FP32: the same cell and offset with two median-of-three clamps, the cell
+// floor(u) clamped to [0, g-2] and t = u - cell clamped to [0, 1], which
+// equals clamping u to [0, g-1] first, bit for bit, for every non-NaN u.
+// A NaN coordinate gives cell 0 (the float-to-integer conversion of NaN is
+// 0), so the index stays in the grid.
+__device__ __forceinline__ void axis_cell(float x, float o_ic, float inv_cell, float top, float last, uint32_t& i,
+                                          float& t) {
+    (void)top;
+    const float u = x * inv_cell - o_ic;
+    const float k = __builtin_amdgcn_fmed3f(floorf(u), 0.0f, last);
+    i = (uint32_t)(int)k;
+    t = __builtin_amdgcn_fmed3f(u - k, 0.0f, 1.0f);
 }
 
 // Grid values are read by raw buffer loads through a resource that spans
@@ -112,8 +125,8 @@ template <typename R>
 __device__ __forceinline__ R sdf2(const Grid& grid, uint32_t gx, const Axis<R>& ax, const Axis<R>& ay, R ic, R x, R y) {
     uint32_t ix, iy;
     R tx, ty;
-    axis_cell<R>(x, ax.o_ic, ic, ax.top, ax.last, ix, tx);
-    axis_cell<R>(y, ay.o_ic, ic, ay.top, ay.last, iy, ty);
+    axis_cell(x, ax.o_ic, ic, ax.top, ax.last, ix, tx);
+    axis_cell(y, ay.o_ic, ic, ay.top, ay.last, iy, ty);
     const uint32_t o0 = iy * gx + ix;
     const f2 r0 = row2(grid, o0), r1 = row2(grid, o0 + gx);
     const R v00 = (R)r0.x, v01 = (R)r0.y, v10 = (R)r1.x, v11 = (R)r1.y;
@@ -127,9 +140,9 @@ __device__ __forceinline__ R sdf3(const Grid& grid, uint32_t gx, uint32_t gxy, c
                                   const Axis<R>& az, R ic, R x, R y, R z) {
     uint32_t ix, iy, iz;
     R tx, ty, tz;
-    axis_cell<R>(x, ax.o_ic, ic, ax.top, ax.last, ix, tx);
-    axis_cell<R>(y, ay.o_ic, ic, ay.top, ay.last, iy, ty);
-    axis_cell<R>(z, az.o_ic, ic, az.top, az.last, iz, tz);
+    axis_cell(x, ax.o_ic, ic, ax.top, ax.last, ix, tx);
+    axis_cell(y, ay.o_ic, ic, ay.top, ay.last, iy, ty);
+    axis_cell(z, az.o_ic, ic, az.top, az.last, iz, tz);
     const uint32_t o = iz * gxy + iy * gx + ix;
     const f2 r00 = row2(grid, o), r01 = row2(grid, o + gx), r10 = row2(grid, o + gxy),
              r11 = row2(grid, o + gxy + gx);
