@@ -254,7 +254,7 @@ def timed_solve(pg, probs, precision, steps, warmup, iters, segments=0, group=0,
             "segments": seg, "group": group_used, "evals": evals, "prof_trials": prof_trials}
 
 
-KERNEL_SOURCE = {"trial_kernel": "chain_impl.h", "expect_kernel": "expect.hip"}
+KERNEL_SOURCE = {"trial_kernel": ["chain_impl.h", "coop.h", "blockmath.h"], "expect_kernel": ["expect.hip"]}
 
 
 def counter_traffic(kernel):
@@ -271,8 +271,10 @@ def counter_traffic(kernel):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
-    src = os.path.join(ROOT, "paper_2411_03416_amd", "csrc", KERNEL_SOURCE[kernel])
-    if kv.get("source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCE[kernel]:
+        h.update(open(os.path.join(ROOT, "paper_2411_03416_amd", "csrc", name), "rb").read())
+    if kv.get("source_sha256") != h.hexdigest():
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])

@@ -162,13 +162,21 @@ __device__ __forceinline__ void coop_mul(const double* A, const double* B, const
 
 // Inverse of the SPD block written to LDS buffer A (read as its lower
 // triangle; A and X are overwritten): Cholesky A = L L^T in place, the
-// diagonal kept as its reciprocal, X = L^-1 by forward substitution on the
-// identity, and Ainv = X^T X (bitwise symmetric).  Multiplies det by the
-// pivots; returns false if a pivot is not positive, not finite or below
-// the smallest normal number (the same test as spd_inverse).
+// diagonal kept as its reciprocal, X = L^-1, and Ainv = X^T X (bitwise
+// symmetric).  Multiplies det by the pivots; returns false if a pivot is
+// not positive, not finite or below the smallest normal number (the same
+// test as spd_inverse).
+//
+// For 8 x 8 blocks (one entry per lane) round k also finishes row k of X,
+// X[k][c] = (delta_kc - sum_{j<k} L[k][j] X[j][c]) / L[k][k] (row k of L
+// and the rows of X above it are final by then): one LDS round per pivot.
+// For 16 x 16 blocks that dot product of up to 13 terms would lengthen every
+// round, so X follows in a second pass of right-looking substitution on the
+// identity, each round one short update (measured faster there).
 template <int n>
 __device__ __forceinline__ bool coop_spd_inverse(double* A, double* X, const Lane<n>& L, DM<n>& Ainv, DetAcc* det) {
     constexpr int LS = Coop<n>::LS;
+    constexpr bool MERGED = Coop<n>::NP == 8;
     const int c = L.col;
     bool ok = true;
     wsync();
@@ -182,6 +190,12 @@ __device__ __forceinline__ bool coop_spd_inverse(double* A, double* X, const Lan
 #pragma unroll
         for (int t = 0; t < Coop<n>::EPL; ++t) {
             const int r = L.row(t);
+            if (MERGED && r == k) {
+                // row k of X from the final rows above it
+                double dot = 0.0;
+                for (int j = 0; j < k; ++j) dot = fma(A[k * LS + j], X[j * LS + c], dot);
+                X[k * LS + c] = ((c == k ? 1.0 : 0.0) - dot) * rs;
+            }
             if (r < n && r >= k) {
                 const double lrk = A[r * LS + k] * rs;  // L[r][k]
                 if (c == k) A[r * LS + k] = r == k ? rs : lrk;
@@ -190,19 +204,21 @@ __device__ __forceinline__ bool coop_spd_inverse(double* A, double* X, const Lan
         }
         wsync();
     }
-    // X = L^-1: row k of X is finished at step k, then removed from the rows below
+    if (!MERGED) {
+        // X = L^-1: row k of X is finished at step k, then removed from the rows below
 #pragma unroll
-    for (int t = 0; t < Coop<n>::EPL; ++t) X[L.row(t) * LS + c] = (L.row(t) == c && c < n) ? 1.0 : 0.0;
-    wsync();
-    for (int k = 0; k < n; ++k) {
-        const double xk = X[k * LS + c] * A[k * LS + k];
-#pragma unroll
-        for (int t = 0; t < Coop<n>::EPL; ++t) {
-            const int r = L.row(t);
-            if (r == k) X[k * LS + c] = xk;
-            else if (r > k && r < n) X[r * LS + c] = fma(-A[r * LS + k], xk, X[r * LS + c]);
-        }
+        for (int t = 0; t < Coop<n>::EPL; ++t) X[L.row(t) * LS + c] = (L.row(t) == c && c < n) ? 1.0 : 0.0;
         wsync();
+        for (int k = 0; k < n; ++k) {
+            const double xk = X[k * LS + c] * A[k * LS + k];
+#pragma unroll
+            for (int t = 0; t < Coop<n>::EPL; ++t) {
+                const int r = L.row(t);
+                if (r == k) X[k * LS + c] = xk;
+                else if (r > k && r < n) X[r * LS + c] = fma(-A[r * LS + k], xk, X[r * LS + c]);
+            }
+            wsync();
+        }
     }
 #pragma unroll
     for (int t = 0; t < Coop<n>::EPL; ++t) {
