@@ -185,11 +185,16 @@ __global__ void __launch_bounds__(kPriorThreads) prior_build_kernel(DevState st,
     for (int e = threadIdx.x; e < n * n; e += blockDim.x) st.Qinv[e * S + s] = M[e];
 }
 
-// K^-1 blocks and eta = K^-1 mu_bar from the factor sums (Alg. 1).
-__global__ void prior_assemble_kernel(DevState st, int plan_lo) {
+// K^-1 blocks and eta = K^-1 mu_bar from the factor sums (Alg. 1), one
+// thread per state.  The block Phi^T Qinv Phi is formed column by column:
+// t = Qinv Phi[:, c] (n values in registers), then entry (r, c) = Phi[:, r]^T t,
+// n^3 operations per block instead of recomputing t for every entry (the
+// sums are the same, in the same order).
+constexpr int kAssembleThreads = 64;
+template <int n>
+__global__ void __launch_bounds__(kAssembleThreads) prior_assemble_kernel(DevState st, int plan_lo) {
     const PlanDev& p = st.plans[plan_lo + blockIdx.y];
     if (!p.active) return;
-    const int n = st.n;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int N = p.N;
     if (i >= N) return;
@@ -205,17 +210,25 @@ __global__ void prior_assemble_kernel(DevState st, int plan_lo) {
         }
         for (int e = 0; e < n; ++e) st.abar[e * S + s] = st.abar[e * S + sI];
     }
-    for (int r = 0; r < n; ++r) {
-        for (int c = 0; c < n; ++c) {
+#pragma unroll 1
+    for (int c = 0; c < n; ++c) {
+        double t[n];
+        if (i < N - 1) {
+#pragma unroll
+            for (int k = 0; k < n; ++k) {
+                double v = 0.0;
+                for (int l = 0; l < n; ++l) v += st.Qinv[(k * n + l) * S + sI] * st.Phi[(l * n + c) * S + sI];
+                t[k] = v;
+            }
+        }
+#pragma unroll 1
+        for (int r = 0; r < n; ++r) {
             double v = 0.0;
             if (i == 0) v += p.Wstart[r * n + c];
             if (i == N - 1) v += p.Wgoal[r * n + c];
             if (i < N - 1) {  // Phi^T Qinv Phi
-                for (int k = 0; k < n; ++k) {
-                    double t = 0.0;
-                    for (int l = 0; l < n; ++l) t += st.Qinv[(k * n + l) * S + sI] * st.Phi[(l * n + c) * S + sI];
-                    v += st.Phi[(k * n + r) * S + sI] * t;
-                }
+#pragma unroll
+                for (int k = 0; k < n; ++k) v += st.Phi[(k * n + r) * S + sI] * t[k];
                 double u = 0.0;  // -Phi^T Qinv
                 for (int k = 0; k < n; ++k) u -= st.Phi[(k * n + r) * S + sI] * st.Qinv[(k * n + c) * S + sI];
                 st.KU[(r * n + c) * S + s] = u;
@@ -223,6 +236,8 @@ __global__ void prior_assemble_kernel(DevState st, int plan_lo) {
             if (i > 0) v += st.Qinv[(r * n + c) * S + sP];
             st.KD[(r * n + c) * S + s] = v;
         }
+    }
+    for (int r = 0; r < n; ++r) {
         double e = 0.0;
         if (i == 0)
             for (int k = 0; k < n; ++k) e += p.Wstart[r * n + k] * p.mu_start[k];
@@ -250,9 +265,16 @@ hipError_t launch_prior_build(const DevState& st, int plan_lo, int plan_hi, int 
 
 hipError_t launch_prior_assemble(const DevState& st, int plan_lo, int plan_hi, int maxN, hipStream_t s) {
     if (plan_hi <= plan_lo || maxN <= 0) return hipSuccess;
-    const int th = 64;
-    hipLaunchKernelGGL(prior_assemble_kernel, dim3((maxN + th - 1) / th, plan_hi - plan_lo), dim3(th), 0, s, st,
-                       plan_lo);
+    const int th = kAssembleThreads;
+    const dim3 grid((maxN + th - 1) / th, plan_hi - plan_lo);
+    switch (st.n) {
+        case 2: hipLaunchKernelGGL(prior_assemble_kernel<2>, grid, dim3(th), 0, s, st, plan_lo); break;
+        case 4: hipLaunchKernelGGL(prior_assemble_kernel<4>, grid, dim3(th), 0, s, st, plan_lo); break;
+        case 6: hipLaunchKernelGGL(prior_assemble_kernel<6>, grid, dim3(th), 0, s, st, plan_lo); break;
+        case 8: hipLaunchKernelGGL(prior_assemble_kernel<8>, grid, dim3(th), 0, s, st, plan_lo); break;
+        case 14: hipLaunchKernelGGL(prior_assemble_kernel<14>, grid, dim3(th), 0, s, st, plan_lo); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
