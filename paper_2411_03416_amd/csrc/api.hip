@@ -688,6 +688,15 @@ static int64_t model_count_of(int n, int m, int N, int ns, int64_t rule_vals) {
            rule_vals + (rule_vals + 1) / 2;
 }
 
+// Device bytes of a plan's map: the FP32 grid and, for 2-D maps, the four
+// corners of every cell (one 16-byte load per bilinear lookup).
+static int64_t map_bytes(const pgvimp_problem* p) {
+    if (p->coll_kind == PGVIMP_COLL_NONE) return 0;
+    int64_t b = align_up((int64_t)p->gx * p->gy * p->gz * 4);
+    if (p->coll_kind == PGVIMP_COLL_POINT2D) b += align_up((int64_t)(p->gx - 1) * (p->gy - 1) * 16);
+    return b;
+}
+
 int64_t pgvimp_plan_heap_bytes(const pgvimp_problem* p) {
     if (!p || p->n < 1 || p->m < 1 || p->N < 1) return PGVIMP_EINVAL;
     const bool coll = p->coll_kind != PGVIMP_COLL_NONE;
@@ -701,8 +710,7 @@ int64_t pgvimp_plan_heap_bytes(const pgvimp_problem* p) {
         if (rule.empty()) return PGVIMP_EINVAL;
         rule_vals = (int64_t)rule.size();
     }
-    const int64_t sdf = coll ? align_up((int64_t)p->gx * p->gy * p->gz * 4) : 0;
-    return sdf + align_up(model_count_of(p->n, p->m, p->N, ns, rule_vals) * 8);
+    return map_bytes(p) + align_up(model_count_of(p->n, p->m, p->N, ns, rule_vals) * 8);
 }
 
 int pgvimp_add_plan(pgvimp_ctx* c, const pgvimp_problem* p, int32_t* plan_out) {
@@ -723,7 +731,7 @@ int pgvimp_add_plan(pgvimp_ctx* c, const pgvimp_problem* p, int32_t* plan_out) {
     const int ns = coll ? p->n_spheres : 1;
     // heap blocks: the SDF grid (shared with live plans of the same map),
     // and the plan's FP64 model data
-    const int64_t sdf_bytes = coll ? align_up((int64_t)p->gx * p->gy * p->gz * 4) : 0;
+    const int64_t sdf_bytes = map_bytes(p);
     const int64_t fk_count = 3 + PGVIMP_ARM_DOF + ns + PGVIMP_ARM_DOF + ns;
     // sparse quadrature rule of the collision expectations (rows xi, W), FP64
     // then FP32 (packed two per double slot)
@@ -815,9 +823,13 @@ int pgvimp_add_plan(pgvimp_ctx* c, const pgvimp_problem* p, int32_t* plan_out) {
             for (int k = 0; k < PGVIMP_ARM_DOF; ++k) f[3 + PGVIMP_ARM_DOF + ns + k] = p->fk_axes[k];
             for (int s = 0; s < ns; ++s) f[3 + 2 * PGVIMP_ARM_DOF + ns + s] = p->fk_sphere_link[s];
         }
-        if (map_new)
+        if (map_new) {
             HCK(c, hipMemcpyAsync(base, p->sdf, (size_t)p->gx * p->gy * p->gz * 4, hipMemcpyHostToDevice,
                                   c->stream));
+            if (p->coll_kind == PGVIMP_COLL_POINT2D)
+                HCK(c, launch_build_quads((const float*)base, p->gx, p->gy,
+                                          (float*)(base + align_up((int64_t)p->gx * p->gy * 4)), c->stream));
+        }
     }
     HCK(c, hipMemcpyAsync(model, h.data(), model_count * 8, hipMemcpyHostToDevice, c->stream));
     pd.active = 1;
@@ -854,6 +866,8 @@ int pgvimp_add_plan(pgvimp_ctx* c, const pgvimp_problem* p, int32_t* plan_out) {
     pd.obs_weight = p->obs_weight;
     for (int k = 0; k < 3; ++k) pd.origin[k] = p->origin[k];
     pd.sdf = coll ? (const float*)base : nullptr;
+    pd.sdfq = coll && p->coll_kind == PGVIMP_COLL_POINT2D ? (const float*)(base + align_up((int64_t)p->gx * p->gy * 4))
+                                                          : nullptr;
     pd.Wstart = Wstart;
     pd.Wgoal = Wgoal;
     pd.mu_start = mus;

@@ -135,6 +135,46 @@ __device__ __forceinline__ R sdf2(const Grid& grid, uint32_t gx, const Axis<R>& 
     return a + ty * (b - a);
 }
 
+// 2-D lookup from the cell-corner table: the four values of cell (ix, iy)
+// in one 16-byte load (two 8-byte row loads otherwise), the same bilinear
+// arithmetic as sdf2.
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+template <typename R>
+__device__ __forceinline__ R sdf2q(const Grid& quad, uint32_t cx, const Axis<R>& ax, const Axis<R>& ay, R ic, R x,
+                                   R y) {
+    uint32_t ix, iy;
+    R tx, ty;
+    axis_cell(x, ax.o_ic, ic, ax.top, ax.last, ix, tx);
+    axis_cell(y, ay.o_ic, ic, ay.top, ay.last, iy, ty);
+    const u4v q = __builtin_amdgcn_raw_buffer_load_b128(quad.rsrc, (iy * cx + ix) * 16u, 0, 0);
+    const R v00 = (R)__uint_as_float(q.x), v01 = (R)__uint_as_float(q.y), v10 = (R)__uint_as_float(q.z),
+            v11 = (R)__uint_as_float(q.w);
+    const R a = v00 + tx * (v01 - v00);
+    const R b = v10 + tx * (v11 - v10);
+    return a + ty * (b - a);
+}
+
+__global__ void build_quads_kernel(const float* __restrict__ sdf, int gx, int gy, float* __restrict__ quad) {
+    const int64_t cells = (int64_t)(gx - 1) * (gy - 1);
+    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t iy = c / (gx - 1), ix = c - iy * (gx - 1);
+        const float* r0 = sdf + iy * gx + ix;
+        quad[4 * c + 0] = r0[0];
+        quad[4 * c + 1] = r0[1];
+        quad[4 * c + 2] = r0[gx];
+        quad[4 * c + 3] = r0[gx + 1];
+    }
+}
+
+hipError_t launch_build_quads(const float* sdf, int gx, int gy, float* quad, hipStream_t s) {
+    const int64_t cells = (int64_t)(gx - 1) * (gy - 1);
+    if (cells <= 0) return hipSuccess;
+    const int threads = 256;
+    const int blocks = (int)std::min<int64_t>((cells + threads - 1) / threads, 65536);
+    hipLaunchKernelGGL(build_quads_kernel, dim3(blocks), dim3(threads), 0, s, sdf, gx, gy, quad);
+    return hipGetLastError();
+}
+
 template <typename R>
 __device__ __forceinline__ R sdf3(const Grid& grid, uint32_t gx, uint32_t gxy, const Axis<R>& ax, const Axis<R>& ay,
                                   const Axis<R>& az, R ic, R x, R y, R z) {
@@ -171,20 +211,20 @@ struct Cost;
 
 template <typename R, int D>
 struct Cost<R, D, PGVIMP_COLL_POINT2D> {
-    Grid grid;
-    uint32_t gx;
+    Grid quad;
+    uint32_t cx;
     Axis<R> ax, ay;
     R ic, er, w;
     __device__ void init(const PlanDev& p) {
-        grid.init(p.sdf, (int64_t)p.gx * p.gy * p.gz);
-        gx = (uint32_t)p.gx;
+        quad.init(p.sdfq, (int64_t)(p.gx - 1) * (p.gy - 1) * 4);
+        cx = (uint32_t)(p.gx - 1);
         ax.init(p.origin[0], p.inv_cell, p.gx);
         ay.init(p.origin[1], p.inv_cell, p.gy);
         ic = (R)p.inv_cell;
         er = (R)(p.hinge_eps + p.radius[0]);
         w = (R)p.obs_weight;
     }
-    __device__ R operator()(const R* x) const { return w * hinge2<R>(er, sdf2<R>(grid, gx, ax, ay, ic, x[0], x[1])); }
+    __device__ R operator()(const R* x) const { return w * hinge2<R>(er, sdf2q<R>(quad, cx, ax, ay, ic, x[0], x[1])); }
 };
 
 template <typename R, int D>

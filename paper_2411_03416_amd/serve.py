@@ -107,10 +107,11 @@ class _Lane:
                 pid = pgvimp_add_plan(self.ctx, req["prob"], mu_init=req.get("mu_init"))
             except PgvimpError as e:
                 self.adm.give(req["bytes"])
-                if e.code in (EBUSY, ENOMEM):
+                if e.code in (EBUSY, ENOMEM) and self.live:
                     break  # this context is full: wait for one of its plans to leave
                 # a problem the library rejects (for instance a prior that is
-                # not positive definite) is answered with its error
+                # not positive definite, or one larger than an empty context)
+                # is answered with its error
                 self.queue.popleft()
                 req["error"] = str(e)
                 req["done"] = time.perf_counter()
@@ -196,7 +197,10 @@ class ServingEngine:
         self.lanes = {}
         for n in dims:
             # arena: states and heap for the budget's worth of this lane's plans
-            m = max_map_bytes if max_map_bytes is not None else (128 ** 3 * 4 if n == 14 else 500 * 500 * 4)
+            # the largest map a plan brings: a 128^3 grid for the arm, else a
+            # 500 x 500 grid with its table of cell corners (16 bytes a cell)
+            m = max_map_bytes if max_map_bytes is not None else (
+                128 ** 3 * 4 if n == 14 else 500 * 500 * 4 + 499 * 499 * 16)
             per_state = (pgvimp_arena_bytes(n, 1, 1001, 0, trial_width, trial_slots)
                          - pgvimp_arena_bytes(n, 1, 1, 0, trial_width, trial_slots)) / 1000.0
             plans = 1 if serial else max_concurrent
