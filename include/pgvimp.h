@@ -109,10 +109,12 @@ typedef struct pgvimp_ctx pgvimp_ctx;
  * r_s - sdf(c_s(x)))^2, where c_s are the collision points (the point
  * itself, or forward-kinematics spheres) and r_s their radii.  The SDF is
  * an FP32 grid sampled at nodes origin + (ix, iy, iz) * cell, stored
- * sdf[iy][ix] (2-D, gz = 1) or sdf[iz][iy][ix] (3-D), at most 2 GiB; lookups
- * are bilinear or trilinear with clamping to the grid.  Plans of one context
- * whose grids are identical (same dimensions and values) share one device
- * copy.  gh_points p in [1, 10] points per
+ * sdf[iy][ix] (2-D, gz = 1) or sdf[iz][iy][ix] (3-D); lookups are bilinear
+ * or trilinear with clamping to the grid.  The library keeps the grid and a
+ * table of its cell corners (16 bytes a cell) on the device, which must stay
+ * under 2 GiB ((gx-1)(gy-1)gz * 16 bytes; larger grids are rejected with
+ * PGVIMP_EINVAL).  Plans of one context whose grids are identical (same
+ * dimensions and values) share one device copy.  gh_points p in [1, 10] points per
  * configuration dimension (tensor rule, p^d nodes).  coll_states: 0 = every
  * support state carries a collision factor, 1 = only interior states.
  *

@@ -391,8 +391,10 @@ int validate_problem(pgvimp_ctx* c, const pgvimp_problem* p) {
     const bool is3 = p->coll_kind != PGVIMP_COLL_POINT2D;
     if (!p->sdf || p->gx < 2 || p->gy < 2 || (is3 ? p->gz < 2 : p->gz != 1))
         FAIL(c, PGVIMP_EINVAL, "bad SDF grid");
-    // lookups address the grid with 32-bit byte offsets
-    if ((int64_t)p->gx * p->gy * p->gz * 4 > INT32_MAX) FAIL(c, PGVIMP_EINVAL, "SDF grid over 2 GiB");
+    // lookups address the table of cell corners (16 bytes a cell, about four
+    // times the grid) with 32-bit byte offsets
+    if ((int64_t)(p->gx - 1) * (p->gy - 1) * p->gz * 16 > INT32_MAX)
+        FAIL(c, PGVIMP_EINVAL, "SDF grid too large: its table of cell corners is over 2 GiB");
     if (!(p->cell > 0.0) || !std::isfinite(p->hinge_eps) || !(p->obs_weight >= 0.0))
         FAIL(c, PGVIMP_EINVAL, "bad grid cell or hinge parameters");
     if (p->n_spheres < 1 || p->n_spheres > PGVIMP_MAX_SPHERES || !p->sphere_radius)
@@ -688,13 +690,12 @@ static int64_t model_count_of(int n, int m, int N, int ns, int64_t rule_vals) {
            rule_vals + (rule_vals + 1) / 2;
 }
 
-// Device bytes of a plan's map: the FP32 grid and, for 2-D maps, the four
-// corners of every cell (one 16-byte load per bilinear lookup).
+// Device bytes of a plan's map: the FP32 grid and the four corners of every
+// cell of each z-slice (one 16-byte load per bilinear lookup, two per
+// trilinear one).
 static int64_t map_bytes(const pgvimp_problem* p) {
     if (p->coll_kind == PGVIMP_COLL_NONE) return 0;
-    int64_t b = align_up((int64_t)p->gx * p->gy * p->gz * 4);
-    if (p->coll_kind == PGVIMP_COLL_POINT2D) b += align_up((int64_t)(p->gx - 1) * (p->gy - 1) * 16);
-    return b;
+    return align_up((int64_t)p->gx * p->gy * p->gz * 4) + align_up((int64_t)(p->gx - 1) * (p->gy - 1) * p->gz * 16);
 }
 
 int64_t pgvimp_plan_heap_bytes(const pgvimp_problem* p) {
@@ -826,9 +827,8 @@ int pgvimp_add_plan(pgvimp_ctx* c, const pgvimp_problem* p, int32_t* plan_out) {
         if (map_new) {
             HCK(c, hipMemcpyAsync(base, p->sdf, (size_t)p->gx * p->gy * p->gz * 4, hipMemcpyHostToDevice,
                                   c->stream));
-            if (p->coll_kind == PGVIMP_COLL_POINT2D)
-                HCK(c, launch_build_quads((const float*)base, p->gx, p->gy,
-                                          (float*)(base + align_up((int64_t)p->gx * p->gy * 4)), c->stream));
+            HCK(c, launch_build_quads((const float*)base, p->gx, p->gy, p->gz,
+                                      (float*)(base + align_up((int64_t)p->gx * p->gy * p->gz * 4)), c->stream));
         }
     }
     HCK(c, hipMemcpyAsync(model, h.data(), model_count * 8, hipMemcpyHostToDevice, c->stream));
@@ -866,8 +866,7 @@ int pgvimp_add_plan(pgvimp_ctx* c, const pgvimp_problem* p, int32_t* plan_out) {
     pd.obs_weight = p->obs_weight;
     for (int k = 0; k < 3; ++k) pd.origin[k] = p->origin[k];
     pd.sdf = coll ? (const float*)base : nullptr;
-    pd.sdfq = coll && p->coll_kind == PGVIMP_COLL_POINT2D ? (const float*)(base + align_up((int64_t)p->gx * p->gy * 4))
-                                                          : nullptr;
+    pd.sdfq = coll ? (const float*)(base + align_up((int64_t)p->gx * p->gy * p->gz * 4)) : nullptr;
     pd.Wstart = Wstart;
     pd.Wgoal = Wgoal;
     pd.mu_start = mus;

@@ -58,7 +58,7 @@ struct PlanDev {
     double beta, kl, E_coll, E_prior, entropy;
     double iter_temperature, entropy_cost, total_cost;  // cost breakdown of q_k (last iteration)
     const float* sdf;
-    const float* sdfq;  // 2-D maps: the four corners of every cell (see build_quads), else null
+    const float* sdfq;  // the four corners of every cell of each z-slice (see launch_build_quads)
     // model block (FP64) laid out by the host, see Layout in api.cpp
     double* Wstart;  // Sig_start^-1 [n*n]   (written by the prior kernel)
     double* Wgoal;   // Sig_goal^-1 [n*n]
@@ -205,9 +205,9 @@ hipError_t launch_scatter(const DevState& st, int what, int plan, int N, const d
 hipError_t launch_slr_model(const DevState& st, int plan, int N, double gravity, int p, double* A_out,
                             double* a_out, int write_model, hipStream_t s);
 bool chain_supported(int n);
-// 2-D maps: writes the corners (v00, v01, v10, v11) of each of the
-// (gx - 1)(gy - 1) cells of sdf [gy][gx] to quad, 16 bytes per cell.
-hipError_t launch_build_quads(const float* sdf, int gx, int gy, float* quad, hipStream_t s);
+// Writes the corners (v00, v01, v10, v11) of each of the (gx - 1)(gy - 1)
+// cells of every z-slice of sdf [gz][gy][gx] to quad, 16 bytes per cell.
+hipError_t launch_build_quads(const float* sdf, int gx, int gy, int gz, float* quad, hipStream_t s);
 bool expect_supported(int coll_kind, int d, int p, int group, int quadrature);
 // factors per expectation workgroup for a launch over `plans` plan slots of
 // at most maxN states (group 0 = chosen from the batch)

@@ -89,9 +89,9 @@ __device__ __forceinline__ void axis_cell(float x, float o_ic, float inv_cell, f
     t = __builtin_amdgcn_fmed3f(u - k, 0.0f, 1.0f);
 }
 
-// Grid values are read by raw buffer loads through a resource that spans
-// exactly the grid: 32-bit byte offsets (one VGPR per address), and an
-// offset past the grid reads 0 instead of faulting.
+// Grid tables are read by raw buffer loads through a resource that spans
+// exactly the table: 32-bit byte offsets (one VGPR per address), and an
+// offset past the table reads 0 instead of faulting.
 struct Grid {
     __amdgpu_buffer_rsrc_t rsrc;
     __device__ void init(const float* g, int64_t count) {
@@ -99,17 +99,6 @@ struct Grid {
         rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)g, (short)0, (int)(count * 4), 0x00020000);
     }
 };
-// Two horizontally adjacent grid values (the cell's corners along x) in one
-// 8-byte load: the cell index is at most g - 2, so both lie in the row.
-typedef unsigned int u2v __attribute__((ext_vector_type(2)));
-struct f2 {
-    float x, y;
-};
-__device__ __forceinline__ f2 row2(const Grid& grid, uint32_t off) {
-    const u2v v = __builtin_amdgcn_raw_buffer_load_b64(grid.rsrc, off * 4u, 0, 0);
-    return f2{__uint_as_float(v.x), __uint_as_float(v.y)};
-}
-
 // Per-axis constants of a grid lookup in type R.
 template <typename R>
 struct Axis {
@@ -121,23 +110,8 @@ struct Axis {
     }
 };
 
-template <typename R>
-__device__ __forceinline__ R sdf2(const Grid& grid, uint32_t gx, const Axis<R>& ax, const Axis<R>& ay, R ic, R x, R y) {
-    uint32_t ix, iy;
-    R tx, ty;
-    axis_cell(x, ax.o_ic, ic, ax.top, ax.last, ix, tx);
-    axis_cell(y, ay.o_ic, ic, ay.top, ay.last, iy, ty);
-    const uint32_t o0 = iy * gx + ix;
-    const f2 r0 = row2(grid, o0), r1 = row2(grid, o0 + gx);
-    const R v00 = (R)r0.x, v01 = (R)r0.y, v10 = (R)r1.x, v11 = (R)r1.y;
-    const R a = v00 + tx * (v01 - v00);
-    const R b = v10 + tx * (v11 - v10);
-    return a + ty * (b - a);
-}
-
 // 2-D lookup from the cell-corner table: the four values of cell (ix, iy)
-// in one 16-byte load (two 8-byte row loads otherwise), the same bilinear
-// arithmetic as sdf2.
+// in one 16-byte load, bilinear in x then y.
 typedef unsigned int u4v __attribute__((ext_vector_type(4)));
 template <typename R>
 __device__ __forceinline__ R sdf2q(const Grid& quad, uint32_t cx, const Axis<R>& ax, const Axis<R>& ay, R ic, R x,
@@ -154,11 +128,14 @@ __device__ __forceinline__ R sdf2q(const Grid& quad, uint32_t cx, const Axis<R>&
     return a + ty * (b - a);
 }
 
-__global__ void build_quads_kernel(const float* __restrict__ sdf, int gx, int gy, float* __restrict__ quad) {
-    const int64_t cells = (int64_t)(gx - 1) * (gy - 1);
+// Cell-corner table of each z-slice of a grid [gz][gy][gx]: entry
+// (iz, iy, ix) holds v[iz][iy][ix], v[iz][iy][ix+1], v[iz][iy+1][ix],
+// v[iz][iy+1][ix+1] (a 2-D grid is one slice).
+__global__ void build_quads_kernel(const float* __restrict__ sdf, int gx, int gy, int gz, float* __restrict__ quad) {
+    const int64_t per = (int64_t)(gx - 1) * (gy - 1), cells = per * gz;
     for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t iy = c / (gx - 1), ix = c - iy * (gx - 1);
-        const float* r0 = sdf + iy * gx + ix;
+        const int64_t iz = c / per, r = c - iz * per, iy = r / (gx - 1), ix = r - iy * (gx - 1);
+        const float* r0 = sdf + (iz * gy + iy) * gx + ix;
         quad[4 * c + 0] = r0[0];
         quad[4 * c + 1] = r0[1];
         quad[4 * c + 2] = r0[gx];
@@ -166,30 +143,32 @@ __global__ void build_quads_kernel(const float* __restrict__ sdf, int gx, int gy
     }
 }
 
-hipError_t launch_build_quads(const float* sdf, int gx, int gy, float* quad, hipStream_t s) {
-    const int64_t cells = (int64_t)(gx - 1) * (gy - 1);
+hipError_t launch_build_quads(const float* sdf, int gx, int gy, int gz, float* quad, hipStream_t s) {
+    const int64_t cells = (int64_t)(gx - 1) * (gy - 1) * gz;
     if (cells <= 0) return hipSuccess;
     const int threads = 256;
     const int blocks = (int)std::min<int64_t>((cells + threads - 1) / threads, 65536);
-    hipLaunchKernelGGL(build_quads_kernel, dim3(blocks), dim3(threads), 0, s, sdf, gx, gy, quad);
+    hipLaunchKernelGGL(build_quads_kernel, dim3(blocks), dim3(threads), 0, s, sdf, gx, gy, gz, quad);
     return hipGetLastError();
 }
 
+// 3-D lookup from the per-slice corner tables: two 16-byte loads (slices
+// iz and iz + 1), trilinear in x, then y, then z.
 template <typename R>
-__device__ __forceinline__ R sdf3(const Grid& grid, uint32_t gx, uint32_t gxy, const Axis<R>& ax, const Axis<R>& ay,
-                                  const Axis<R>& az, R ic, R x, R y, R z) {
+__device__ __forceinline__ R sdf3q(const Grid& quad, uint32_t cx, uint32_t cxy, const Axis<R>& ax, const Axis<R>& ay,
+                                   const Axis<R>& az, R ic, R x, R y, R z) {
     uint32_t ix, iy, iz;
     R tx, ty, tz;
     axis_cell(x, ax.o_ic, ic, ax.top, ax.last, ix, tx);
     axis_cell(y, ay.o_ic, ic, ay.top, ay.last, iy, ty);
     axis_cell(z, az.o_ic, ic, az.top, az.last, iz, tz);
-    const uint32_t o = iz * gxy + iy * gx + ix;
-    const f2 r00 = row2(grid, o), r01 = row2(grid, o + gx), r10 = row2(grid, o + gxy),
-             r11 = row2(grid, o + gxy + gx);
-    const R a0 = (R)r00.x + tx * ((R)r00.y - (R)r00.x);
-    const R a1 = (R)r01.x + tx * ((R)r01.y - (R)r01.x);
-    const R a2 = (R)r10.x + tx * ((R)r10.y - (R)r10.x);
-    const R a3 = (R)r11.x + tx * ((R)r11.y - (R)r11.x);
+    const uint32_t o = iz * cxy + iy * cx + ix;
+    const u4v q0 = __builtin_amdgcn_raw_buffer_load_b128(quad.rsrc, o * 16u, 0, 0);
+    const u4v q1 = __builtin_amdgcn_raw_buffer_load_b128(quad.rsrc, (o + cxy) * 16u, 0, 0);
+    const R a0 = (R)__uint_as_float(q0.x) + tx * ((R)__uint_as_float(q0.y) - (R)__uint_as_float(q0.x));
+    const R a1 = (R)__uint_as_float(q0.z) + tx * ((R)__uint_as_float(q0.w) - (R)__uint_as_float(q0.z));
+    const R a2 = (R)__uint_as_float(q1.x) + tx * ((R)__uint_as_float(q1.y) - (R)__uint_as_float(q1.x));
+    const R a3 = (R)__uint_as_float(q1.z) + tx * ((R)__uint_as_float(q1.w) - (R)__uint_as_float(q1.z));
     const R b0 = a0 + ty * (a1 - a0);
     const R b1 = a2 + ty * (a3 - a2);
     return b0 + tz * (b1 - b0);
@@ -229,14 +208,14 @@ struct Cost<R, D, PGVIMP_COLL_POINT2D> {
 
 template <typename R, int D>
 struct Cost<R, D, PGVIMP_COLL_POINT3D> {
-    Grid grid;
-    uint32_t gx, gxy;
+    Grid quad;
+    uint32_t cx, cxy;
     Axis<R> ax, ay, az;
     R ic, er, w;
     __device__ void init(const PlanDev& p) {
-        grid.init(p.sdf, (int64_t)p.gx * p.gy * p.gz);
-        gx = (uint32_t)p.gx;
-        gxy = (uint32_t)p.gx * (uint32_t)p.gy;
+        quad.init(p.sdfq, (int64_t)(p.gx - 1) * (p.gy - 1) * p.gz * 4);
+        cx = (uint32_t)(p.gx - 1);
+        cxy = (uint32_t)(p.gx - 1) * (uint32_t)(p.gy - 1);
         ax.init(p.origin[0], p.inv_cell, p.gx);
         ay.init(p.origin[1], p.inv_cell, p.gy);
         az.init(p.origin[2], p.inv_cell, p.gz);
@@ -245,24 +224,24 @@ struct Cost<R, D, PGVIMP_COLL_POINT3D> {
         w = (R)p.obs_weight;
     }
     __device__ R operator()(const R* x) const {
-        return w * hinge2<R>(er, sdf3<R>(grid, gx, gxy, ax, ay, az, ic, x[0], x[1], x[2]));
+        return w * hinge2<R>(er, sdf3q<R>(quad, cx, cxy, ax, ay, az, ic, x[0], x[1], x[2]));
     }
 };
 
 // Serial chain of PGVIMP_ARM_DOF revolute joints; spheres sorted by link.
 template <typename R, int D>
 struct Cost<R, D, PGVIMP_COLL_ARM3D> {
-    Grid grid;
+    Grid quad;
     const double* fk;
     const double* rad;
-    uint32_t gx, gxy;
+    uint32_t cx, cxy;
     int ns;
     Axis<R> ax, ay, az;
     R ic, eps, w;
     __device__ void init(const PlanDev& p) {
-        grid.init(p.sdf, (int64_t)p.gx * p.gy * p.gz);
-        gx = (uint32_t)p.gx;
-        gxy = (uint32_t)p.gx * (uint32_t)p.gy;
+        quad.init(p.sdfq, (int64_t)(p.gx - 1) * (p.gy - 1) * p.gz * 4);
+        cx = (uint32_t)(p.gx - 1);
+        cxy = (uint32_t)(p.gx - 1) * (uint32_t)(p.gy - 1);
         ax.init(p.origin[0], p.inv_cell, p.gx);
         ay.init(p.origin[1], p.inv_cell, p.gy);
         az.init(p.origin[2], p.inv_cell, p.gz);
@@ -314,7 +293,7 @@ struct Cost<R, D, PGVIMP_COLL_ARM3D> {
             for (; s < ns && (int)link[s] == k; ++s) {
                 const R f = (R)frac[s] * L;
                 const R px = o[0] + f * c2[0], py = o[1] + f * c2[1], pz = o[2] + f * c2[2];
-                const R dist = sdf3<R>(grid, gx, gxy, ax, ay, az, ic, px, py, pz);
+                const R dist = sdf3q<R>(quad, cx, cxy, ax, ay, az, ic, px, py, pz);
                 acc += hinge2<R>(eps + (R)rad[s], dist);
             }
 #pragma unroll

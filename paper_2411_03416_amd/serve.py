@@ -197,10 +197,10 @@ class ServingEngine:
         self.lanes = {}
         for n in dims:
             # arena: states and heap for the budget's worth of this lane's plans
-            # the largest map a plan brings: a 128^3 grid for the arm, else a
-            # 500 x 500 grid with its table of cell corners (16 bytes a cell)
+            # the largest map a plan brings, with its table of cell corners (16
+            # bytes a cell): a 128^3 grid for the arm, else a 500 x 500 grid
             m = max_map_bytes if max_map_bytes is not None else (
-                128 ** 3 * 4 if n == 14 else 500 * 500 * 4 + 499 * 499 * 16)
+                128 ** 3 * 4 + 127 * 127 * 128 * 16 if n == 14 else 500 * 500 * 4 + 499 * 499 * 16)
             per_state = (pgvimp_arena_bytes(n, 1, 1001, 0, trial_width, trial_slots)
                          - pgvimp_arena_bytes(n, 1, 1, 0, trial_width, trial_slots)) / 1000.0
             plans = 1 if serial else max_concurrent
