@@ -69,15 +69,39 @@ __device__ __forceinline__ void dm_zero(DM<n>& X) {
     for (int t = 0; t < Coop<n>::EPL; ++t) X.v[t] = 0.0;
 }
 
-// Block at byte offset off of a tiled chain-order array (entry e = r n + c);
-// zero outside the n x n block.
+// Entry of lane entry t inside the n x n block: padding entries are clamped
+// to a real one, so every lane loads (no branch around the loads: those of
+// the next state stay in flight behind the current one's arithmetic) and
+// padding lanes discard what they read.
+template <int n>
+__device__ __forceinline__ int dm_e(const Lane<n>& L, int t) {
+    const int r = L.row(t) < n ? L.row(t) : n - 1, c = L.col < n ? L.col : n - 1;
+    return r * n + c;
+}
+template <int n>
+__device__ __forceinline__ bool dm_in(const Lane<n>& L, int t) {
+    return L.row(t) < n && L.col < n;
+}
+
+// Block at byte offset off of a tiled chain-order array (entry e = r n + c)
+// as loaded: padding entries hold whatever real entry they were clamped to
+// (dm_mask zeroes them where the block is used, so a load for the next
+// state is not waited for until then).
+template <int n>
+__device__ __forceinline__ void dm_ld_raw(const double* base, uint32_t off, const Lane<n>& L, DM<n>& X) {
+#pragma unroll
+    for (int t = 0; t < Coop<n>::EPL; ++t) X.v[t] = ldo(base, off, dm_e<n>(L, t));
+}
+template <int n>
+__device__ __forceinline__ void dm_mask(const Lane<n>& L, DM<n>& X) {
+#pragma unroll
+    for (int t = 0; t < Coop<n>::EPL; ++t) X.v[t] = dm_in<n>(L, t) ? X.v[t] : 0.0;
+}
+// The block, zero outside n x n.
 template <int n>
 __device__ __forceinline__ void dm_ld(const double* base, uint32_t off, const Lane<n>& L, DM<n>& X) {
-#pragma unroll
-    for (int t = 0; t < Coop<n>::EPL; ++t) {
-        const int r = L.row(t), c = L.col;
-        X.v[t] = (r < n && c < n) ? ldo(base, off, r * n + c) : 0.0;
-    }
+    dm_ld_raw<n>(base, off, L, X);
+    dm_mask<n>(L, X);
 }
 template <int n>
 __device__ __forceinline__ void dm_st(double* base, uint32_t off, const Lane<n>& L, const DM<n>& X) {
@@ -87,28 +111,44 @@ __device__ __forceinline__ void dm_st(double* base, uint32_t off, const Lane<n>&
         if (r < n && c < n) sto(base, off, r * n + c, X.v[t]);
     }
 }
-// a0 X0 + a1 X1 of two blocks of a source (the same expression as lin2)
+// The two blocks of a source, as loaded (combined by dm_lin2).
 template <int n>
-__device__ __forceinline__ void dm_src(const double* X0, const double* X1, double a0, double a1, uint32_t off,
-                                       const Lane<n>& L, DM<n>& X) {
-#pragma unroll
-    for (int t = 0; t < Coop<n>::EPL; ++t) {
-        const int r = L.row(t), c = L.col;
-        const bool in = r < n && c < n;
-        const double x0 = in ? ldo(X0, off, r * n + c) : 0.0;
-        const double x1 = in ? ldo(X1, off, r * n + c) : 0.0;
-        X.v[t] = in ? lin2(a0, x0, a1, x1) : 0.0;
-    }
+struct DM2 {
+    DM<n> x0, x1;
+};
+template <int n>
+__device__ __forceinline__ void dm_ld2(const double* X0, const double* X1, uint32_t off, const Lane<n>& L,
+                                       DM2<n>& R) {
+    dm_ld_raw<n>(X0, off, L, R.x0);
+    dm_ld_raw<n>(X1, off, L, R.x1);
 }
-// Vector entries r < n of a tiled array with E entries per position, held
-// by the lanes of column `col` (the others get 0).
+// a0 X0 + a1 X1 (the same expression as lin2), zero outside the block
+template <int n>
+__device__ __forceinline__ void dm_lin2(double a0, double a1, const DM2<n>& R, const Lane<n>& L, DM<n>& X) {
+#pragma unroll
+    for (int t = 0; t < Coop<n>::EPL; ++t) X.v[t] = dm_in<n>(L, t) ? lin2(a0, R.x0.v[t], a1, R.x1.v[t]) : 0.0;
+}
+// Vector entries r < n of a tiled array with E entries per position, as
+// loaded by every lane (lane entry t reads entry min(row, n - 1)); dm_mask_col
+// keeps them in the lanes of column `col` only.
 template <int n, int E>
-__device__ __forceinline__ void dm_ld_vec(const double* base, int64_t q, int col, const Lane<n>& L, DM<n>& X) {
+__device__ __forceinline__ void dm_ld_vec_raw(const double* base, int64_t q, const Lane<n>& L, DM<n>& X) {
 #pragma unroll
     for (int t = 0; t < Coop<n>::EPL; ++t) {
         const int r = L.row(t);
-        X.v[t] = (L.col == col && r < n) ? base[tidx<E>(q, r)] : 0.0;
+        X.v[t] = base[tidx<E>(q, r < n ? r : n - 1)];
     }
+}
+template <int n>
+__device__ __forceinline__ void dm_mask_col(int col, const Lane<n>& L, DM<n>& X) {
+#pragma unroll
+    for (int t = 0; t < Coop<n>::EPL; ++t) X.v[t] = (L.col == col && L.row(t) < n) ? X.v[t] : 0.0;
+}
+// The vector in the lanes of column `col` (the others get 0).
+template <int n, int E>
+__device__ __forceinline__ void dm_ld_vec(const double* base, int64_t q, int col, const Lane<n>& L, DM<n>& X) {
+    dm_ld_vec_raw<n, E>(base, q, L, X);
+    dm_mask_col<n>(col, L, X);
 }
 template <int n, int E>
 __device__ __forceinline__ void dm_st_vec(double* base, int64_t q, int col, const Lane<n>& L, const DM<n>& X) {
@@ -244,7 +284,11 @@ __device__ __forceinline__ bool coop_forward(const BlockSrc& M, int N, const Ws&
     DetAcc det;
     bool ok = true;
     DM<n> P, Y;
-    dm_src<n>(M.D0, M.D1, M.a0, M.a1, toff<NN>(0), L, P);
+    {
+        DM2<n> P0;
+        dm_ld2<n>(M.D0, M.D1, toff<NN>(0), L, P0);
+        dm_lin2<n>(M.a0, M.a1, P0, L, P);
+    }
     if (RHS) {
         DM<n> r0, r1;
         dm_ld_vec<n, n>(M.R0, 0, n, L, r0);
@@ -255,19 +299,18 @@ __device__ __forceinline__ bool coop_forward(const BlockSrc& M, int N, const Ws&
     for (int i = 0; i < N; ++i) {
         const uint32_t o = toff<NN>(i);
         const bool more = i + 1 < N;
-        // the next state's inputs, independent of the recurrence
-        DM<n> U, Dn, Rn;
-        dm_zero<n>(U);
-        if (more) {
-            dm_src<n>(M.U0, M.U1, M.a0, M.a1, o, L, U);
-            dm_src<n>(M.D0, M.D1, M.a0, M.a1, toff<NN>(i + 1), L, Dn);
-            if (RHS) {
-                DM<n> r0, r1;
-                dm_ld_vec<n, n>(M.R0, i + 1, n, L, r0);
-                dm_ld_vec<n, n>(M.R1, i + 1, n, L, r1);
-#pragma unroll
-                for (int t = 0; t < C::EPL; ++t) Rn.v[t] = lin2(M.a0, r0.v[t], M.a1, r1.v[t]);
-            }
+        // the next state's inputs, independent of the recurrence: loaded
+        // here and combined after the pivot inversion, so the loads are in
+        // flight meanwhile
+        // (past the last state they reread it, and are not used)
+        const int nx = more ? i + 1 : i;
+        DM2<n> Ur, Dr;
+        DM<n> r0n, r1n;
+        dm_ld2<n>(M.U0, M.U1, o, L, Ur);
+        dm_ld2<n>(M.D0, M.D1, toff<NN>(nx), L, Dr);
+        if (RHS) {
+            dm_ld_vec_raw<n, n>(M.R0, nx, L, r0n);
+            dm_ld_vec_raw<n, n>(M.R1, nx, L, r1n);
         }
         wsync();
         dm_put<n>(P, bA, L);
@@ -276,6 +319,9 @@ __device__ __forceinline__ bool coop_forward(const BlockSrc& M, int N, const Ws&
         if (!RHS) dm_st<n>(ws.P, o, L, Pinv);
         if (!more && !RHS) break;
         // G = P^-1 [U | y] (U = 0 after the last state), then S = U^T G
+        DM<n> U;
+        if (more) dm_lin2<n>(M.a0, M.a1, Ur, L, U);
+        else dm_zero<n>(U);
         wsync();
         dm_put<n>(Pinv, bA, L);
         dm_put<n>(U, bB, L);
@@ -289,13 +335,14 @@ __device__ __forceinline__ bool coop_forward(const BlockSrc& M, int N, const Ws&
         wsync();
         dm_put<n>(G, bX, L);
         wsync();
-        DM<n> S;
+        DM<n> S, Dn;
+        dm_lin2<n>(M.a0, M.a1, Dr, L, Dn);
         coop_mul<n, true, false>(bB, bX, nullptr, -1, L, S);
 #pragma unroll
         for (int t = 0; t < C::EPL; ++t) {
             const int r = L.row(t), c = L.col;
             P.v[t] = (r < n && c < n) ? Dn.v[t] - S.v[t] : 0.0;
-            if (RHS) Y.v[t] = (c == n && r < n) ? Rn.v[t] - S.v[t] : 0.0;
+            if (RHS) Y.v[t] = (c == n && r < n) ? lin2(M.a0, r0n.v[t], M.a1, r1n.v[t]) - S.v[t] : 0.0;
         }
     }
     *logdet += det.log_value();
@@ -322,14 +369,37 @@ __device__ __forceinline__ void coop_cov_backward(int N, const Ws& ws, double* S
 #pragma unroll
         for (int t = 0; t < C::EPL; ++t) *part = fma(K.v[t], Sg.v[t], *part);
     }
+    // the blocks of state i are loaded during state i + 1 (state 0 rereads
+    // its own, unused), masked where used
+    DM<n> G, Pinv, Kd, Ku;
+    dm_zero<n>(Kd);
+    dm_zero<n>(Ku);
+    {
+        const uint32_t o0 = toff<NN>(N >= 2 ? N - 2 : 0);
+        dm_ld_raw<n>(ws.G, o0, L, G);
+        dm_ld_raw<n>(ws.P, o0, L, Pinv);
+        if (KH) {
+            dm_ld_raw<n>(KH, o0, L, Kd);
+            dm_ld_raw<n>(KU, o0, L, Ku);
+        }
+    }
     for (int i = N - 2; i >= 0; --i) {
         const uint32_t o = toff<NN>(i);
-        DM<n> G, Pinv, Kd, Ku;
-        dm_ld<n>(ws.G, o, L, G);
-        dm_ld<n>(ws.P, o, L, Pinv);
-        if (KH) {
-            dm_ld<n>(KH, o, L, Kd);
-            dm_ld<n>(KU, o, L, Ku);
+        dm_mask<n>(L, G);
+        dm_mask<n>(L, Pinv);
+        dm_mask<n>(L, Kd);
+        dm_mask<n>(L, Ku);
+        DM<n> Gn, Pn, Kdn, Kun;
+        dm_zero<n>(Kdn);
+        dm_zero<n>(Kun);
+        {
+            const uint32_t on = toff<NN>(i > 0 ? i - 1 : 0);
+            dm_ld_raw<n>(ws.G, on, L, Gn);
+            dm_ld_raw<n>(ws.P, on, L, Pn);
+            if (KH) {
+                dm_ld_raw<n>(KH, on, L, Kdn);
+                dm_ld_raw<n>(KU, on, L, Kun);
+            }
         }
         // Sigma_{i,i+1} = -G Sigma_{i+1}
         wsync();
@@ -367,6 +437,10 @@ __device__ __forceinline__ void coop_cov_backward(int N, const Ws& ws, double* S
             }
             *part = fma(2.0, s, *part);
         }
+        G = Gn;
+        Pinv = Pn;
+        Kd = Kdn;
+        Ku = Kun;
     }
 }
 
@@ -391,16 +465,39 @@ __device__ __forceinline__ void coop_rhs_backward(const BlockSrc& M, int N, cons
 #pragma unroll
         for (int t = 0; t < C::EPL; ++t) d.v[t] = x.v[t] - m0.v[t];
     }
+    // the inputs of state i are loaded during state i + 1 (state 0 rereads
+    // its own, unused), masked where used
+    DM<n> G, w, m0, LDc, LUc;
+    dm_zero<n>(G);
+    dm_zero<n>(w);
+    dm_zero<n>(m0);
+    dm_zero<n>(LDc);
+    dm_zero<n>(LUc);
+    if (mu0) dm_ld_raw<n>(M.D1, toff<NN>(N - 1), L, LDc);
     for (int i = N - 1; i >= 0; --i) {
-        const uint32_t o = toff<NN>(i);
         const bool below = i + 1 < N;
+        dm_mask<n>(L, G);
+        dm_mask_col<n>(0, L, w);
+        dm_mask_col<n>(0, L, m0);
+        dm_mask<n>(L, LDc);
+        dm_mask<n>(L, LUc);
+        DM<n> Gn, wn, m0n, LDn, LUn;
+        dm_zero<n>(m0n);
+        dm_zero<n>(LDn);
+        dm_zero<n>(LUn);
+        {
+            const int iq = i > 0 ? i - 1 : 0;
+            const uint32_t on = toff<NN>(iq);
+            dm_ld_raw<n>(ws.G, on, L, Gn);
+            dm_ld_vec_raw<n, NN>(ws.H, iq, L, wn);
+            if (mu0) {
+                dm_ld_vec_raw<n, n>(mu0, iq, L, m0n);
+                dm_ld_raw<n>(M.D1, on, L, LDn);
+                dm_ld_raw<n>(M.U1, on, L, LUn);
+            }
+        }
         DM<n> xi = x, di = d;
         if (below) {
-            DM<n> G, w, m0;
-            dm_zero<n>(m0);
-            dm_ld<n>(ws.G, o, L, G);
-            dm_ld_vec<n, NN>(ws.H, i, 0, L, w);
-            if (mu0) dm_ld_vec<n, n>(mu0, i, 0, L, m0);
             wsync();
             dm_put<n>(G, bA, L);
             dm_put_col<n>(x, 0, bV, L);
@@ -425,8 +522,8 @@ __device__ __forceinline__ void coop_rhs_backward(const BlockSrc& M, int N, cons
             for (int t = 0; t < C::EPL; ++t) {
                 const int r = L.row(t), c = L.col;
                 if (r < n && c < n) {
-                    const double ld = ldo(M.D1, o, r * n + c);
-                    const double lu = below ? ldo(M.U1, o, r * n + c) : 0.0;
+                    const double ld = LDc.v[t];
+                    const double lu = below ? LUc.v[t] : 0.0;
                     const double dn = below ? bD[c] : 0.0;
                     s = fma(bV[r], fma(ld, bV[c], 2.0 * lu * dn), s);
                 }
@@ -435,6 +532,11 @@ __device__ __forceinline__ void coop_rhs_backward(const BlockSrc& M, int N, cons
         }
         x = xi;
         d = di;
+        G = Gn;
+        w = wn;
+        m0 = m0n;
+        LDc = LDn;
+        LUc = LUn;
     }
 }
 
