@@ -179,10 +179,13 @@ typedef struct pgvimp_problem {
  * in windows: each window of a plan continues where its previous one ended,
  * until one holds a passing step.  A window's width is the number of
  * compute units divided by the number of plans still searching, clamped to
- * [trial_width, trial_slots]: trial_width (0 = 8, at most 64) is the
- * narrowest window, trial_slots (0 = 2 * trial_width, at least
- * trial_width, at most 64) the widest, and the trial scratch scales with
- * trial_slots.  trial_lookahead > 0 cuts each plan's first window of an
+ * [trial_width, trial_slots]: trial_width (0 = 8 for n <= 4, 24 for
+ * n >= 6, at most 64) is the narrowest window, trial_slots (0 = 2 *
+ * trial_width for n <= 4, trial_width for n >= 6; at least trial_width, at
+ * most 64) the widest, and the trial scratch scales with trial_slots.  (For
+ * n >= 6 one trial is a long chain of small latency-bound block steps, so
+ * several trials per compute unit in one wide window beat narrow windows
+ * run one after another.)  trial_lookahead > 0 cuts each plan's first window of an
  * iteration to t + trial_lookahead step sizes (at least 1), t = the number
  * its previous iteration tried; 0 = no cut.  All three change speed and
  * memory, never results: the accepted step is the first passing one in

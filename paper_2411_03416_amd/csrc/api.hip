@@ -19,6 +19,7 @@ namespace {
 
 constexpr int64_t kAlign = 256;
 constexpr int kDefaultTrialWidth = 8;
+constexpr int kDefaultTrialWidthLarge = 24;  // n >= 6
 constexpr int kMaxTrialWidth = 64;
 constexpr int kMaxSparseNodes = 65536;  // nodes of a sparse quadrature rule
 
@@ -453,15 +454,19 @@ int64_t pgvimp_device_bytes(const pgvimp_ctx* ctx) { return ctx ? (int64_t)ctx->
 
 static int64_t layout_bytes(const pgvimp_engine_cfg* cfg);
 
-// Narrowest window of trial step sizes per plan (1..kMaxTrialWidth).
+// Narrowest window of trial step sizes per plan (1..kMaxTrialWidth).  For
+// n >= 6 a trial is a long chain of latency-bound block steps, so the
+// default evaluates more step sizes at once (several trials share a compute
+// unit) rather than in windows one after another.
 static int64_t trial_width(const pgvimp_engine_cfg* cfg) {
-    return cfg->trial_width > 0 ? std::min<int64_t>(cfg->trial_width, kMaxTrialWidth) : kDefaultTrialWidth;
+    if (cfg->trial_width > 0) return std::min<int64_t>(cfg->trial_width, kMaxTrialWidth);
+    return cfg->n >= 6 ? kDefaultTrialWidthLarge : kDefaultTrialWidth;
 }
 // Trial slots per plan = the widest window (trial_width..kMaxTrialWidth,
-// default twice trial_width).
+// default twice trial_width, or trial_width for n >= 6).
 static int64_t trial_slots(const pgvimp_engine_cfg* cfg) {
     const int64_t w = trial_width(cfg);
-    const int64_t s = cfg->trial_slots > 0 ? cfg->trial_slots : 2 * w;
+    const int64_t s = cfg->trial_slots > 0 ? cfg->trial_slots : (cfg->n >= 6 ? w : 2 * w);
     return std::min<int64_t>(kMaxTrialWidth, std::max(w, s));
 }
 
