@@ -1320,76 +1320,49 @@ __global__ void __launch_bounds__(Coop<n>::value ? Coop<n>::THREADS : kTrialThre
 // Sum over the block in a fixed order (sh holds blockDim.x + 1 doubles).
 __device__ __forceinline__ double block_sum(double v, double* sh) { return wg_sum(v, sh); }
 
-// prep_kernel's per-state right-hand side for n >= 6: rb = eta - g (+ H mu_k
-// for the natural-gradient step), mu_k and Lambda_k mu_k to chain position
-// q, vectors in registers and blocks read straight from memory.
+// Row e of state i's right-hand side eta - g (eta - g + H mu_k for the
+// natural-gradient step), of mu_k and of Lambda_k mu_k = D_i mu_i + U_i
+// mu_{i+1} + U_{i-1}^T mu_{i-1}, the blocks read straight from memory (for
+// n >= 6, one thread per (state, row)).
 template <int n>
-__device__ __forceinline__ void prep_rhs_direct(const DevState& st, const PlanDev& p, int i, int64_t s, int64_t q,
-                                                bool act) {
+__device__ __forceinline__ void prep_rhs_row(const DevState& st, const PlanDev& p, int i, int e, int64_t s,
+                                             int64_t q, bool act) {
     const int64_t S = st.S;
     const int N = p.N, d = p.d;
-    double r[n], m[n], acc[n];
-#pragma unroll
-    for (int e = 0; e < n; ++e) {
-        r[e] = st.eta[e * S + s];
-        m[e] = st.mu[e * S + s];
-    }
+    double r = st.eta[e * S + s];
     if (act) {
         for (int a = 0; a < d; ++a) {
             const double ga = st.gcol[a * S + s];
             const int ca = p.coll_index[a];
             double h = 0.0;
             if (p.update == PGVIMP_UPDATE_NGD) {
-                for (int b = 0; b < d; ++b) {
-                    const int cb = p.coll_index[b];
-                    double mb = 0.0;
-#pragma unroll
-                    for (int e = 0; e < n; ++e) mb = e == cb ? m[e] : mb;
-                    h = fma(st.Hcol[(a * d + b) * S + s], mb, h);
-                }
+                for (int b = 0; b < d; ++b)
+                    h = fma(st.Hcol[(a * d + b) * S + s], st.mu[(int64_t)p.coll_index[b] * S + s], h);
             }
-#pragma unroll
-            for (int e = 0; e < n; ++e) r[e] += e == ca ? h - ga : 0.0;
+            r += e == ca ? h - ga : 0.0;
         }
     }
-    // Lambda_k mu_k = D_i mu_i + U_i mu_{i+1} + U_{i-1}^T mu_{i-1}
+    double m[n];
 #pragma unroll
-    for (int e = 0; e < n; ++e) {
+    for (int c = 0; c < n; ++c) m[c] = st.mu[c * S + s];
+    double acc = 0.0;
+#pragma unroll
+    for (int c = 0; c < n; ++c) acc = fma(st.LD[(e * n + c) * S + s], m[c], acc);
+    if (i < N - 1) {
         double t = 0.0;
 #pragma unroll
-        for (int c = 0; c < n; ++c) t = fma(st.LD[(e * n + c) * S + s], m[c], t);
-        acc[e] = t;
-    }
-    if (i < N - 1) {
-        double mn[n];
-#pragma unroll
-        for (int c = 0; c < n; ++c) mn[c] = st.mu[c * S + s + 1];
-#pragma unroll
-        for (int e = 0; e < n; ++e) {
-            double t = 0.0;
-#pragma unroll
-            for (int c = 0; c < n; ++c) t = fma(st.LU[(e * n + c) * S + s], mn[c], t);
-            acc[e] += t;
-        }
+        for (int c = 0; c < n; ++c) t = fma(st.LU[(e * n + c) * S + s], st.mu[c * S + s + 1], t);
+        acc += t;
     }
     if (i > 0) {
-        double mp[n];
+        double t = 0.0;
 #pragma unroll
-        for (int c = 0; c < n; ++c) mp[c] = st.mu[c * S + s - 1];
-#pragma unroll
-        for (int e = 0; e < n; ++e) {
-            double t = 0.0;
-#pragma unroll
-            for (int c = 0; c < n; ++c) t = fma(st.LU[(c * n + e) * S + s - 1], mp[c], t);
-            acc[e] += t;
-        }
+        for (int c = 0; c < n; ++c) t = fma(st.LU[(c * n + e) * S + s - 1], st.mu[c * S + s - 1], t);
+        acc += t;
     }
-#pragma unroll
-    for (int e = 0; e < n; ++e) {
-        st.crb[tidx<n>(q, e)] = r[e];
-        st.cmu[tidx<n>(q, e)] = m[e];
-        st.cLmu[tidx<n>(q, e)] = acc[e];
-    }
+    st.crb[tidx<n>(q, e)] = r;
+    st.cmu[tidx<n>(q, e)] = m[e];
+    st.cLmu[tidx<n>(q, e)] = acc;
 }
 
 // One proximal iteration (Alg. 1), part 1: per-state quantities shared by all
@@ -1415,18 +1388,24 @@ __global__ void __launch_bounds__(kIterThreads) prep_kernel(DevState st) {
     const int64_t off = p.off, S = st.S, coff = p.coff;
     TS ts = thread_ws<n>(st, pid, y);
     double ecol = 0.0, epri = 0.0;
-    for (int i = y * kIterThreads + tid; i < N; i += nb * kIterThreads) {
-        TS lt = ts;
+    // Each group's loads come before its stores (the stores go to other
+    // arrays, but the compiler cannot know that): Lambda_k's blocks and the
+    // collision blocks of K^-1 + H, then the right-hand side eta - g and
+    // Lambda_k mu_k, then the prior costs.  K^-1 itself and K^-1 + H outside
+    // the collision blocks are written by the set-up chain kernel after every
+    // prior build (K^-1 does not change between builds).  For n >= 6 the
+    // copies are spread over (state, chunk of entries) and the right-hand
+    // sides over (state, row), states fastest, so a state's many loads are
+    // not one thread's chain of waits.
+    constexpr int CPS = Coop<n>::value ? (NN + kCopyChunk<NN> - 1) / kCopyChunk<NN> : 1;
+    for (int w = y * kIterThreads + tid; w < N * CPS; w += nb * kIterThreads) {
+        const int i = w % N;
         const int64_t s = off + i, q = coff + chain_pos(N, nseg, i);
         const bool act = coll_active<n>(p, i);
         const bool notlast = i < N - 1;
-        // Each group's loads come before its stores (the stores go to other
-        // arrays, but the compiler cannot know that): Lambda_k's blocks and
-        // the collision blocks of K^-1 + H, then the right-hand side eta - g
-        // and Lambda_k mu_k, then the prior costs.  K^-1 itself and K^-1 + H
-        // outside the collision blocks are written by the set-up chain kernel
-        // after every prior build (K^-1 does not change between builds).
-        for (int e0 = 0; e0 < NN; e0 += kCopyChunk<NN>) {
+        const int c_lo = Coop<n>::value ? (w / N) * kCopyChunk<NN> : 0;
+        const int c_hi = Coop<n>::value ? c_lo + kCopyChunk<NN> : NN;
+        for (int e0 = c_lo; e0 < c_hi && e0 < NN; e0 += kCopyChunk<NN>) {
             constexpr int CH = kCopyChunk<NN>;
             double kh[CH], ld[CH], lu[CH];
             bool ce[CH];
@@ -1451,12 +1430,8 @@ __global__ void __launch_bounds__(kIterThreads) prep_kernel(DevState st) {
                 st.cLU[qe] = lu[k];
             }
         }
-        if constexpr (Coop<n>::value) {
-            // n >= 6: the right-hand side and Lambda_k mu_k in registers,
-            // the blocks read straight from memory
-            prep_rhs_direct<n>(st, p, i, s, q, act);
-            continue;
-        }
+        if constexpr (Coop<n>::value) continue;
+        TS lt = ts;
         PG_VEC(r, lt);
         ld_vec<n>(st.eta, S, s, r);
         if (act) {
@@ -1524,7 +1499,12 @@ PG_UNROLL
         epri += prior_cost_state<n>(st, p, i, nullptr, nullptr, nullptr, lt);
     }
     if constexpr (Coop<n>::value) {
-        // n >= 6: collision costs per thread, prior costs one wavefront per state
+        // n >= 6: right-hand sides per (state, row), collision costs per
+        // thread, prior costs one wavefront per state
+        for (int w = y * kIterThreads + tid; w < N * n; w += nb * kIterThreads) {
+            const int i = w % N;
+            prep_rhs_row<n>(st, p, i, w / N, off + i, coff + chain_pos(N, nseg, i), coll_active<n>(p, i));
+        }
         for (int i = y * kIterThreads + tid; i < N; i += nb * kIterThreads)
             if (coll_active<n>(p, i)) ecol += st.Ecol[off + i];
         __shared__ double p_lds[(kIterThreads / 64) * Coop<n>::WAVE_LDS];
