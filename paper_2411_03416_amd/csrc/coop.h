@@ -215,53 +215,76 @@ __device__ __forceinline__ void coop_mul(const double* A, const double* B, const
 // identity, each round one short update (measured faster there).
 template <int n>
 __device__ __forceinline__ bool coop_spd_inverse(double* A, double* X, const Lane<n>& L, DM<n>& Ainv, DetAcc* det) {
-    constexpr int LS = Coop<n>::LS;
-    constexpr bool MERGED = Coop<n>::NP == 8;
+    using C = Coop<n>;
+    constexpr int LS = C::LS;
+    constexpr bool MERGED = C::NP == 8;
     const int c = L.col;
     bool ok = true;
     wsync();
+    // Every round reads all it needs first and then writes every entry of
+    // the lane back (unchanged where the round does not touch it): one LDS
+    // round trip per round, and no branch around a load.  A lane's entries
+    // are written by that lane only, and all reads of a round precede its
+    // writes, so the reads see the previous round's values.
     for (int k = 0; k < n; ++k) {
         const double d = A[k * LS + k];
+        const double ack = A[(c < n ? c : 0) * LS + k];
+        double ark[C::EPL], arc[C::EPL], dot[C::EPL];
+#pragma unroll
+        for (int t = 0; t < C::EPL; ++t) {
+            const int r = L.row(t);
+            ark[t] = A[r * LS + k];
+            arc[t] = A[r * LS + c];
+            dot[t] = 0.0;
+            if (MERGED) {
+                // row r of X from the final rows above it (used for r = k)
+                for (int j = 0; j < k; ++j) dot[t] = fma(A[r * LS + j], X[j * LS + c], dot[t]);
+            }
+        }
         const bool good = d >= 2.2250738585072014e-308 && d < INFINITY;
         ok = ok && good;
         if (det) det->mul(good ? d : 1.0);
         const double rs = good ? rsqrt_nr(d) : 0.0;
-        const double lck = (c > k && c < n) ? A[c * LS + k] * rs : 0.0;  // L[c][k]
+        const double lck = (c > k && c < n) ? ack * rs : 0.0;  // L[c][k]
 #pragma unroll
-        for (int t = 0; t < Coop<n>::EPL; ++t) {
+        for (int t = 0; t < C::EPL; ++t) {
             const int r = L.row(t);
-            if (MERGED && r == k) {
-                // row k of X from the final rows above it
-                double dot = 0.0;
-                for (int j = 0; j < k; ++j) dot = fma(A[k * LS + j], X[j * LS + c], dot);
-                X[k * LS + c] = ((c == k ? 1.0 : 0.0) - dot) * rs;
-            }
+            if (MERGED && r == k) X[k * LS + c] = ((c == k ? 1.0 : 0.0) - dot[t]) * rs;
+            const double lrk = ark[t] * rs;  // L[r][k]
+            double v = arc[t];
             if (r < n && r >= k) {
-                const double lrk = A[r * LS + k] * rs;  // L[r][k]
-                if (c == k) A[r * LS + k] = r == k ? rs : lrk;
-                else if (c > k && c <= r) A[r * LS + c] = fma(-lrk, lck, A[r * LS + c]);
+                if (c == k) v = r == k ? rs : lrk;
+                else if (c > k && c <= r) v = fma(-lrk, lck, arc[t]);
             }
+            A[r * LS + c] = v;
         }
         wsync();
     }
     if (!MERGED) {
         // X = L^-1: row k of X is finished at step k, then removed from the rows below
 #pragma unroll
-        for (int t = 0; t < Coop<n>::EPL; ++t) X[L.row(t) * LS + c] = (L.row(t) == c && c < n) ? 1.0 : 0.0;
+        for (int t = 0; t < C::EPL; ++t) X[L.row(t) * LS + c] = (L.row(t) == c && c < n) ? 1.0 : 0.0;
         wsync();
         for (int k = 0; k < n; ++k) {
             const double xk = X[k * LS + c] * A[k * LS + k];
+            double ark[C::EPL], xrc[C::EPL];
 #pragma unroll
-            for (int t = 0; t < Coop<n>::EPL; ++t) {
+            for (int t = 0; t < C::EPL; ++t) {
                 const int r = L.row(t);
-                if (r == k) X[k * LS + c] = xk;
-                else if (r > k && r < n) X[r * LS + c] = fma(-A[r * LS + k], xk, X[r * LS + c]);
+                ark[t] = A[r * LS + k];
+                xrc[t] = X[r * LS + c];
+            }
+#pragma unroll
+            for (int t = 0; t < C::EPL; ++t) {
+                const int r = L.row(t);
+                const double v = r == k ? xk : (r > k && r < n) ? fma(-ark[t], xk, xrc[t]) : xrc[t];
+                X[r * LS + c] = v;
             }
             wsync();
         }
     }
 #pragma unroll
-    for (int t = 0; t < Coop<n>::EPL; ++t) {
+    for (int t = 0; t < C::EPL; ++t) {
         const int r = L.row(t);
         double s = 0.0;
         for (int k = 0; k < n; ++k) s = fma(X[k * LS + r], X[k * LS + c], s);
