@@ -169,8 +169,9 @@ typedef struct pgvimp_problem {
  * the context); otherwise it allocates its own.  segments overrides the
  * tuned chain segments (0 = tuned default); expect_group fixes the factors
  * per workgroup of the expectation kernel (32, 64, 128 or 256; 0 = the
- * largest that gives every compute unit four workgroups; the arm always
- * uses 32; speed only, never results);
+ * largest that gives every compute unit four workgroups; the arm uses 32,
+ * or with 0 also 8 when 32 would give fewer than two workgroups per compute
+ * unit; speed only, never results);
  * use_graph = 1 captures pgvimp_prox_step's iterations in a HIP graph sized
  * to the plans present (re-captured when they change); use_graph = 2 sizes
  * the graph to the full capacity so plans can join and leave without a new

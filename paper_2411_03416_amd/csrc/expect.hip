@@ -793,7 +793,17 @@ static hipError_t dispatch(const DevState& st, int kind, int d, int p, int f, in
         }
     }
     if (kind == PGVIMP_COLL_ARM3D && d == PGVIMP_ARM_DOF) {
-        // the arm's nodes are costly and many: 32 factors per workgroup
+        // the arm's nodes are costly and many: 32 factors per workgroup, or
+        // 8 (f < 32, see launch_expect) when 32 would leave most compute
+        // units idle
+        if (f < 32) {
+            switch (p) {
+                case 0: return launch_one<R, PGVIMP_ARM_DOF, 0, PGVIMP_COLL_ARM3D, 8>(st, plo, phi, maxN, respect, s);
+                case 2: return launch_one<R, PGVIMP_ARM_DOF, 2, PGVIMP_COLL_ARM3D, 8>(st, plo, phi, maxN, respect, s);
+                case 3: return launch_one<R, PGVIMP_ARM_DOF, 3, PGVIMP_COLL_ARM3D, 8>(st, plo, phi, maxN, respect, s);
+                default: return hipErrorInvalidValue;
+            }
+        }
         switch (p) {
             case 0: return launch_one<R, PGVIMP_ARM_DOF, 0, PGVIMP_COLL_ARM3D, 32>(st, plo, phi, maxN, respect, s);
             case 2: return launch_one<R, PGVIMP_ARM_DOF, 2, PGVIMP_COLL_ARM3D, 32>(st, plo, phi, maxN, respect, s);
@@ -828,7 +838,14 @@ bool expect_supported(int kind, int d, int p, int group, int quadrature) {
 hipError_t launch_expect(const DevState& st, int kind, int d, int p, int quadrature, int precision, int group, int plo,
                          int phi, int maxN, int respect, hipStream_t s) {
     if (kind == PGVIMP_COLL_NONE) return hipSuccess;
-    const int f = pick_group(group, phi - plo, maxN, st.wbudget);
+    int f = pick_group(group, phi - plo, maxN, st.wbudget);
+    if (kind == PGVIMP_COLL_ARM3D) {
+        // the arm: 32 factors per workgroup, or 8 when the batch gives fewer
+        // than two workgroups of 32 per compute unit (f = 8 then)
+        const int64_t slots = (phi - plo + kNumXcd - 1) / kNumXcd;
+        const bool small = group == 0 && slots * kNumXcd * ((maxN + 31) / 32) < 2 * (int64_t)st.wbudget;
+        f = small ? 8 : 32;
+    }
     const int shape = quadrature == PGVIMP_QUAD_SPARSE ? 0 : p;
     if (precision == PGVIMP_MIXED) return dispatch<float>(st, kind, d, shape, f, plo, phi, maxN, respect, s);
     return dispatch<double>(st, kind, d, shape, f, plo, phi, maxN, respect, s);

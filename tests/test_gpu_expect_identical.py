@@ -168,6 +168,24 @@ def test_workgroup_shapes_give_the_same_bits(pg, kind, p_gh, precision):
         assert all(np.array_equal(u, v) for u, v in zip(outs[0], o))
 
 
+@pytest.mark.parametrize("p_gh,quad", [(2, "tensor"), (3, "tensor"), (3, "sparse")])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_arm_workgroup_shapes_give_the_same_bits(pg, p_gh, quad, precision):
+    """The arm's launch takes 8 factors per workgroup for small batches (the
+    default) and 32 otherwise; both shapes must give bitwise identical
+    results (several chunks of nodes per factor for the 3^7 rule)."""
+    p = workloads.arm_problem(1, N=40, gh_points=p_gh)
+    p["quadrature"] = quad
+    print(f"arm shapes p={p_gh} {quad} precision={precision}", flush=True)
+    outs = []
+    for group in (0, 32):
+        ctx = pg.pgvimp_create([p], precision=precision, use_graph=False, expect_group=group)
+        outs.append(pg.pgvimp_factor_expectations(ctx, 0))
+        pg.pgvimp_destroy(ctx)
+    assert np.abs(outs[0][0]).max() > 0
+    assert all(np.array_equal(u, v) for u, v in zip(outs[0], outs[1]))
+
+
 def _sparse_factor_errors(p, mu, S, E, g, H, mixed):
     """_factor_errors for a sparse rule, whose weights can be negative: the
     sums are bounded by the rule with |W|, so E_ref becomes
