@@ -282,6 +282,37 @@ def counter_traffic(kernel):
         return None
 
 
+def expect_plateau():
+    """The expectation kernel at its batch plateau, from the committed counter
+    summary (profiles/expect_kernel_batch_counters.txt, 8192 plans x 750
+    factors): the busy fraction of the unit that binds it (the texture data
+    unit returning the grid gathers) beside HBM and VALU issue; None when the
+    summary is missing or was taken on other kernel sources."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "expect_kernel_batch_counters.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCE["expect_kernel"]:
+        h.update(open(os.path.join(ROOT, "paper_2411_03416_amd", "csrc", name), "rb").read())
+    if kv.get("source_sha256") != h.hexdigest():
+        return None
+    try:
+        return {"kernel": "expect_lane_kernel<float,2,5,point2d>", "factors_per_launch": 6144000,
+                "factors_per_s": float(kv["factors_per_s"]), "bound": "gather data path (texture data unit)",
+                "frac": float(kv["td_busy_frac"]), "addresser_busy_frac": float(kv["ta_busy_frac"]),
+                "hbm_frac": float(kv["hbm_GBs"]) * 1e9 / (HBM_PEAK_GBS * 1e9),
+                "valu_issue_frac": float(kv["valu_issue_frac"]),
+                "source": "profiles/expect_kernel_batch_counters.txt"}
+    except (KeyError, ValueError):
+        return None
+
+
 def pct(xs, q):
     xs = sorted(xs)
     k = min(len(xs) - 1, max(0, int(math.ceil(q / 100.0 * len(xs))) - 1))
@@ -595,7 +626,8 @@ def main():
         rexp = {"kernel": "expect_kernel<float,2,5,point2d>", "bound": "hbm", "achieved": exp_gbs,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": exp_gbs / HBM_PEAK_GBS,
                 "traffic": counter_traffic("expect_kernel"), "avg_ms": exp_ms, "bytes_per_launch": exp_bytes,
-                "note": "24k factors per launch: latency-bound; the batch sweep (--expect-sweep) gives the plateau"}
+                "note": "24k factors per launch: latency-bound; the batch sweep (--expect-sweep) gives the plateau",
+                "plateau": expect_plateau()}
         dominant = max(totals, key=totals.get)
         out["roofline"] = rtrial if dominant == "trial" else rexp
         out["roofline_expect"] = rexp
