@@ -189,28 +189,31 @@ class ServingEngine:
     (at least one plan of max_N states).  max_concurrent: live plans in all
     contexts together."""
 
-    def __init__(self, precision=FP64, hbm_budget=16 << 30, max_concurrent=256, chunk=2, trial_width=8,
-                 trial_slots=8, dims=(4, 6, 14), max_N=1000, use_graph=2, serial=False, max_map_bytes=None):
+    def __init__(self, precision=FP64, hbm_budget=16 << 30, max_concurrent=256, chunk=2, trial_width=None,
+                 trial_slots=None, dims=(4, 6, 14), max_N=1000, use_graph=2, serial=False, max_map_bytes=None):
         self.precision = precision
         self.serial = serial
         self.adm = Admission(hbm_budget, 1 if serial else max_concurrent)
         self.lanes = {}
         for n in dims:
+            # trial windows (None: 8 step sizes for n <= 4; 24 for n >= 6, whose
+            # trials are long latency-bound chains, so one wide window beats
+            # several narrow ones in a row)
+            tw = trial_width if trial_width is not None else (8 if n <= 4 else 24)
+            ts = trial_slots if trial_slots is not None else tw
             # arena: states and heap for the budget's worth of this lane's plans
             # the largest map a plan brings, with its table of cell corners (16
             # bytes a cell): a 128^3 grid for the arm, else a 500 x 500 grid
             m = max_map_bytes if max_map_bytes is not None else (
                 128 ** 3 * 4 + 127 * 127 * 128 * 16 if n == 14 else 500 * 500 * 4 + 499 * 499 * 16)
-            per_state = (pgvimp_arena_bytes(n, 1, 1001, 0, trial_width, trial_slots)
-                         - pgvimp_arena_bytes(n, 1, 1, 0, trial_width, trial_slots)) / 1000.0
+            per_state = (pgvimp_arena_bytes(n, 1, 1001, 0, tw, ts) - pgvimp_arena_bytes(n, 1, 1, 0, tw, ts)) / 1000.0
             plans = 1 if serial else max_concurrent
             states = int(min(plans * max_N, max(max_N, hbm_budget / per_state)))
             # heap per plan: its map and FP64 model (per interval A, a, B,
             # plus fixed blocks), with slack for alignment
             one = m + 8 * (max_N * (n * n + n + n * (n // 2)) + 8 * n * n) + (64 << 10)
             heap = int(min(plans * one, max(one, hbm_budget)))
-            self.lanes[n] = _Lane(n, precision, plans, states, heap, chunk, trial_width, trial_slots, use_graph,
-                                  self.adm)
+            self.lanes[n] = _Lane(n, precision, plans, states, heap, chunk, tw, ts, use_graph, self.adm)
 
     def run(self, requests, timeout_s=600.0, measured_from=0):
         """requests: list of (arrival_s, problem).  Metrics cover the
