@@ -434,21 +434,20 @@ __device__ __forceinline__ void coop_cov_backward(int N, const Ws& ws, double* S
 #pragma unroll
         for (int t = 0; t < C::EPL; ++t) So.v[t] = -So.v[t];
         dm_st<n>(SUo, o, L, So);
-        // Sigma_i = P^-1 - Sigma_{i,i+1} G^T, its lower triangle mirrored
+        // Sigma_i = P^-1 - Sigma_{i,i+1} G^T, bitwise symmetric: a lane above
+        // the diagonal forms the mirrored entry (T[c][r], the same operands
+        // in the same order as the lane below; P^-1 is bitwise symmetric), so
+        // no second exchange is needed
         wsync();
         dm_put<n>(So, bX, L);
-        wsync();
-        DM<n> T;
-        coop_mul<n, false, true>(bX, bA, nullptr, -1, L, T);
-#pragma unroll
-        for (int t = 0; t < C::EPL; ++t) Sg.v[t] = Pinv.v[t] - T.v[t];
-        wsync();
-        dm_put<n>(Sg, bB, L);
         wsync();
 #pragma unroll
         for (int t = 0; t < C::EPL; ++t) {
             const int r = L.row(t), c = L.col;
-            if (r < c) Sg.v[t] = bB[c * C::LS + r];
+            const int a = r >= c ? r : c, b = r >= c ? c : r;
+            double tv = 0.0;
+            for (int k = 0; k < n; ++k) tv = fma(bX[a * C::LS + k], bA[b * C::LS + k], tv);
+            Sg.v[t] = Pinv.v[t] - tv;
         }
         dm_st<n>(SDo, o, L, Sg);
         if (KH) {
