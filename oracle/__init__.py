@@ -19,8 +19,9 @@ Modules and the passages they follow:
   slr        Sec. 6.2 eqs. SLR_objective, SLR_best_ai, SLR_best_Ai, Alg. 2
 
 Parity status: every function is pinned by the -m "not gpu" tests against
-closed forms, invariants or brute force, except the hinge-cost expectation
-itself at a finite number of points, which is "parity unpinned" against the
+closed forms, invariants, brute force or (the hinge-cost expectation at a
+converged rule, p = 30) Monte Carlo, except the hinge-cost expectation at
+the small rules the workloads use, which is "parity unpinned" against the
 exact integral (Gauss-Hermite is an approximation for the non-smooth hinge);
 only the GPU-vs-oracle agreement at the same rule is checked there.
 """
